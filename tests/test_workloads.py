@@ -1,0 +1,46 @@
+"""Input generators: determinism, sizes, and the SplitMix64 definition."""
+
+import workloads
+from workloads import SplitMix64
+from workloads.formulas import cnf_clause_count, random_dag_batch
+
+
+def test_splitmix64_seed0():
+    # first output of SplitMix64 from state 0 (published generator)
+    assert SplitMix64(0).next() == 0xE220A8397B1DCDAF
+
+
+def test_deterministic():
+    assert workloads.random_3cnf(32, 136, 7) == workloads.random_3cnf(32, 136, 7)
+    assert workloads.random_3cnf(32, 136, 7) != workloads.random_3cnf(32, 136, 8)
+    assert workloads.random_dag(20, 300, 1) == workloads.random_dag(20, 300, 1)
+
+
+def test_clause_counts():
+    def lines(t):
+        return len(t.strip().split("\n"))
+    assert lines(workloads.equivalence_relations(6)[0]) == 60
+    assert lines(workloads.equivalence_relations(6, deduplicate=False)[0]) == 120
+    assert lines(workloads.equivalence_relations(9)[0]) == 252
+    assert workloads.equivalence_relations(9)[1] == 36
+    assert lines(workloads.permutation_matrices(5)[0]) == 110
+    assert lines(workloads.triangle_free(8)[0]) == 56
+    assert workloads.triangle_free(8)[1] == 28
+    assert cnf_clause_count(32) == 136
+    t, n = workloads.random_3cnf(32, 136, 0)
+    assert lines(t) == 136 and n == 32
+
+
+def test_3cnf_clauses_have_distinct_vars():
+    t, n = workloads.random_3cnf(12, 51, 0)
+    for line in t.strip().split("\n"):
+        vs = [int(l.strip().lstrip("~x")) for l in line.split("|")]
+        assert len(set(vs)) == 3 and all(0 <= v < n for v in vs)
+
+
+def test_dag_batch_ranges():
+    batch = random_dag_batch(64, 0)
+    for text, n in batch:
+        assert 10 <= n <= 30
+        size = len(text.strip().split("\n")) - 1
+        assert 50 <= size <= 2000
