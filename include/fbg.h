@@ -1,0 +1,196 @@
+/*
+ * fbg.h -- evaluation of Boolean terms on free Boolean generators, MI355X.
+ *
+ * Problem (Section 2.3, Proposition "prop22"): for a Boolean term
+ * t(x0..x{n-1}) and the free generators b_0..b_{n-1} of the algebra 2^(2^n)
+ * (Section 2.2: generator k is row k of the matrix whose columns are the
+ * binary expansions of 0..2^n-1), the vector d = t(b_0..b_{n-1}) codes the
+ * full DNF of t: bit mu of d is t at the valuation mu.  The number of 1-bits
+ * of d is the number of models of t (Section 3.2, l_{T,n}), and the positions
+ * of the 1-bits are the models themselves (a system of equations phi_i = 1
+ * has exactly those solutions, Section 5.1).  The method computes d block by
+ * block on wide bitwise processors (Section 2.3, time T = 2^(l+n-k-r) delta).
+ *
+ * Conventions used by every call:
+ *  - variable xk is bit k of the valuation index mu (least significant first);
+ *  - the DNF vector is an array of uint64 words; word w holds valuations
+ *    64w .. 64w+63, valuation mu at bit (mu & 63).  It has max(1, 2^(n-6))
+ *    words; bits at or above 2^n are zero;
+ *  - formula text: statements separated by newlines or ';', '#' comments.
+ *    "name = expr" defines a temporary; a bare "expr" is an assertion and the
+ *    formula is the conjunction of all assertions (at least one).  Operators
+ *    are the Python ones of the paper's scripts (Section 4.2): '~' not, '&'
+ *    and, '^' symmetric difference (the paper's '+'), '|' or, with Python
+ *    precedence ~ > & > ^ > |; parentheses; constants 0 and 1 (removed by
+ *    constant folding, the paper's Reduction of Section 4.1); variables
+ *    x0 .. x{n-1}.
+ *
+ * Memory and streams: device pointers are caller-owned device memory (for
+ * example torch tensors' data_ptr()); `stream` is a hipStream_t (NULL = the
+ * legacy default stream).  Every compute call is asynchronous on `stream`:
+ * results are valid once the stream is synchronised.  Argument errors are
+ * reported synchronously and nothing is launched.  A program is immutable
+ * after fbg_compile and may be used from several streams at once.
+ *
+ * Errors: every call returns an fbg_status; on failure fbg_last_error() (per
+ * thread) describes it and fbg_last_error_offset() gives the byte offset of a
+ * parse error (-1 otherwise).
+ */
+#ifndef FBG_H
+#define FBG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FBG_OK = 0,
+  FBG_E_INVAL = -1,   /* bad argument (null pointer, too-small buffer, ...) */
+  FBG_E_PARSE = -2,   /* malformed formula text */
+  FBG_E_RANGE = -3,   /* n out of range, variable >= n, program too large */
+  FBG_E_NOMEM = -4,   /* host or device allocation failed */
+  FBG_E_DEVICE = -5   /* HIP error (launch, copy, no device) */
+} fbg_status;
+
+/* Largest n accepted by fbg_count / fbg_enumerate / batches, and by
+   fbg_eval_dnf (whose output has 2^(n-6) words). */
+#define FBG_MAX_VARS 48
+#define FBG_MAX_DNF_VARS 40
+
+/* Largest number of words (32-bit slices) one lane evaluates per tile. */
+#define FBG_MAX_WORDS_PER_LANE 16
+
+typedef struct fbg_program fbg_program; /* opaque, library-owned */
+typedef struct fbg_batch fbg_batch;     /* opaque, library-owned */
+
+typedef struct {
+  int32_t n_vars;        /* n: the valuation space is 2^n */
+  int32_t const_value;   /* -1, or 0/1 when the formula folds to a constant */
+  uint64_t l2in;         /* 2-input AND/OR/XOR operations of the term after
+                            constant folding, hashing and dead-code removal
+                            (NOT is not counted): the node count of the time
+                            model of Section 2.3 */
+  int32_t n_instr;       /* device instructions (for words_per_lane below) */
+  int32_t n_regs;        /* LDS registers per slice the program needs */
+  int32_t n_clause_instr;/* instructions that conjoin a literal set directly */
+  int32_t words_per_lane;/* tuning the library picked for this program */
+  uint64_t dnf_words;    /* max(1, 2^(n-6)) */
+} fbg_program_info;
+
+/* Launch tuning.  Zero fields mean "let the library choose". */
+typedef struct {
+  int32_t words_per_lane;  /* 1, 2, 4, 8 or 16 (32-bit words per lane per tile) */
+  int32_t grid_blocks;     /* blocks of 256 threads for persistent launches */
+  int32_t reserved0;
+  int32_t reserved1;
+} fbg_tune;
+
+/*
+ * fbg_compile -- turn formula text into a straight-line bitwise program and
+ * upload it to the current HIP device (Section 4.1: the engine builds a
+ * computing tree for the formula; Reduction removes constants).
+ *   src     NUL-terminated formula text (format above).
+ *   n_vars  n, 0 <= n <= FBG_MAX_VARS; every variable used must be < n.
+ *           Variables below n that do not occur still index valuations.
+ *   flags   0 (reserved).
+ *   out     receives the program; free it with fbg_program_free.
+ * Errors: FBG_E_PARSE (with offset), FBG_E_RANGE, FBG_E_INVAL, FBG_E_NOMEM,
+ * FBG_E_DEVICE.  Synchronous.
+ */
+fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_program **out);
+
+/* Release a program and its device copy.  NULL is a no-op.  The caller must
+   make sure no launch that uses it is still pending. */
+void fbg_program_free(fbg_program *p);
+
+/* Metadata of a compiled program (host memory `out`). */
+fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out);
+
+/*
+ * fbg_eval_dnf -- write d = t(b_0..b_{n-1}) (Proposition "prop22") into
+ * d_out[0 .. max(1, 2^(n-6))), layout above.
+ *   d_out      device pointer, caller-owned, 8-byte aligned.
+ *   out_words  capacity of d_out in words; must be >= max(1, 2^(n-6)).
+ * n <= FBG_MAX_DNF_VARS.
+ */
+fbg_status fbg_eval_dnf(const fbg_program *p, uint64_t *d_out, uint64_t out_words, void *stream);
+
+/*
+ * fbg_count -- *d_count = number of 1-bits of d, i.e. the number of models
+ * (Section 3.2: l_{T,n} is the number of 1-bits of b).  Overwrites *d_count
+ * (device pointer to one uint64).  No device memory is allocated.
+ */
+fbg_status fbg_count(const fbg_program *p, uint64_t *d_count, void *stream);
+
+/*
+ * fbg_enumerate -- the models, i.e. the positions mu of the 1-bits of d in
+ * ascending order (Section 3.2: every model of T* is read off b; the paper
+ * writes all solutions to out.txt, Section 4.2).
+ *   d_idx     device array of `capacity` uint64; receives the first
+ *             min(total, capacity) model indices, ascending.  May be NULL
+ *             when capacity is 0.
+ *   d_total   device pointer to one uint64; receives the total number of
+ *             models (also when it exceeds capacity).
+ * Allocates temporary device memory on `stream` (stream-ordered) for the
+ * per-tile counts and offsets.
+ */
+fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total,
+                         void *stream);
+
+/*
+ * Batches (Section 2.3: 2^r processors act as one wide processor; Section
+ * 4.1: the search space is sliced into blocks by the available processors).
+ * A batch packs the tiles of many programs into one work queue served by one
+ * persistent launch, largest work first.
+ *
+ * fbg_batch_create -- build and upload the work plan for `np` programs.
+ *   ps     array of np program pointers (the programs must outlive the batch).
+ *   tune   NULL for automatic tuning, else fixed words_per_lane / grid.
+ * fbg_batch_count -- d_counts[i] = number of models of ps[i], i < np
+ *   (overwritten).  One zero-fill kernel and one persistent kernel on
+ *   `stream`; allocates nothing, so it may be captured into a HIP graph.
+ *   Concurrent fbg_batch_count calls on one batch object race (it holds the
+ *   queue head); use one batch object per stream.
+ * fbg_count_batch -- create, count and free in one call (allocates).
+ */
+fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_tune *tune, fbg_batch **out);
+fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream);
+void fbg_batch_free(fbg_batch *b);
+fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d_counts, const fbg_tune *tune,
+                           void *stream);
+
+/*
+ * Tuned single-program variants: as fbg_count / fbg_eval_dnf but with an
+ * explicit tuning (used by the autotuner and by tests that sweep tilings).
+ */
+fbg_status fbg_count_tuned(const fbg_program *p, uint64_t *d_count, const fbg_tune *tune, void *stream);
+fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t out_words, const fbg_tune *tune,
+                              void *stream);
+
+/*
+ * fbg_program_emulate -- run the encoded device program of `p` for the given
+ * words_per_lane on the host, slice by slice, exactly as the kernels
+ * interpret it, and write the DNF words (h_dnf, host memory, >= dnf_words)
+ * and/or the count (h_count).  A debugging aid for the compiler and encoder,
+ * never used by the calls above.  n <= 30.
+ */
+fbg_status fbg_program_emulate(const fbg_program *p, int32_t words_per_lane, uint64_t *h_dnf, uint64_t out_words,
+                               uint64_t *h_count);
+
+/* Human-readable listing of the encoded program (host memory, NUL-terminated,
+   truncated to `cap` bytes).  Returns the full length. */
+int64_t fbg_program_disasm(const fbg_program *p, int32_t words_per_lane, char *buf, int64_t cap);
+
+const char *fbg_last_error(void);
+int64_t fbg_last_error_offset(void);
+
+/* Library version string. */
+const char *fbg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FBG_H */

@@ -46,10 +46,12 @@ def _load():
     lib.orc_models.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, u64p, ctypes.c_uint64, u64p]
     lib.orc_eval_at.argtypes = [ctypes.c_char_p, ctypes.c_int, u64p, ctypes.c_uint64,
                                 ctypes.POINTER(ctypes.c_uint8)]
+    lib.orc_count_range.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_int, u64p]
     lib.orc_describe.argtypes = [ctypes.c_char_p] + [ctypes.POINTER(ctypes.c_int)] * 3
     lib.orc_bitpar_count.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, u64p]
     lib.orc_bitpar_dnf.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, u64p, ctypes.c_uint64]
-    for f in ("orc_count", "orc_dnf", "orc_models", "orc_eval_at", "orc_describe",
+    for f in ("orc_count", "orc_count_range", "orc_dnf", "orc_models", "orc_eval_at", "orc_describe",
               "orc_bitpar_count", "orc_bitpar_dnf"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -81,6 +83,13 @@ def count(src, n, threads=0):
     """Number of models: valuations mu in 2^n with t(mu) = 1."""
     out = ctypes.c_uint64(0)
     _check(_load().orc_count(_b(src), n, threads, ctypes.byref(out)))
+    return out.value
+
+
+def count_range(src, n, lo, hi, threads=0):
+    """Number of models mu with lo <= mu < hi."""
+    out = ctypes.c_uint64(0)
+    _check(_load().orc_count_range(_b(src), n, int(lo), int(hi), threads, ctypes.byref(out)))
     return out.value
 
 

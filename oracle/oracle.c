@@ -411,20 +411,29 @@ static int default_threads(int threads) {
   return c > 0 ? (int)c : 1;
 }
 
-/* Split [0, total) into contiguous chunks aligned to 64 valuations. */
+/* Split [lo, hi) into contiguous chunks aligned to 64 valuations. */
+static int run_range(const oformula *f, uint64_t lo, uint64_t hi, int threads, uint64_t *dnf, int want_models,
+                     uint64_t *count, uint64_t *models, uint64_t cap, uint64_t *total);
+
 static int run_valuations(const oformula *f, int n, int threads, uint64_t *dnf, int want_models,
                           uint64_t *count, uint64_t *models, uint64_t cap, uint64_t *total) {
-  uint64_t total_v = (uint64_t)1 << n;
+  return run_range(f, 0, (uint64_t)1 << n, threads, dnf, want_models, count, models, cap, total);
+}
+
+static int run_range(const oformula *f, uint64_t lo, uint64_t hi, int threads, uint64_t *dnf, int want_models,
+                     uint64_t *count, uint64_t *models, uint64_t cap, uint64_t *total) {
+  uint64_t total_v = hi;
   int T = default_threads(threads);
-  uint64_t words = (total_v + 63) / 64;
+  uint64_t w0 = lo / 64;
+  uint64_t words = (total_v + 63) / 64 - w0;
   if ((uint64_t)T > words) T = (int)words;
   if (T < 1) T = 1;
   vjob *jobs = (vjob *)calloc((size_t)T, sizeof(vjob));
   pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
   for (int t = 0; t < T; t++) {
-    uint64_t wlo = words * (uint64_t)t / (uint64_t)T, whi = words * (uint64_t)(t + 1) / (uint64_t)T;
+    uint64_t wlo = w0 + words * (uint64_t)t / (uint64_t)T, whi = w0 + words * (uint64_t)(t + 1) / (uint64_t)T;
     jobs[t].f = f;
-    jobs[t].lo = wlo * 64;
+    jobs[t].lo = wlo * 64 > lo ? wlo * 64 : lo;
     jobs[t].hi = whi * 64 < total_v ? whi * 64 : total_v;
     jobs[t].dnf = dnf;
     jobs[t].want_models = want_models;
@@ -492,6 +501,26 @@ int orc_models(const char *src, int n, int threads, uint64_t *out, uint64_t cap,
     return -1;
   }
   run_valuations(&f, n, threads, NULL, 1, NULL, out, cap, total);
+  free_formula(&f);
+  return 0;
+}
+
+/* Models among the valuations lo <= mu < hi (a bounded sample of the count). */
+int orc_count_range(const char *src, int n, uint64_t lo, uint64_t hi, int threads, uint64_t *out_count) {
+  oformula f;
+  if (parse_formula(src, &f)) return -1;
+  if (check_n(&f, n, ORC_NMAX)) {
+    free_formula(&f);
+    return -1;
+  }
+  uint64_t top = (uint64_t)1 << n;
+  if (hi > top) hi = top;
+  if (lo >= hi) {
+    *out_count = 0;
+    free_formula(&f);
+    return 0;
+  }
+  run_range(&f, lo, hi, threads, NULL, 0, out_count, NULL, 0, NULL);
   free_formula(&f);
   return 0;
 }

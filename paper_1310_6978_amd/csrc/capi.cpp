@@ -1,0 +1,514 @@
+// capi.cpp -- the C ABI of include/fbg.h: program residency, launch
+// geometry, work plans for batches, and argument checking.
+#include <hip/hip_runtime_api.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fbg.h"
+#include "fbg_internal.h"
+#include "fbg_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+thread_local int64_t g_err_off = -1;
+
+fbg_status fail(fbg_status st, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  g_err_off = -1;
+  return st;
+}
+
+fbg_status hip_fail(hipError_t e, const char *what) {
+  return fail(FBG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int kMaxLog2W = 4;
+constexpr int kWavesPerBlock = 4;
+constexpr size_t kMaxLdsPerBlock = 64 * 1024;
+
+int g_cu_count[64];
+std::once_flag g_cu_once[64];
+
+int cu_count(int dev) {
+  if (dev < 0 || dev >= 64) return 256;
+  std::call_once(g_cu_once[dev], [dev] {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    g_cu_count[dev] = v;
+  });
+  return g_cu_count[dev];
+}
+
+uint64_t slices_of(int n) { return n >= FBG_SLICE_BITS ? (1ull << (n - FBG_SLICE_BITS)) : 1ull; }
+uint64_t dnf_words_of(int n) { return n >= 6 ? (1ull << (n - 6)) : 1ull; }
+uint64_t tiles_of(uint64_t nslices, int log2w) {
+  const uint64_t per = 64ull << log2w;
+  return (nslices + per - 1) / per;
+}
+
+size_t lds_per_wave(uint32_t nregs, int log2w) { return (size_t)nregs * (64u << log2w) * 4u; }
+
+}  // namespace
+
+struct fbg_program {
+  fbg::Compiled c;
+  int device = -1;                 // -1: compiled without a device (host only)
+  uint32_t *d_code = nullptr;
+  std::vector<uint32_t> words[kMaxLog2W + 1];
+  uint64_t dev_off[kMaxLog2W + 1] = {0, 0, 0, 0, 0};
+  uint32_t nins[kMaxLog2W + 1] = {0, 0, 0, 0, 0};
+  int auto_log2w = 0;
+  uint64_t nslices = 1;
+};
+
+struct fbg_batch {
+  int device = -1;
+  int log2w = 0;
+  int grid = 1;
+  int block = 256;
+  size_t lds = 0;
+  int32_t np = 0;
+  uint32_t nitems = 0;
+  uint32_t max_regs = 0;
+  fbg::BatchProg *d_progs = nullptr;
+  fbg::BatchItem *d_items = nullptr;
+  uint32_t *d_head = nullptr;
+};
+
+namespace {
+
+// Largest words-per-lane that still gives every wave of a full grid a tile,
+// within the LDS budget of the program's registers.
+int pick_log2w(uint64_t nslices, uint32_t nregs, int dev) {
+  const uint64_t waves = (uint64_t)cu_count(dev) * 32;  // 8 waves per SIMD
+  int best = 0;
+  for (int l = kMaxLog2W; l >= 0; l--) {
+    if (lds_per_wave(nregs, l) > kMaxLdsPerBlock) continue;
+    if (tiles_of(nslices, l) >= waves || l == 0) {
+      best = l;
+      break;
+    }
+  }
+  while (best > 0 && lds_per_wave(nregs, best) > kMaxLdsPerBlock) best--;
+  return best;
+}
+
+struct Geometry {
+  int log2w, grid, block;
+  size_t lds;
+};
+
+fbg_status geometry(const fbg_program *p, const fbg_tune *tune, uint64_t min_tiles_per_wave, Geometry &g) {
+  int l = p->auto_log2w;
+  if (tune && tune->words_per_lane) {
+    int w = tune->words_per_lane;
+    if (w < 1 || w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1)))
+      return fail(FBG_E_INVAL, "words_per_lane must be 1, 2, 4, 8 or 16 (got %d)", w);
+    l = __builtin_ctz((unsigned)w);
+  }
+  const size_t lw = lds_per_wave((uint32_t)p->c.nregs, l);
+  int wpb = kWavesPerBlock;
+  if (lw * wpb > kMaxLdsPerBlock) wpb = 1;
+  if (lw * wpb > kMaxLdsPerBlock)
+    return fail(FBG_E_RANGE, "program needs %d registers x %d words per lane: %zu bytes of LDS per wave (max %zu)",
+                p->c.nregs, 1 << l, lw, kMaxLdsPerBlock);
+  const uint64_t ntiles = tiles_of(p->nslices, l);
+  uint64_t blocks = (ntiles + wpb - 1) / wpb;
+  (void)min_tiles_per_wave;
+  uint64_t maxb = (uint64_t)cu_count(p->device) * (32 / wpb);
+  if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
+  g.log2w = l;
+  g.block = 64 * wpb;
+  g.grid = (int)std::max<uint64_t>(1, std::min(blocks, maxb));
+  g.lds = lw * wpb;
+  return FBG_OK;
+}
+
+fbg_status check_program(const fbg_program *p) {
+  if (!p) return fail(FBG_E_INVAL, "program is NULL");
+  if (p->device < 0 || !p->d_code) return fail(FBG_E_DEVICE, "program was compiled without a HIP device");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != p->device)
+    return fail(FBG_E_INVAL, "program lives on device %d but the current device is %d", p->device, dev);
+  return FBG_OK;
+}
+
+fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
+  fbg::EvalArgs a;
+  memset(&a, 0, sizeof a);
+  a.code = p->d_code + p->dev_off[log2w];
+  a.nins = p->nins[log2w];
+  a.nregs = (uint32_t)p->c.nregs;
+  a.n = p->c.n;
+  a.nslices = p->nslices;
+  a.ntiles = tiles_of(p->nslices, log2w);
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fbg_version(void) { return "fbg 0.1 (gfx950)"; }
+const char *fbg_last_error(void) { return g_err.c_str(); }
+int64_t fbg_last_error_offset(void) { return g_err_off; }
+
+fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_program **out) {
+  if (!out) return fail(FBG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!src) return fail(FBG_E_INVAL, "src is NULL");
+  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
+  if (n_vars < 0 || n_vars > FBG_MAX_VARS) return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_VARS);
+  fbg_program *p = new (std::nothrow) fbg_program();
+  if (!p) return fail(FBG_E_NOMEM, "out of host memory");
+  std::string msg;
+  int64_t off = -1;
+  int st = fbg::compile_formula(src, n_vars, p->c, msg, off);
+  if (st != FBG_OK) {
+    delete p;
+    g_err = msg;
+    g_err_off = off;
+    if (off >= 0) g_err += " (offset " + std::to_string(off) + ")";
+    return (fbg_status)st;
+  }
+  p->nslices = slices_of(n_vars);
+  size_t total = 0;
+  for (int l = 0; l <= kMaxLog2W; l++) {
+    p->nins[l] = fbg::encode_program(p->c, l, p->words[l]);
+    p->dev_off[l] = total;
+    total += p->words[l].size();
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(e, "hipGetDevice");
+    }
+    p->device = dev;
+    std::vector<uint32_t> all;
+    all.reserve(total + 8);
+    for (int l = 0; l <= kMaxLog2W; l++) all.insert(all.end(), p->words[l].begin(), p->words[l].end());
+    all.resize(all.size() + 8, 0);  // padding: never read, keeps the allocation non-empty
+    e = hipMalloc((void **)&p->d_code, all.size() * sizeof(uint32_t));
+    if (e != hipSuccess) {
+      delete p;
+      return fail(FBG_E_NOMEM, "hipMalloc of the program: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->d_code, all.data(), all.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p->d_code);
+      delete p;
+      return hip_fail(e, "hipMemcpy of the program");
+    }
+    p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, dev);
+  } else {
+    p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, -1);
+  }
+  *out = p;
+  return FBG_OK;
+}
+
+void fbg_program_free(fbg_program *p) {
+  if (!p) return;
+  if (p->d_code) (void)hipFree(p->d_code);
+  delete p;
+}
+
+fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out) {
+  if (!p || !out) return fail(FBG_E_INVAL, "NULL argument");
+  memset(out, 0, sizeof *out);
+  out->n_vars = p->c.n;
+  out->const_value = p->c.const_value;
+  out->l2in = p->c.l2in;
+  out->n_instr = (int32_t)p->nins[p->auto_log2w];
+  out->n_regs = p->c.nregs;
+  out->n_clause_instr = p->c.n_clause_instr;
+  out->words_per_lane = 1 << p->auto_log2w;
+  out->dnf_words = dnf_words_of(p->c.n);
+  return FBG_OK;
+}
+
+fbg_status fbg_count_tuned(const fbg_program *p, uint64_t *d_count, const fbg_tune *tune, void *stream) {
+  fbg_status st = check_program(p);
+  if (st) return st;
+  if (!d_count) return fail(FBG_E_INVAL, "d_count is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (p->c.const_value >= 0) {
+    e = fbg::launch_set_u64(d_count, p->c.const_value ? (1ull << p->c.n) : 0ull, s);
+    return e == hipSuccess ? FBG_OK : hip_fail(e, "launch");
+  }
+  Geometry g;
+  if ((st = geometry(p, tune, 1, g))) return st;
+  fbg::EvalArgs a = base_args(p, g.log2w);
+  a.out_count = d_count;
+  e = fbg::launch_set_u64(d_count, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "launch");
+  e = fbg::launch_eval(fbg::EVAL_COUNT, g.log2w, a, g.grid, g.block, g.lds, s);
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the count kernel");
+}
+
+fbg_status fbg_count(const fbg_program *p, uint64_t *d_count, void *stream) {
+  return fbg_count_tuned(p, d_count, nullptr, stream);
+}
+
+fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t out_words, const fbg_tune *tune,
+                              void *stream) {
+  fbg_status st = check_program(p);
+  if (st) return st;
+  if (!d_out) return fail(FBG_E_INVAL, "d_out is NULL");
+  if (p->c.n > FBG_MAX_DNF_VARS) return fail(FBG_E_RANGE, "n=%d above %d for a DNF vector", p->c.n, FBG_MAX_DNF_VARS);
+  const uint64_t need = dnf_words_of(p->c.n);
+  if (out_words < need)
+    return fail(FBG_E_INVAL, "out_words=%llu < %llu", (unsigned long long)out_words, (unsigned long long)need);
+  Geometry g;
+  if ((st = geometry(p, tune, 1, g))) return st;
+  fbg::EvalArgs a = base_args(p, g.log2w);
+  a.out32 = (uint32_t *)d_out;
+  a.out_slices = 2 * need;
+  hipError_t e = fbg::launch_eval(fbg::EVAL_DNF, g.log2w, a, g.grid, g.block, g.lds, (hipStream_t)stream);
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the DNF kernel");
+}
+
+fbg_status fbg_eval_dnf(const fbg_program *p, uint64_t *d_out, uint64_t out_words, void *stream) {
+  return fbg_eval_dnf_tuned(p, d_out, out_words, nullptr, stream);
+}
+
+fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total,
+                         void *stream) {
+  fbg_status st = check_program(p);
+  if (st) return st;
+  if (!d_total) return fail(FBG_E_INVAL, "d_total is NULL");
+  if (capacity > 0 && !d_idx) return fail(FBG_E_INVAL, "d_idx is NULL with capacity %llu", (unsigned long long)capacity);
+  Geometry g;
+  if ((st = geometry(p, nullptr, 1, g))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  fbg::EvalArgs a = base_args(p, g.log2w);
+  const uint64_t nt = a.ntiles;
+  const uint64_t nb = fbg::scan_block_count(nt);
+  const size_t bytes_cnt = ((nt * 4 + 255) / 256) * 256;
+  const size_t bytes_off = nt * 8;
+  const size_t bytes_blk = (nb + 1) * 8;
+  char *tmp = nullptr;
+  hipError_t e = hipMallocAsync((void **)&tmp, bytes_cnt + bytes_off + bytes_blk, s);
+  if (e != hipSuccess) return fail(FBG_E_NOMEM, "hipMallocAsync of %zu bytes: %s", bytes_cnt + bytes_off + bytes_blk,
+                                   hipGetErrorString(e));
+  uint32_t *cnt = (uint32_t *)tmp;
+  uint64_t *off = (uint64_t *)(tmp + bytes_cnt);
+  uint64_t *blk = (uint64_t *)(tmp + bytes_cnt + bytes_off);
+  a.tile_counts = cnt;
+  e = fbg::launch_eval(fbg::EVAL_TILECNT, g.log2w, a, g.grid, g.block, g.lds, s);
+  if (e == hipSuccess) e = fbg::launch_scan(cnt, nt, off, blk, d_total, s);
+  if (e == hipSuccess && capacity > 0) {
+    a.tile_offsets = off;
+    a.out_idx = d_idx;
+    a.capacity = capacity;
+    e = fbg::launch_eval(fbg::EVAL_ENUM, g.log2w, a, g.grid, g.block, g.lds, s);
+  }
+  hipError_t e2 = hipFreeAsync(tmp, s);
+  if (e != hipSuccess) return hip_fail(e, "launch of an enumeration kernel");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return FBG_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_tune *tune, fbg_batch **out) {
+  if (!out) return fail(FBG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (np <= 0 || !ps) return fail(FBG_E_INVAL, "empty batch");
+  int dev = -1;
+  for (int32_t i = 0; i < np; i++) {
+    fbg_status st = check_program(ps[i]);
+    if (st) return st;
+    dev = ps[i]->device;
+  }
+  // words per lane: the tuning, else the choice for the largest program
+  int l = 0;
+  if (tune && tune->words_per_lane) {
+    int w = tune->words_per_lane;
+    if (w < 1 || w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1)))
+      return fail(FBG_E_INVAL, "words_per_lane must be 1, 2, 4, 8 or 16 (got %d)", w);
+    l = __builtin_ctz((unsigned)w);
+  } else {
+    uint64_t best = 0;
+    for (int32_t i = 0; i < np; i++) {
+      uint64_t cost = ps[i]->nslices * (uint64_t)std::max<size_t>(1, ps[i]->c.code.size());
+      if (cost >= best) {
+        best = cost;
+        l = ps[i]->auto_log2w;
+      }
+    }
+  }
+  uint32_t max_regs = 0;
+  for (int32_t i = 0; i < np; i++) max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
+  while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
+  const size_t lw = lds_per_wave(max_regs, l);
+  int wpb = kWavesPerBlock;
+  if (lw * wpb > kMaxLdsPerBlock) wpb = 1;
+  if (lw * wpb > kMaxLdsPerBlock) return fail(FBG_E_RANGE, "a program of the batch needs %u registers", max_regs);
+
+  std::vector<fbg::BatchProg> progs((size_t)np);
+  double total_cost = 0;
+  for (int32_t i = 0; i < np; i++) {
+    const fbg_program *p = ps[i];
+    fbg::BatchProg &b = progs[(size_t)i];
+    b.code = p->d_code + p->dev_off[l];
+    b.nins = p->nins[l];
+    b.nregs = (uint32_t)p->c.nregs;
+    b.n = p->c.n;
+    b.pad0 = 0;
+    b.nslices = p->nslices;
+    b.ntiles = tiles_of(p->nslices, l);
+    total_cost += (double)b.ntiles * (b.nins + 4);
+  }
+  const int cus = cu_count(dev);
+  const uint64_t waves = (uint64_t)cus * 32;
+  // about four items per wave; never split below one tile
+  const double target = std::max(1.0, total_cost / (double)(waves * 4));
+  std::vector<fbg::BatchItem> items;
+  std::vector<double> cost;
+  for (int32_t i = 0; i < np; i++) {
+    const fbg::BatchProg &b = progs[(size_t)i];
+    const double per_tile = b.nins + 4.0;
+    uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
+    for (uint64_t t = 0; t < b.ntiles; t += chunk) {
+      fbg::BatchItem it;
+      it.prog = (uint32_t)i;
+      it.pad0 = 0;
+      it.t0 = t;
+      it.t1 = std::min(b.ntiles, t + chunk);
+      items.push_back(it);
+      cost.push_back((double)(it.t1 - it.t0) * per_tile);
+    }
+  }
+  if (items.size() > 0xFFFFFFF0ull) return fail(FBG_E_RANGE, "too many work items");
+  std::vector<size_t> order(items.size());
+  for (size_t i = 0; i < order.size(); i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<fbg::BatchItem> sorted;
+  sorted.reserve(items.size());
+  for (size_t i : order) sorted.push_back(items[i]);
+
+  fbg_batch *b = new (std::nothrow) fbg_batch();
+  if (!b) return fail(FBG_E_NOMEM, "out of host memory");
+  b->device = dev;
+  b->log2w = l;
+  b->np = np;
+  b->nitems = (uint32_t)sorted.size();
+  b->max_regs = max_regs;
+  b->block = 64 * wpb;
+  b->lds = lw * wpb;
+  uint64_t maxb = (uint64_t)cus * (32 / wpb);
+  if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
+  b->grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((b->nitems + wpb - 1) / wpb, maxb));
+  hipError_t e = hipMalloc((void **)&b->d_progs, progs.size() * sizeof(fbg::BatchProg));
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, sorted.size() * sizeof(fbg::BatchItem));
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_head, 256);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_progs, progs.data(), progs.size() * sizeof(fbg::BatchProg), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_items, sorted.data(), sorted.size() * sizeof(fbg::BatchItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    fbg_batch_free(b);
+    return fail(FBG_E_NOMEM, "batch upload: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return FBG_OK;
+}
+
+fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream) {
+  if (!b) return fail(FBG_E_INVAL, "batch is NULL");
+  if (!d_counts) return fail(FBG_E_INVAL, "d_counts is NULL");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != b->device) return fail(FBG_E_INVAL, "batch lives on device %d, current device is %d", b->device, dev);
+  hipStream_t s = (hipStream_t)stream;
+  e = fbg::launch_zero(d_counts, (uint64_t)b->np, b->d_head, s);
+  if (e != hipSuccess) return hip_fail(e, "launch of the zero fill");
+  fbg::BatchArgs a;
+  a.progs = b->d_progs;
+  a.items = b->d_items;
+  a.nitems = b->nitems;
+  a.max_regs = b->max_regs;
+  a.head = b->d_head;
+  a.counts = d_counts;
+  e = fbg::launch_batch(b->log2w, a, b->grid, b->block, b->lds, s);
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the batch kernel");
+}
+
+void fbg_batch_free(fbg_batch *b) {
+  if (!b) return;
+  if (b->d_progs) (void)hipFree(b->d_progs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_head) (void)hipFree(b->d_head);
+  delete b;
+}
+
+fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d_counts, const fbg_tune *tune,
+                           void *stream) {
+  fbg_batch *b = nullptr;
+  fbg_status st = fbg_batch_create(ps, np, tune, &b);
+  if (st) return st;
+  st = fbg_batch_count(b, d_counts, stream);
+  // the plan must outlive the launch
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  fbg_batch_free(b);
+  if (st) return st;
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+// --------------------------------------------------------------- debugging
+
+fbg_status fbg_program_emulate(const fbg_program *p, int32_t words_per_lane, uint64_t *h_dnf, uint64_t out_words,
+                               uint64_t *h_count) {
+  if (!p) return fail(FBG_E_INVAL, "program is NULL");
+  if (p->c.n > 30) return fail(FBG_E_RANGE, "emulation is limited to n <= 30");
+  int w = words_per_lane;
+  if (w < 1 || w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1))) return fail(FBG_E_INVAL, "bad words_per_lane %d", w);
+  const int l = __builtin_ctz((unsigned)w);
+  const uint64_t need = dnf_words_of(p->c.n);
+  if (h_dnf && out_words < need) return fail(FBG_E_INVAL, "out_words too small");
+  std::vector<uint32_t> s32((size_t)std::max<uint64_t>(2, p->nslices), 0u);
+  fbg::emulate_program(p->words[l], p->nins[l], p->c.nregs, p->c.n, l, s32.data());
+  if (h_dnf) memcpy(h_dnf, s32.data(), need * 8);
+  if (h_count) {
+    uint64_t c = 0;
+    for (uint64_t i = 0; i < p->nslices; i++) c += (uint64_t)__builtin_popcount(s32[i]);
+    *h_count = c;
+  }
+  return FBG_OK;
+}
+
+int64_t fbg_program_disasm(const fbg_program *p, int32_t words_per_lane, char *buf, int64_t cap) {
+  if (!p) return -1;
+  int w = words_per_lane <= 0 ? (1 << p->auto_log2w) : words_per_lane;
+  if (w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1))) return -1;
+  const int l = __builtin_ctz((unsigned)w);
+  std::string s = fbg::disasm_program(p->words[l], p->nins[l], l);
+  if (buf && cap > 0) {
+    size_t k = std::min<size_t>((size_t)cap - 1, s.size());
+    memcpy(buf, s.data(), k);
+    buf[k] = 0;
+  }
+  return (int64_t)s.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,946 @@
+// compiler.cpp -- formula text to straight-line bitwise program.
+//
+// Section 4.1 of the paper: the engine builds a computing tree for the formula
+// and the Reduction submodule removes the constants 0 and 1.  Here the text is
+// parsed into a hash-consed graph of 2-input AND / XOR nodes with complemented
+// edges (OR is AND with complemented inputs and output), which gives constant
+// folding, common-subexpression elimination and dead-code removal by
+// construction.  Code generation then:
+//   * splits the root into top-level conjuncts (the equations of a system,
+//     Section 5.1, and the clauses of a CNF);
+//   * turns every sub-term that is an OR, AND or XOR of literals into one
+//     literal-set operand (fbg_isa.h), whatever its width;
+//   * evaluates the remaining structure in post order through a current value
+//     and LDS registers, registers being allocated by a linear scan over the
+//     emitted code.
+#include <pthread.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cctype>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/fbg.h"
+#include "fbg_internal.h"
+
+namespace fbg {
+namespace {
+
+// ------------------------------------------------------------------ graph
+
+enum : uint8_t { NK_CONST = 0, NK_VAR = 1, NK_AND = 2, NK_XOR = 3 };
+
+struct GNode {
+  uint8_t kind;
+  uint32_t a, b;  // VAR: a = variable; AND/XOR: child edges
+};
+
+// Edge = node << 1 | complement.  Node 0 is the constant false.
+typedef uint32_t Edge;
+constexpr Edge kFalse = 0, kTrue = 1;
+
+struct Graph {
+  std::vector<GNode> nodes;
+  std::unordered_map<uint64_t, uint32_t> table;
+  std::unordered_map<int, uint32_t> vars;
+
+  Graph() { nodes.push_back({NK_CONST, 0, 0}); }
+
+  uint32_t node_of(uint8_t kind, uint32_t a, uint32_t b) {
+    uint64_t key = ((uint64_t)kind << 62) ^ ((uint64_t)a << 31) ^ (uint64_t)b;
+    auto it = table.find(key);
+    if (it != table.end()) {
+      const GNode &g = nodes[it->second];
+      if (g.kind == kind && g.a == a && g.b == b) return it->second;
+      // key collision (only for gigantic graphs): fall back to a linear probe
+      for (uint32_t i = 1; i < nodes.size(); i++)
+        if (nodes[i].kind == kind && nodes[i].a == a && nodes[i].b == b) return i;
+    }
+    uint32_t id = (uint32_t)nodes.size();
+    nodes.push_back({kind, a, b});
+    table.emplace(key, id);
+    return id;
+  }
+
+  Edge var(int k) {
+    auto it = vars.find(k);
+    if (it != vars.end()) return it->second << 1;
+    uint32_t id = node_of(NK_VAR, (uint32_t)k, 0);
+    vars.emplace(k, id);
+    return id << 1;
+  }
+
+  Edge And(Edge a, Edge b) {
+    if (a > b) std::swap(a, b);
+    if (a == kFalse) return kFalse;
+    if (a == kTrue) return b;
+    if (a == b) return a;
+    if ((a ^ 1u) == b) return kFalse;
+    return node_of(NK_AND, a, b) << 1;
+  }
+
+  Edge Xor(Edge a, Edge b) {
+    uint32_t c = (a ^ b) & 1u;
+    a &= ~1u;
+    b &= ~1u;
+    if (a > b) std::swap(a, b);
+    if (a == kFalse) return b ^ c;
+    if (a == b) return kFalse ^ c;
+    return (node_of(NK_XOR, a, b) << 1) ^ c;
+  }
+
+  Edge Or(Edge a, Edge b) { return And(a ^ 1u, b ^ 1u) ^ 1u; }
+};
+
+// ----------------------------------------------------------------- parser
+
+struct Tok {
+  enum Kind { END, SEP, LP, RP, NOT, AND, XOR, OR, EQ, CONST, VAR, NAME } kind;
+  int64_t pos;
+  int64_t val;  // CONST value, VAR index
+  std::string name;
+};
+
+struct Parser {
+  const char *src;
+  int n;
+  Graph &g;
+  std::vector<Tok> toks;
+  size_t p = 0;
+  std::unordered_map<std::string, Edge> names;
+  std::string msg;
+  int64_t off = -1;
+  int status = FBG_OK;
+
+  Parser(const char *s, int nv, Graph &gr) : src(s), n(nv), g(gr) {}
+
+  bool fail(int st, int64_t at, const std::string &m) {
+    if (status == FBG_OK) {
+      status = st;
+      off = at;
+      msg = m;
+    }
+    return false;
+  }
+
+  bool lex() {
+    int64_t i = 0;
+    for (;;) {
+      char c = src[i];
+      if (c == 0) {
+        toks.push_back({Tok::END, i, 0, {}});
+        return true;
+      }
+      if (c == ' ' || c == '\t' || c == '\r') {
+        i++;
+        continue;
+      }
+      if (c == '#') {
+        while (src[i] && src[i] != '\n') i++;
+        continue;
+      }
+      Tok t{Tok::END, i, 0, {}};
+      switch (c) {
+        case '\n':
+        case ';': t.kind = Tok::SEP; i++; break;
+        case '(': t.kind = Tok::LP; i++; break;
+        case ')': t.kind = Tok::RP; i++; break;
+        case '~': t.kind = Tok::NOT; i++; break;
+        case '&': t.kind = Tok::AND; i++; break;
+        case '^': t.kind = Tok::XOR; i++; break;
+        case '|': t.kind = Tok::OR; i++; break;
+        case '=': t.kind = Tok::EQ; i++; break;
+        default:
+          if (isdigit((unsigned char)c)) {
+            int64_t st = i;
+            while (isdigit((unsigned char)src[i])) i++;
+            if (i - st != 1 || (c != '0' && c != '1'))
+              return fail(FBG_E_PARSE, st, "only the constants 0 and 1 are allowed");
+            t.kind = Tok::CONST;
+            t.val = c - '0';
+          } else if (isalpha((unsigned char)c) || c == '_') {
+            int64_t st = i;
+            while (isalnum((unsigned char)src[i]) || src[i] == '_') i++;
+            std::string word(src + st, (size_t)(i - st));
+            bool isvar = word.size() >= 2 && word[0] == 'x';
+            for (size_t q = 1; isvar && q < word.size(); q++) isvar = isdigit((unsigned char)word[q]) != 0;
+            if (isvar) {
+              if (word.size() > 9) return fail(FBG_E_RANGE, st, "variable index too large");
+              t.kind = Tok::VAR;
+              t.val = std::stoll(word.substr(1));
+            } else {
+              t.kind = Tok::NAME;
+              t.name = word;
+            }
+          } else {
+            return fail(FBG_E_PARSE, i, std::string("unexpected character '") + c + "'");
+          }
+      }
+      toks.push_back(t);
+    }
+  }
+
+  const Tok &peek() const { return toks[p]; }
+
+  // precedence climbing over | (1), ^ (2), & (3); ~ is a prefix operator
+  bool primary(Edge &e) {
+    const Tok &t = toks[p];
+    switch (t.kind) {
+      case Tok::NOT: {
+        p++;
+        Edge a;
+        if (!primary(a)) return false;
+        e = a ^ 1u;
+        return true;
+      }
+      case Tok::LP: {
+        p++;
+        if (!expr(e, 1)) return false;
+        if (toks[p].kind != Tok::RP) return fail(FBG_E_PARSE, toks[p].pos, "expected ')'");
+        p++;
+        return true;
+      }
+      case Tok::CONST: p++; e = t.val ? kTrue : kFalse; return true;
+      case Tok::VAR:
+        if (t.val >= n) return fail(FBG_E_RANGE, t.pos, "variable x" + std::to_string(t.val) + " >= n");
+        p++;
+        e = g.var((int)t.val);
+        return true;
+      case Tok::NAME: {
+        auto it = names.find(t.name);
+        if (it == names.end()) return fail(FBG_E_PARSE, t.pos, "undefined name '" + t.name + "'");
+        p++;
+        e = it->second;
+        return true;
+      }
+      default: return fail(FBG_E_PARSE, t.pos, "expected an operand");
+    }
+  }
+
+  static int prec(Tok::Kind k) { return k == Tok::OR ? 1 : k == Tok::XOR ? 2 : k == Tok::AND ? 3 : 0; }
+
+  bool expr(Edge &e, int minp) {
+    if (!primary(e)) return false;
+    for (;;) {
+      Tok::Kind k = toks[p].kind;
+      int pr = prec(k);
+      if (pr == 0 || pr < minp) return true;
+      p++;
+      Edge r;
+      if (!expr(r, pr + 1)) return false;  // left associative
+      e = (k == Tok::OR) ? g.Or(e, r) : (k == Tok::XOR) ? g.Xor(e, r) : g.And(e, r);
+    }
+  }
+
+  bool program(Edge &root) {
+    if (!lex()) return false;
+    root = kTrue;
+    int nassert = 0;
+    for (;;) {
+      while (peek().kind == Tok::SEP) p++;
+      if (peek().kind == Tok::END) break;
+      bool def = peek().kind == Tok::NAME && toks[p + 1].kind == Tok::EQ;
+      if (peek().kind == Tok::VAR && toks[p + 1].kind == Tok::EQ)
+        return fail(FBG_E_PARSE, peek().pos, "cannot assign to a variable");
+      std::string name;
+      if (def) {
+        name = peek().name;
+        if (names.count(name)) return fail(FBG_E_PARSE, peek().pos, "name '" + name + "' defined twice");
+        p += 2;
+      }
+      Edge e;
+      if (!expr(e, 1)) return false;
+      if (peek().kind != Tok::SEP && peek().kind != Tok::END)
+        return fail(FBG_E_PARSE, peek().pos, "unexpected token");
+      if (def) {
+        names[name] = e;
+      } else {
+        root = g.And(root, e);
+        nassert++;
+      }
+    }
+    if (nassert == 0) return fail(FBG_E_PARSE, 0, "no assertion in the formula");
+    return true;
+  }
+};
+
+// ---------------------------------------------------------------- codegen
+
+struct Codegen {
+  Graph &g;
+  std::vector<uint32_t> fanout;      // per node, parents among reachable nodes
+  std::vector<HIns> code;
+  std::unordered_map<uint32_t, int> stored;  // node -> virtual register
+  int nvregs = 0;
+
+  explicit Codegen(Graph &gr) : g(gr) {}
+
+  bool is_var(Edge e) const { return g.nodes[e >> 1].kind == NK_VAR; }
+  Lit lit_of(Edge e) const { return Lit{(int)g.nodes[e >> 1].a, (e & 1u) != 0}; }
+
+  // Reachable AND/XOR nodes and their fan-out (iterative DFS).
+  uint64_t analyse(Edge root) {
+    fanout.assign(g.nodes.size(), 0);
+    std::vector<uint8_t> seen(g.nodes.size(), 0);
+    std::vector<uint32_t> stack{root >> 1};
+    uint64_t gates = 0;
+    seen[root >> 1] = 1;
+    while (!stack.empty()) {
+      uint32_t v = stack.back();
+      stack.pop_back();
+      const GNode &nd = g.nodes[v];
+      if (nd.kind != NK_AND && nd.kind != NK_XOR) continue;
+      gates++;
+      for (uint32_t c : {nd.a >> 1, nd.b >> 1}) {
+        fanout[c]++;
+        if (!seen[c]) {
+          seen[c] = 1;
+          stack.push_back(c);
+        }
+      }
+    }
+    return gates;
+  }
+
+  // If edge e is an OR / AND / XOR of literals only, describe it as a
+  // literal set.  Flattening passes through shared nodes too: a literal set
+  // costs one instruction wherever it is used.
+  bool literal_set(Edge e, LitSet &ls) {
+    const GNode &top = g.nodes[e >> 1];
+    ls = LitSet();
+    if (top.kind == NK_VAR) {
+      ls.lits.push_back(lit_of(e));
+      return true;
+    }
+    if (top.kind == NK_AND) {
+      // e = AND(leaves) (possibly complemented); leaves through plain AND edges
+      std::vector<Edge> stack{top.a, top.b};
+      std::vector<Lit> leaves;
+      while (!stack.empty()) {
+        Edge c = stack.back();
+        stack.pop_back();
+        const GNode &nd = g.nodes[c >> 1];
+        if (nd.kind == NK_AND && !(c & 1u)) {
+          stack.push_back(nd.a);
+          stack.push_back(nd.b);
+        } else if (nd.kind == NK_VAR) {
+          leaves.push_back(lit_of(c));
+        } else {
+          return false;
+        }
+      }
+      // AND(l) = ~OR(~l); ~AND(l) = OR(~l)
+      for (Lit &l : leaves) l.neg = !l.neg;
+      ls.lits = leaves;
+      ls.inv = !(e & 1u);
+      return true;
+    }
+    if (top.kind == NK_XOR) {
+      std::vector<Edge> stack{top.a, top.b};
+      bool parity = (e & 1u) != 0;
+      std::vector<Lit> leaves;
+      while (!stack.empty()) {
+        Edge c = stack.back();
+        stack.pop_back();
+        const GNode &nd = g.nodes[c >> 1];
+        if (nd.kind == NK_XOR) {
+          parity ^= (c & 1u) != 0;
+          stack.push_back(nd.a);
+          stack.push_back(nd.b);
+        } else if (nd.kind == NK_VAR) {
+          leaves.push_back(Lit{(int)nd.a, false});
+          parity ^= (c & 1u) != 0;
+        } else {
+          return false;
+        }
+      }
+      ls.is_xor = true;
+      ls.lits = leaves;
+      ls.inv = parity;
+      return true;
+    }
+    return false;
+  }
+
+  void emit(const HIns &h) { code.push_back(h); }
+
+  // Invert cur: fold into the previous cur-writing instruction when possible.
+  void emit_not() {
+    if (!code.empty()) {
+      HIns &last = code.back();
+      if (last.op != FBG_OP_ST && last.op != FBG_OP_CL && last.op != FBG_OP_ACC) {
+        last.invout = !last.invout;
+        return;
+      }
+    }
+    HIns h;
+    h.op = FBG_OP_NOT;
+    emit(h);
+  }
+
+  // value of edge e into cur
+  void gen_edge(Edge e) {
+    LitSet ls;
+    if (literal_set(e, ls)) {
+      HIns h;
+      h.op = FBG_OP_LDL;
+      h.ls = ls;
+      emit(h);
+      return;
+    }
+    gen_node(e >> 1);
+    if (e & 1u) emit_not();
+  }
+
+  // Operand list of a node: flatten through single-use children of the same
+  // kind that are not already stored.
+  void operands(uint32_t v, std::vector<Edge> &ops, bool &parity) {
+    const GNode &top = g.nodes[v];
+    uint8_t kind = top.kind;
+    parity = false;
+    std::vector<Edge> stack{top.a, top.b};
+    while (!stack.empty()) {
+      Edge c = stack.back();
+      stack.pop_back();
+      uint32_t cn = c >> 1;
+      const GNode &nd = g.nodes[cn];
+      bool through = nd.kind == kind && fanout[cn] == 1 && !stored.count(cn);
+      if (kind == NK_AND) through = through && !(c & 1u);
+      if (through) {
+        if (kind == NK_XOR) parity ^= (c & 1u) != 0;
+        stack.push_back(nd.a);
+        stack.push_back(nd.b);
+      } else {
+        ops.push_back(c);
+      }
+    }
+    // duplicates: AND keeps one; XOR cancels pairs (x ^ x = 0, x ^ ~x = 1)
+    std::sort(ops.begin(), ops.end());
+    std::vector<Edge> out;
+    for (size_t i = 0; i < ops.size();) {
+      size_t j = i;
+      if (kind == NK_XOR) {
+        // group by node, ignoring complement
+        while (j < ops.size() && (ops[j] >> 1) == (ops[i] >> 1)) j++;
+        bool odd = ((j - i) & 1u) != 0;
+        bool par = false;
+        for (size_t q = i; q < j; q++) par ^= (ops[q] & 1u) != 0;
+        parity ^= par;
+        if (odd) out.push_back(ops[i] & ~1u);
+      } else {
+        while (j < ops.size() && ops[j] == ops[i]) j++;
+        out.push_back(ops[i]);
+      }
+      i = j;
+    }
+    ops.swap(out);
+  }
+
+  void gen_node(uint32_t v) {
+    auto it = stored.find(v);
+    if (it != stored.end()) {
+      HIns h;
+      h.op = FBG_OP_LDR;
+      h.reg = it->second;
+      emit(h);
+      return;
+    }
+    const GNode &nd = g.nodes[v];
+    bool is_and = nd.kind == NK_AND;
+    uint32_t f = is_and ? FBG_F_AND : FBG_F_XOR;
+    std::vector<Edge> ops;
+    bool parity = false;
+    operands(v, ops, parity);
+
+    // AND with x and ~x among the operands is false; the hashed graph folds
+    // direct pairs, flattening can still bring them together.
+    if (is_and) {
+      std::unordered_set<Edge> have(ops.begin(), ops.end());
+      for (Edge e : ops)
+        if (have.count(e ^ 1u)) {
+          HIns h;
+          h.op = FBG_OP_LDL;  // empty OR-set = 0
+          emit(h);
+          store_if_shared(v);
+          return;
+        }
+    }
+
+    std::vector<Lit> plain;
+    std::vector<LitSet> sets;
+    std::vector<Edge> general;
+    for (Edge e : ops) {
+      LitSet ls;
+      if (is_var(e)) {
+        plain.push_back(lit_of(e));
+      } else if (literal_set(e, ls)) {
+        sets.push_back(ls);
+      } else {
+        general.push_back(e);
+      }
+    }
+    if (!plain.empty()) {
+      LitSet ls;
+      if (is_and) {  // AND(l) = ~OR(~l)
+        for (Lit l : plain) ls.lits.push_back(Lit{l.k, !l.neg});
+        ls.inv = true;
+      } else {
+        ls.is_xor = true;
+        ls.lits = plain;
+      }
+      sets.insert(sets.begin(), ls);
+    }
+    // an XOR's parity goes into one of its XOR literal sets if it has one
+    if (!is_and && parity) {
+      for (LitSet &ls : sets)
+        if (ls.is_xor) {
+          ls.inv = !ls.inv;
+          parity = false;
+          break;
+        }
+    }
+    // Stored operands first (cheap register reads), then the others.
+    std::stable_sort(general.begin(), general.end(),
+                     [&](Edge a, Edge b) { return stored.count(a >> 1) > stored.count(b >> 1); });
+
+    bool have_cur = false;
+    if (!general.empty()) {
+      // start from a general operand that is not stored if there is one, so
+      // that stored ones combine through OPR without a reload
+      size_t first = 0;
+      for (size_t i = 0; i < general.size(); i++)
+        if (!stored.count(general[i] >> 1)) {
+          first = i;
+          break;
+        }
+      gen_edge(general[first]);
+      general.erase(general.begin() + (long)first);
+      have_cur = true;
+      for (Edge e : general) {
+        auto s = stored.find(e >> 1);
+        if (s != stored.end()) {
+          HIns h;
+          h.op = FBG_OP_OPR;
+          h.f = f;
+          h.reg = s->second;
+          h.inv = (e & 1u) != 0;
+          emit(h);
+        } else {
+          int t = nvregs++;
+          HIns st;
+          st.op = FBG_OP_ST;
+          st.reg = t;
+          emit(st);
+          gen_edge(e);
+          HIns h;
+          h.op = FBG_OP_OPR;
+          h.f = f;
+          h.reg = t;
+          emit(h);
+        }
+      }
+    }
+    for (const LitSet &ls : sets) {
+      HIns h;
+      h.ls = ls;
+      if (!have_cur) {
+        h.op = FBG_OP_LDL;
+        have_cur = true;
+      } else {
+        h.op = FBG_OP_OPL;
+        h.f = f;
+      }
+      emit(h);
+    }
+    if (!have_cur) {  // cannot happen for a hashed AND/XOR node
+      HIns h;
+      h.op = FBG_OP_LDL;
+      h.ls.inv = is_and;  // neutral element
+      emit(h);
+    }
+    if (parity) emit_not();
+    store_if_shared(v);
+  }
+
+  void store_if_shared(uint32_t v) {
+    if (fanout[v] > 1) {
+      int r = nvregs++;
+      HIns st;
+      st.op = FBG_OP_ST;
+      st.reg = r;
+      emit(st);
+      stored[v] = r;
+    }
+  }
+
+  void top(Edge root, int &n_clause) {
+    // conjuncts: flatten plain AND edges from the root through single-use nodes
+    std::vector<Edge> conj;
+    std::vector<Edge> stack{root};
+    while (!stack.empty()) {
+      Edge e = stack.back();
+      stack.pop_back();
+      const GNode &nd = g.nodes[e >> 1];
+      if (nd.kind == NK_AND && !(e & 1u) && (e == root || fanout[e >> 1] == 1)) {
+        stack.push_back(nd.b);
+        stack.push_back(nd.a);
+      } else {
+        conj.push_back(e);
+      }
+    }
+    std::unordered_set<Edge> seen;
+    std::vector<Edge> uniq;
+    for (Edge e : conj)
+      if (seen.insert(e).second) uniq.push_back(e);
+    for (Edge e : uniq)
+      if (seen.count(e ^ 1u)) {  // x & ~x
+        code.clear();
+        HIns h;
+        h.op = FBG_OP_CL;  // acc &= 0
+        emit(h);
+        n_clause = 1;
+        return;
+      }
+    // literal-set conjuncts first (they need no registers), then the rest
+    n_clause = 0;
+    std::vector<Edge> general;
+    for (Edge e : uniq) {
+      LitSet ls;
+      if (literal_set(e, ls)) {
+        HIns h;
+        h.ls = ls;
+        if (!ls.is_xor && !ls.inv) {  // a clause: one CL instruction
+          h.op = FBG_OP_CL;
+          emit(h);
+          n_clause++;
+        } else {  // XOR or AND of literals: through cur
+          h.op = FBG_OP_LDL;
+          emit(h);
+          HIns a;
+          a.op = FBG_OP_ACC;
+          emit(a);
+        }
+      } else {
+        general.push_back(e);
+      }
+    }
+    for (Edge e : general) {
+      gen_node(e >> 1);
+      HIns h;
+      h.op = FBG_OP_ACC;
+      h.inv = (e & 1u) != 0;
+      emit(h);
+    }
+  }
+};
+
+// Linear-scan allocation of virtual registers to the fewest physical ones.
+int allocate_registers(std::vector<HIns> &code, int nv) {
+  if (nv == 0) return 0;
+  std::vector<long> last(nv, -1);
+  for (long i = 0; i < (long)code.size(); i++) {
+    const HIns &h = code[i];
+    if ((h.op == FBG_OP_OPR || h.op == FBG_OP_LDR) && h.reg >= 0) last[h.reg] = i;
+  }
+  // drop stores that are never read
+  std::vector<HIns> kept;
+  std::vector<long> remap(code.size(), -1);
+  for (long i = 0; i < (long)code.size(); i++) {
+    if (code[i].op == FBG_OP_ST && last[code[i].reg] < 0) continue;
+    remap[i] = (long)kept.size();
+    kept.push_back(code[i]);
+  }
+  for (int r = 0; r < nv; r++)
+    if (last[r] >= 0) last[r] = remap[last[r]];
+  code.swap(kept);
+  std::vector<int> phys(nv, -1);
+  std::vector<int> free_list;
+  int used = 0;
+  for (long i = 0; i < (long)code.size(); i++) {
+    HIns &h = code[i];
+    if (h.op == FBG_OP_ST) {
+      int p;
+      if (!free_list.empty()) {
+        std::sort(free_list.begin(), free_list.end(), std::greater<int>());
+        p = free_list.back();
+        free_list.pop_back();
+      } else {
+        p = used++;
+      }
+      phys[h.reg] = p;
+      h.reg = p;
+    } else if (h.op == FBG_OP_OPR || h.op == FBG_OP_LDR) {
+      int v = h.reg;
+      h.reg = phys[v];
+      if (last[v] == i) free_list.push_back(phys[v]);
+    }
+  }
+  return used;
+}
+
+struct CompileJob {
+  const char *src;
+  int n;
+  Compiled *out;
+  std::string msg;
+  int64_t off = -1;
+  int status = FBG_OK;
+};
+
+void *compile_thread(void *arg) {
+  CompileJob *job = (CompileJob *)arg;
+  Graph g;
+  Parser ps(job->src, job->n, g);
+  Edge root;
+  if (!ps.program(root)) {
+    job->status = ps.status;
+    job->msg = ps.msg;
+    job->off = ps.off;
+    return nullptr;
+  }
+  Compiled &c = *job->out;
+  c = Compiled();
+  c.n = job->n;
+  if (root == kFalse || root == kTrue) {
+    c.const_value = root == kTrue ? 1 : 0;
+    if (root == kFalse) {
+      HIns h;
+      h.op = FBG_OP_CL;  // acc &= (empty OR-set) = 0
+      c.code.push_back(h);
+      c.n_clause_instr = 1;
+    }
+    return nullptr;
+  }
+  Codegen cg(g);
+  c.l2in = cg.analyse(root);
+  cg.top(root, c.n_clause_instr);
+  c.code.swap(cg.code);
+  c.nregs = allocate_registers(c.code, cg.nvregs);
+  return nullptr;
+}
+
+}  // namespace
+
+int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset) {
+  CompileJob job;
+  job.src = src;
+  job.n = n;
+  job.out = &out;
+  // Deeply nested text recurses in the parser and code generator; give the
+  // work a large stack of its own.
+  pthread_attr_t attr;
+  pthread_attr_init(&attr);
+  pthread_attr_setstacksize(&attr, (size_t)512 << 20);
+  pthread_t th;
+  if (pthread_create(&th, &attr, compile_thread, &job) != 0) {
+    pthread_attr_destroy(&attr);
+    compile_thread(&job);
+  } else {
+    pthread_join(th, nullptr);
+    pthread_attr_destroy(&attr);
+  }
+  msg = job.msg;
+  offset = job.off;
+  return job.status;
+}
+
+// ---------------------------------------------------------------- encoding
+
+namespace {
+
+struct SetWords {
+  uint32_t flags = 0, pat = 0, mconst = 0;
+  uint64_t lanemask = 0, sel = 0, neg = 0;
+};
+
+SetWords encode_set(const LitSet &ls, int log2w) {
+  SetWords s;
+  const int W = 1 << log2w;
+  const int tile_bit = FBG_TILE_BASE_BIT + log2w;
+  bool taut = false;
+  for (const Lit &l : ls.lits) {
+    uint32_t negmask = l.neg ? ~0u : 0u;
+    if (l.k < FBG_SLICE_BITS) {
+      uint32_t m = fbg_inword_mask(l.k) ^ negmask;
+      if (ls.is_xor) s.mconst ^= m; else s.mconst |= m;
+    } else if (l.k < FBG_TILE_BASE_BIT) {
+      uint64_t m = 0;
+      for (int lane = 0; lane < 64; lane++)
+        if ((((unsigned)lane >> (l.k - FBG_SLICE_BITS)) & 1u) ^ (l.neg ? 1u : 0u)) m |= 1ull << lane;
+      if (ls.is_xor) s.lanemask ^= m; else s.lanemask |= m;
+    } else if (l.k < tile_bit) {
+      uint32_t m = 0;
+      for (int i = 0; i < W; i++)
+        if ((((unsigned)i >> (l.k - FBG_TILE_BASE_BIT)) & 1u) ^ (l.neg ? 1u : 0u)) m |= 1u << i;
+      if (ls.is_xor) s.pat ^= m; else s.pat |= m;
+    } else {
+      uint64_t b = 1ull << (l.k - FBG_TILE_BASE_BIT);
+      if (ls.is_xor) {
+        s.sel ^= b;
+        if (l.neg) s.mconst ^= ~0u;
+      } else if (s.sel & b) {
+        if (((s.neg & b) != 0) != l.neg) taut = true;
+      } else {
+        s.sel |= b;
+        if (l.neg) s.neg |= b;
+      }
+    }
+  }
+  if (taut) s.mconst = ~0u;
+  if (ls.is_xor) {
+    s.flags |= FBG_XORSET;
+    if (ls.inv) s.mconst ^= ~0u;
+  } else if (ls.inv) {
+    s.flags |= FBG_INV;
+  }
+  if (s.lanemask) s.flags |= FBG_HASLANE;
+  return s;
+}
+
+}  // namespace
+
+uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words) {
+  const size_t base = words.size();
+  const int W = 1 << log2w;
+  std::vector<uint32_t> pats{0u};  // pattern table, entry 0 = no per-word literal
+  for (const HIns &h : c.code) {
+    uint32_t w[FBG_INS_WORDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    w[0] = h.op;
+    if (h.op == FBG_OP_CL || h.op == FBG_OP_LDL || h.op == FBG_OP_OPL) {
+      SetWords s = encode_set(h.ls, log2w);
+      // CL carries plain OR-sets only (the kernel's clause loop relies on it)
+      if (h.op == FBG_OP_CL) {
+        s.flags &= ~(uint32_t)(FBG_XORSET | FBG_INV);
+        size_t e = 0;
+        while (e < pats.size() && pats[e] != s.pat) e++;
+        if (e == pats.size()) pats.push_back(s.pat);
+        w[0] |= (uint32_t)e << FBG_F_SHIFT;  // at most 81 entries
+      }
+      w[0] |= s.flags | (s.pat << FBG_ARG_SHIFT);
+      w[1] = s.mconst;
+      w[2] = (uint32_t)s.lanemask;
+      w[3] = (uint32_t)(s.lanemask >> 32);
+      w[4] = (uint32_t)s.sel;
+      w[5] = (uint32_t)(s.sel >> 32);
+      w[6] = (uint32_t)s.neg;
+      w[7] = (uint32_t)(s.neg >> 32);
+    } else {
+      if (h.inv) w[0] |= FBG_INV;
+      if (h.reg >= 0) w[0] |= (uint32_t)h.reg << FBG_ARG_SHIFT;
+    }
+    if (h.op == FBG_OP_OPL || h.op == FBG_OP_OPR) w[0] |= h.f << FBG_F_SHIFT;
+    if (h.invout) w[0] |= FBG_INVOUT;
+    words.insert(words.end(), w, w + FBG_INS_WORDS);
+  }
+  const uint32_t nins = (uint32_t)((words.size() - base) / FBG_INS_WORDS);
+  for (uint32_t pat : pats)
+    for (int i = 0; i < W; i++) words.push_back(((pat >> i) & 1u) ? ~0u : 0u);
+  return nins;
+}
+
+std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
+  static const char *ops[] = {"?", "CL", "LDL", "OPL", "ST", "OPR", "ACC", "LDR", "NOT"};
+  static const char *fs[] = {"and", "or", "xor", "?"};
+  std::string out = "; words per lane " + std::to_string(1 << log2w) + "\n";
+  char buf[256];
+  for (size_t pc = 0; pc < (size_t)nins * FBG_INS_WORDS; pc += FBG_INS_WORDS) {
+    const uint32_t *w = &words[pc];
+    uint32_t op = w[0] & 15u;
+    uint32_t arg = w[0] >> FBG_ARG_SHIFT;
+    const char *name = op <= 8 ? ops[op] : "?";
+    if (op == FBG_OP_CL || op == FBG_OP_LDL || op == FBG_OP_OPL) {
+      snprintf(buf, sizeof buf,
+               "%4zu %-3s %s%s%s set=%s%s mconst=%08x lane=%08x%08x pat=%04x sel=%08x%08x neg=%08x%08x\n",
+               pc / FBG_INS_WORDS, name, op == FBG_OP_OPL ? fs[(w[0] >> FBG_F_SHIFT) & 3u] : "",
+               (w[0] & FBG_INVOUT) ? " invout" : "", "", (w[0] & FBG_XORSET) ? "xor" : "or",
+               (w[0] & FBG_INV) ? " inv" : "", w[1], w[3], w[2], arg, w[5], w[4], w[7], w[6]);
+    } else {
+      snprintf(buf, sizeof buf, "%4zu %-3s %s r%u%s%s\n", pc / FBG_INS_WORDS, name,
+               op == FBG_OP_OPR ? fs[(w[0] >> FBG_F_SHIFT) & 3u] : "", arg, (w[0] & FBG_INV) ? " inv" : "",
+               (w[0] & FBG_INVOUT) ? " invout" : "");
+    }
+    out += buf;
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------- emulator
+
+namespace {
+
+inline uint32_t set_value(const uint32_t *w, uint32_t lane, uint32_t i, uint64_t U0) {
+  bool x = (w[0] & FBG_XORSET) != 0;
+  uint64_t lanemask = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+  uint64_t sel = (uint64_t)w[4] | ((uint64_t)w[5] << 32);
+  uint64_t neg = (uint64_t)w[6] | ((uint64_t)w[7] << 32);
+  uint32_t pat = w[0] >> FBG_ARG_SHIFT;
+  uint32_t V = ((lanemask >> lane) & 1u) ? ~0u : 0u;
+  uint32_t P = ((pat >> i) & 1u) ? ~0u : 0u;
+  uint32_t Q;
+  if (x)
+    Q = (__builtin_popcountll(U0 & sel) & 1) ? ~0u : 0u;
+  else
+    Q = ((U0 ^ neg) & sel) ? ~0u : 0u;
+  uint32_t L = x ? (w[1] ^ V ^ P ^ Q) : (w[1] | V | P | Q);
+  if (w[0] & FBG_INV) L = ~L;
+  return L;
+}
+
+inline uint32_t apply_f(uint32_t f, uint32_t a, uint32_t b) {
+  return f == FBG_F_AND ? (a & b) : f == FBG_F_OR ? (a | b) : (a ^ b);
+}
+
+}  // namespace
+
+void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nregs, int n, int log2w,
+                     uint32_t *out32) {
+  const uint64_t slices = n >= FBG_SLICE_BITS ? (1ull << (n - FBG_SLICE_BITS)) : 1ull;
+  const uint64_t W = 1ull << log2w;
+  std::vector<uint32_t> R((size_t)nregs + 1, 0);
+  const uint32_t *table = words.data() + (size_t)nins * FBG_INS_WORDS;
+  for (uint64_t s = 0; s < slices; s++) {
+    uint32_t lane = (uint32_t)(s & 63u);
+    uint64_t U = s >> FBG_LANE_BITS;
+    uint32_t i = (uint32_t)(U & (W - 1));
+    uint64_t U0 = U - i;
+    uint32_t acc = ~0u, cur = 0;
+    for (size_t pc = 0; pc < nins; pc++) {
+      const uint32_t *w = &words[pc * FBG_INS_WORDS];
+      uint32_t op = w[0] & 15u;
+      uint32_t f = (w[0] >> FBG_F_SHIFT) & 3u;
+      uint32_t arg = w[0] >> FBG_ARG_SHIFT;
+      uint32_t inv = (w[0] & FBG_INV) ? ~0u : 0u;
+      switch (op) {
+        case FBG_OP_CL: {
+          // as the kernel reads it: P(i) from the pattern table, the rest
+          // from the instruction (pat cleared)
+          uint32_t wc[FBG_INS_WORDS];
+          for (int q = 0; q < FBG_INS_WORDS; q++) wc[q] = w[q];
+          wc[0] &= 0xFFFFu;
+          const uint32_t e = (w[0] >> FBG_F_SHIFT) & 0xFFu;
+          acc &= set_value(wc, lane, i, U0) | table[(size_t)e * W + i];
+          break;
+        }
+        case FBG_OP_LDL: cur = set_value(w, lane, i, U0); break;
+        case FBG_OP_OPL: cur = apply_f(f, cur, set_value(w, lane, i, U0)); break;
+        case FBG_OP_ST: R[arg] = cur; break;
+        case FBG_OP_OPR: cur = apply_f(f, cur, R[arg] ^ inv); break;
+        case FBG_OP_ACC: acc &= cur ^ inv; break;
+        case FBG_OP_LDR: cur = R[arg] ^ inv; break;
+        case FBG_OP_NOT: cur = ~cur; break;
+      }
+      if (w[0] & FBG_INVOUT) cur = ~cur;
+    }
+    if (n < FBG_SLICE_BITS) acc &= (uint32_t)((1ull << (1u << n)) - 1u);
+    out32[s] = acc;
+  }
+  if (n < 6) {
+    // the DNF has one 64-bit word: clear the upper slice if it is not valid
+    if (slices < 2) out32[1] = 0;
+  }
+}
+
+}  // namespace fbg

@@ -1,0 +1,65 @@
+// fbg_internal.h -- host-side structures shared by the compiler, the runtime
+// and the C ABI.  Not installed; the public interface is include/fbg.h.
+#ifndef FBG_INTERNAL_H
+#define FBG_INTERNAL_H
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fbg_isa.h"
+
+namespace fbg {
+
+// A literal: variable k, complemented or not.
+struct Lit {
+  int k;
+  bool neg;
+};
+
+// OR (or XOR) of literals, optionally inverted.
+struct LitSet {
+  bool is_xor = false;
+  bool inv = false;
+  std::vector<Lit> lits;
+};
+
+// Host form of one device instruction, before the words-per-lane dependent
+// encoding.  Registers are virtual until allocation, physical after.
+struct HIns {
+  uint32_t op = 0;
+  LitSet ls;          // CL, LDL, OPL
+  uint32_t f = 0;     // OPL, OPR
+  int reg = -1;       // ST, OPR, LDR
+  bool inv = false;   // OPR, ACC, LDR (the register / cur operand inverted)
+  bool invout = false;
+};
+
+struct Compiled {
+  int n = 0;
+  int const_value = -1;   // -1, or 0/1 when the formula folded to a constant
+  uint64_t l2in = 0;      // AND/XOR nodes reachable from the root
+  int nregs = 0;
+  int n_clause_instr = 0;
+  std::vector<HIns> code;
+};
+
+// Parse and compile.  Returns 0, or an fbg_status with msg / offset set.
+int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset);
+
+// Encode for words-per-lane 2^log2w (W <= 16).  Appends FBG_INS_WORDS words
+// per instruction, then the pattern table; returns the instruction count.
+uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words);
+
+// Listing of an encoded program.
+std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w);
+
+// Host interpretation of an encoded program, slice by slice (debug aid).
+// Writes 2^max(n-5,0) 32-bit slices into out32 (zeroed tail for n < 5).
+void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nregs, int n, int log2w,
+                     uint32_t *out32);
+
+}  // namespace fbg
+
+#endif

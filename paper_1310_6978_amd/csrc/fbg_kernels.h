@@ -1,0 +1,65 @@
+// fbg_kernels.h -- kernel argument blocks and launch wrappers (host side).
+#ifndef FBG_KERNELS_H
+#define FBG_KERNELS_H
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace fbg {
+
+struct EvalArgs {
+  const uint32_t *code;   // encoded program, FBG_INS_WORDS words per instruction
+  uint32_t nins;
+  uint32_t nregs;         // LDS registers per word
+  int32_t n;              // variables
+  int32_t pad0;
+  uint64_t nslices;       // 2^max(n-5, 0) valid 32-bit words
+  uint64_t ntiles;        // ceil(nslices / (64 W))
+  uint64_t *out_count;    // MODE_COUNT
+  uint32_t *out32;        // MODE_DNF
+  uint64_t out_slices;    // MODE_DNF: words written (>= nslices, >= 2)
+  uint32_t *tile_counts;  // MODE_TILECNT (out), MODE_ENUM (in)
+  const uint64_t *tile_offsets;  // MODE_ENUM
+  uint64_t *out_idx;      // MODE_ENUM
+  uint64_t capacity;      // MODE_ENUM
+};
+
+struct BatchProg {
+  const uint32_t *code;
+  uint32_t nins;
+  uint32_t nregs;
+  int32_t n;
+  int32_t pad0;
+  uint64_t nslices;
+  uint64_t ntiles;
+};
+
+struct BatchItem {
+  uint32_t prog;
+  uint32_t pad0;
+  uint64_t t0, t1;  // tile range [t0, t1)
+};
+
+struct BatchArgs {
+  const BatchProg *progs;
+  const BatchItem *items;
+  uint32_t nitems;
+  uint32_t max_regs;
+  uint32_t *head;     // queue head, zeroed before the launch
+  uint64_t *counts;   // per program, zeroed before the launch
+};
+
+enum { EVAL_COUNT = 0, EVAL_DNF = 1, EVAL_TILECNT = 2, EVAL_ENUM = 3 };
+
+hipError_t launch_eval(int mode, int log2w, const EvalArgs &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_batch(int log2w, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
+                       hipStream_t s);
+uint64_t scan_block_count(uint64_t n);
+hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, hipStream_t s);
+hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
+hipError_t launch_fill_words(uint64_t *p, uint64_t n, uint64_t v, uint64_t last, hipStream_t s);
+
+}  // namespace fbg
+
+#endif

@@ -1,0 +1,258 @@
+"""ctypes binding of libfbg (include/fbg.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current HIP device (int64
+storage, read back as uint64), streams are torch streams.  If libfbg.so has
+not been built, importing this module raises: there is no fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfbg.so")
+
+FBG_OK = 0
+FBG_E_INVAL = -1
+FBG_E_PARSE = -2
+FBG_E_RANGE = -3
+FBG_E_NOMEM = -4
+FBG_E_DEVICE = -5
+_STATUS = {0: "FBG_OK", -1: "FBG_E_INVAL", -2: "FBG_E_PARSE", -3: "FBG_E_RANGE",
+           -4: "FBG_E_NOMEM", -5: "FBG_E_DEVICE"}
+
+MAX_VARS = 48
+MAX_DNF_VARS = 40
+MAX_WORDS_PER_LANE = 16
+
+
+class FbgError(RuntimeError):
+    def __init__(self, status, message, offset=-1):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+        self.offset = offset
+
+
+class ProgramInfo(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("const_value", ctypes.c_int32), ("l2in", ctypes.c_uint64),
+                ("n_instr", ctypes.c_int32), ("n_regs", ctypes.c_int32), ("n_clause_instr", ctypes.c_int32),
+                ("words_per_lane", ctypes.c_int32), ("dnf_words", ctypes.c_uint64)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("words_per_lane", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfbg.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_1310_6978_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    sigs = {
+        "fbg_compile": (i32, [ctypes.c_char_p, i32, u32, ctypes.POINTER(vp)]),
+        "fbg_program_free": (None, [vp]),
+        "fbg_program_get_info": (i32, [vp, ctypes.POINTER(ProgramInfo)]),
+        "fbg_eval_dnf": (i32, [vp, vp, u64, vp]),
+        "fbg_eval_dnf_tuned": (i32, [vp, vp, u64, ctypes.POINTER(Tune), vp]),
+        "fbg_count": (i32, [vp, vp, vp]),
+        "fbg_count_tuned": (i32, [vp, vp, ctypes.POINTER(Tune), vp]),
+        "fbg_enumerate": (i32, [vp, vp, u64, vp, vp]),
+        "fbg_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(Tune), ctypes.POINTER(vp)]),
+        "fbg_batch_count": (i32, [vp, vp, vp]),
+        "fbg_batch_free": (None, [vp]),
+        "fbg_count_batch": (i32, [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(Tune), vp]),
+        "fbg_program_emulate": (i32, [vp, i32, u64p, u64, u64p]),
+        "fbg_program_disasm": (ctypes.c_int64, [vp, i32, ctypes.c_char_p, ctypes.c_int64]),
+        "fbg_last_error": (ctypes.c_char_p, []),
+        "fbg_last_error_offset": (ctypes.c_int64, []),
+        "fbg_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+# every symbol include/fbg.h declares
+EXPORTED = ("fbg_compile", "fbg_program_free", "fbg_program_get_info", "fbg_eval_dnf", "fbg_eval_dnf_tuned",
+            "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_batch_create", "fbg_batch_count",
+            "fbg_batch_free", "fbg_count_batch", "fbg_program_emulate", "fbg_program_disasm", "fbg_last_error",
+            "fbg_last_error_offset", "fbg_version")
+
+
+def _check(st):
+    if st != FBG_OK:
+        raise FbgError(st, lib.fbg_last_error().decode(errors="replace"), lib.fbg_last_error_offset())
+
+
+def _tune(words_per_lane=0, grid_blocks=0):
+    if not words_per_lane and not grid_blocks:
+        return None
+    return ctypes.byref(Tune(int(words_per_lane), int(grid_blocks), 0, 0))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _device_u64(nelem, like=None):
+    import torch
+    return torch.empty(max(int(nelem), 1), dtype=torch.int64, device="cuda")
+
+
+def as_u64(t):
+    """Device or host int64 tensor -> numpy uint64 array (host copy)."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def dnf_words(n):
+    return 1 if n < 6 else 1 << (n - 6)
+
+
+class Program:
+    """A compiled formula, resident on the device it was compiled on."""
+
+    def __init__(self, src, n, flags=0):
+        h = ctypes.c_void_p()
+        if isinstance(src, str):
+            src = src.encode()
+        _check(lib.fbg_compile(src, int(n), int(flags), ctypes.byref(h)))
+        self._h = h
+        self.n = int(n)
+        info = ProgramInfo()
+        _check(lib.fbg_program_get_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in ProgramInfo._fields_}
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise FbgError(FBG_E_INVAL, "program was freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            lib.fbg_program_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def emulate(self, words_per_lane=1):
+        """Host interpretation of the encoded program: (dnf uint64 array, count)."""
+        out = np.zeros(dnf_words(self.n), dtype=np.uint64)
+        cnt = ctypes.c_uint64(0)
+        _check(lib.fbg_program_emulate(self.handle, int(words_per_lane),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size,
+                                       ctypes.byref(cnt)))
+        return out, cnt.value
+
+    def disasm(self, words_per_lane=0):
+        size = lib.fbg_program_disasm(self.handle, int(words_per_lane), None, 0)
+        buf = ctypes.create_string_buffer(int(size) + 1)
+        lib.fbg_program_disasm(self.handle, int(words_per_lane), buf, int(size) + 1)
+        return buf.value.decode()
+
+
+def compile(src, n, flags=0):  # noqa: A001 - the boundary's name
+    return Program(src, n, flags)
+
+
+def eval_dnf(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0):
+    """fbg_eval_dnf: the DNF vector as an int64 device tensor of uint64 words."""
+    words = dnf_words(prog.n)
+    if out is None:
+        out = _device_u64(words)
+    tune = _tune(words_per_lane, grid_blocks)
+    if tune is None:
+        _check(lib.fbg_eval_dnf(prog.handle, _ptr(out), out.numel(), _stream(stream)))
+    else:
+        _check(lib.fbg_eval_dnf_tuned(prog.handle, _ptr(out), out.numel(), tune, _stream(stream)))
+    return out
+
+
+def count(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0):
+    """fbg_count: one-element int64 device tensor holding the model count."""
+    if out is None:
+        out = _device_u64(1)
+    tune = _tune(words_per_lane, grid_blocks)
+    if tune is None:
+        _check(lib.fbg_count(prog.handle, _ptr(out), _stream(stream)))
+    else:
+        _check(lib.fbg_count_tuned(prog.handle, _ptr(out), tune, _stream(stream)))
+    return out
+
+
+def enumerate_models(prog, capacity, out=None, total=None, stream=None):
+    """fbg_enumerate: (device tensor of the first min(total, capacity) model
+    indices, ascending; one-element device tensor with the total)."""
+    if out is None:
+        out = _device_u64(capacity)
+    if total is None:
+        total = _device_u64(1)
+    ptr = _ptr(out) if capacity > 0 else ctypes.c_void_p(0)
+    _check(lib.fbg_enumerate(prog.handle, ptr, int(capacity), _ptr(total), _stream(stream)))
+    return out, total
+
+
+class Batch:
+    """A work plan for counting many programs in one persistent launch."""
+
+    def __init__(self, progs, words_per_lane=0, grid_blocks=0):
+        self._progs = list(progs)  # keep the programs alive
+        arr = (ctypes.c_void_p * len(self._progs))(*[p.handle.value for p in self._progs])
+        h = ctypes.c_void_p()
+        _check(lib.fbg_batch_create(arr, len(self._progs), _tune(words_per_lane, grid_blocks), ctypes.byref(h)))
+        self._h = h
+
+    def __len__(self):
+        return len(self._progs)
+
+    def count(self, out=None, stream=None):
+        if out is None:
+            out = _device_u64(len(self._progs))
+        _check(lib.fbg_batch_count(self._h, _ptr(out), _stream(stream)))
+        return out
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            lib.fbg_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def count_batch(progs, out=None, stream=None, words_per_lane=0, grid_blocks=0):
+    """fbg_count_batch: counts of all programs (one persistent launch)."""
+    progs = list(progs)
+    if out is None:
+        out = _device_u64(len(progs))
+    arr = (ctypes.c_void_p * len(progs))(*[p.handle.value for p in progs])
+    _check(lib.fbg_count_batch(arr, len(progs), _ptr(out), _tune(words_per_lane, grid_blocks),
+                               _stream(stream)))
+    return out
+
+
+def version():
+    return lib.fbg_version().decode()

@@ -1,0 +1,55 @@
+"""The C-ABI library loads and exports every symbol include/fbg.h declares;
+calls that need a device fail loudly without one."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1310_6978_amd import fbg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "fbg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fbg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(fbg.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(fbg.EXPORTED)
+
+
+def test_version():
+    assert "gfx950" in fbg.version()
+
+
+def test_library_is_the_in_tree_build():
+    assert os.path.dirname(fbg.LIB_PATH) == os.path.join(ROOT, "paper_1310_6978_amd")
+
+
+def test_device_calls_fail_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = fbg.Program("x0 | x1", 4)
+    st = fbg.lib.fbg_count(p.handle, ctypes.c_void_p(8), ctypes.c_void_p(0))
+    assert st == fbg.FBG_E_DEVICE
+    assert "without a HIP device" in fbg.lib.fbg_last_error().decode()
+
+
+def test_null_arguments():
+    assert fbg.lib.fbg_count(None, None, None) == fbg.FBG_E_INVAL
+    assert fbg.lib.fbg_program_get_info(None, None) == fbg.FBG_E_INVAL
+    out = ctypes.c_void_p()
+    assert fbg.lib.fbg_compile(None, 3, 0, ctypes.byref(out)) == fbg.FBG_E_INVAL
+    assert fbg.lib.fbg_compile(b"x0", 3, 7, ctypes.byref(out)) == fbg.FBG_E_INVAL
+    fbg.lib.fbg_program_free(None)
+    fbg.lib.fbg_batch_free(None)

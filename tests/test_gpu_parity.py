@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact throughout: DNF words, counts and model lists are integers.  Small
+cases compare every element with the oracle; full-size cases compare against
+stored oracle results (tests/golden, written by make_golden.py) and check
+sampled DNF words and every enumerated model with the oracle one valuation
+at a time.
+"""
+
+import hashlib
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.formula_gen import random_cnf, random_program
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+WPL = [1, 2, 4, 8, 16]
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1310_6978_amd import fbg
+    return fbg
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip("golden file %s not generated" % name)
+    with open(path) as f:
+        return json.load(f)
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def gpu_dnf(F, p, wpl=0):
+    return host(F.eval_dnf(p, words_per_lane=wpl))
+
+
+def gpu_count(F, p, wpl=0):
+    return int(host(F.count(p, words_per_lane=wpl))[0])
+
+
+def gpu_models(F, p, cap):
+    idx, tot = F.enumerate_models(p, cap)
+    return host(idx)[:cap].copy(), int(host(tot)[0])
+
+
+def full_check(F, text, n, wpls=WPL):
+    """DNF, count and models for every tiling against the oracle."""
+    want = oracle.dnf(text, n)
+    want_models, total = oracle.models(text, n)
+    p = F.Program(text, n)
+    for w in wpls:
+        got = gpu_dnf(F, p, w)
+        assert np.array_equal(got, want), ("dnf", w, n)
+        assert gpu_count(F, p, w) == total, ("count", w, n)
+    m, t = gpu_models(F, p, max(total, 1))
+    assert t == total
+    assert np.array_equal(m[:total], want_models)
+    return p
+
+
+def test_generators_are_the_rows_of_M(F):
+    # Section 2.2: bit mu of generator k is bit k of mu
+    for n in range(0, 13):
+        for k in range(n):
+            p = F.Program("x%d" % k, n)
+            assert np.array_equal(gpu_dnf(F, p), oracle.dnf("x%d" % k, n)), (n, k)
+
+
+def test_small_n_tails(F):
+    for n in range(0, 8):
+        for text in ("1", "0", "x0" if n else "1", "~x%d" % (n - 1) if n else "0"):
+            full_check(F, text, n)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_formulas(F, seed):
+    rng = random.Random(500 + seed)
+    n = rng.choice([3, 6, 9, 12, 14, 16, 17, 18, 20])
+    _, text = random_program(rng, n)
+    full_check(F, text, n)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_cnf_several_tiles(F, seed):
+    rng = random.Random(700 + seed)
+    n = rng.choice([18, 19, 20, 21])
+    full_check(F, random_cnf(rng, n, rng.randrange(4, 30)), n)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_dags(F, seed):
+    rng = random.Random(900 + seed)
+    n = rng.choice([10, 14, 18, 20])
+    text, n = workloads.random_dag(n, rng.randrange(50, 2000), seed)
+    full_check(F, text, n)
+
+
+def test_baequ4(F):
+    text, n = workloads.baequ4()
+    p = full_check(F, text, n)
+    m, t = gpu_models(F, p, 8)
+    assert t == 3 and m[:t].tolist() == [0, 9, 15]
+
+
+def test_c0_equivalence_k6(F):
+    g = golden("c0_equivalence_k6.json")
+    text, n = workloads.equivalence_relations(6)
+    p = F.Program(text, n)
+    want = np.array([int(h, 16) for h in g["dnf_words_hex"]], dtype=np.uint64)
+    for w in WPL:
+        assert np.array_equal(gpu_dnf(F, p, w), want)
+        assert gpu_count(F, p, w) == 203
+    m, t = gpu_models(F, p, 1000)
+    assert t == 203 and m[:203].tolist() == g["models"]
+
+
+def test_c2b_permutations(F):
+    g = golden("c2_theories.json")["permutations_k5"]
+    text, n = workloads.permutation_matrices(5)
+    p = F.Program(text, n)
+    assert gpu_count(F, p) == 120 == g["count"]
+    m, t = gpu_models(F, p, 200)
+    assert t == 120 and m[:120].tolist() == g["models"]
+
+
+def test_c2c_triangle_free(F):
+    g = golden("c2_theories.json")["triangle_free_k8"]
+    text, n = workloads.triangle_free(8)
+    p = F.Program(text, n)
+    assert gpu_count(F, p) == 4682270 == g["count"]
+    m, t = gpu_models(F, p, 4682270)
+    assert t == 4682270
+    assert hashlib.sha256(m.astype("<u8").tobytes()).hexdigest() == g["models_sha256"]
+    d = gpu_dnf(F, p)
+    assert int(np.unpackbits(d.view(np.uint8)).sum()) == 4682270
+    # every set bit of the DNF is a model and vice versa
+    bits = np.flatnonzero(np.unpackbits(d.view(np.uint8), bitorder="little"))
+    assert np.array_equal(bits.astype(np.uint64), m)
+
+
+def test_c2a_equivalence_k9(F):
+    text, n = workloads.equivalence_relations(9)
+    p = F.Program(text, n)
+    assert gpu_count(F, p) == 21147  # Bell number B_9
+    m, t = gpu_models(F, p, 30000)
+    assert t == 21147
+    m = m[:t]
+    assert np.all(np.diff(m.astype(np.int64)) > 0)
+    assert np.all(oracle.eval_at(text, n, m) == 1)
+    g = golden("c2_theories.json").get("equivalence_k9")
+    if g:
+        assert m.tolist() == g["models"]
+
+
+def test_c1_random_3cnf_counts_and_models(F):
+    g = golden("c1_3cnf_n32.json")
+    for s, rec in sorted(g["seeds"].items(), key=lambda kv: int(kv[0])):
+        text, n = workloads.random_3cnf(32, 136, int(s))
+        p = F.Program(text, n)
+        assert gpu_count(F, p) == rec["count"], s
+        m, t = gpu_models(F, p, 4096)
+        assert t == rec["count"]
+        assert m[:t].tolist() == rec["models"]
+
+
+def test_c1_dnf_sampled_words(F):
+    import torch
+    text, n = workloads.random_3cnf(32, 136, 0)
+    p = F.Program(text, n)
+    d = F.eval_dnf(p)
+    rng = np.random.default_rng(1)
+    words = np.sort(rng.choice(d.numel(), 256, replace=False))
+    sample = d[torch.from_numpy(words.astype(np.int64)).cuda()].cpu().numpy().view(np.uint64)
+    idx = (words[:, None].astype(np.uint64) * 64 + np.arange(64, dtype=np.uint64)[None, :]).ravel()
+    bits = oracle.eval_at(text, n, idx).reshape(-1, 64)
+    want = (bits.astype(np.uint64) << np.arange(64, dtype=np.uint64)[None, :]).sum(axis=1).astype(np.uint64)
+    assert np.array_equal(sample, want)
+    assert gpu_count(F, p) == oracle_count_golden(0)
+
+
+def oracle_count_golden(seed):
+    path = os.path.join(GOLDEN, "c1_3cnf_n32.json")
+    if not os.path.exists(path):
+        pytest.skip("c1 golden not generated")
+    with open(path) as f:
+        return json.load(f)["seeds"][str(seed)]["count"]
+
+
+def test_enumerate_truncation(F):
+    text, n = workloads.triangle_free(6)
+    want, total = oracle.models(text, n)
+    p = F.Program(text, n)
+    for cap in (0, 1, 7, 100, total - 1, total, total + 5):
+        m, t = gpu_models(F, p, cap)
+        assert t == total
+        assert np.array_equal(m[:min(cap, total)], want[:min(cap, total)])
+
+
+def test_determinism(F):
+    text, n = workloads.random_3cnf(24, 102, 3)
+    p = F.Program(text, n)
+    a, b = gpu_dnf(F, p), gpu_dnf(F, p)
+    assert np.array_equal(a, b)
+    assert gpu_count(F, p) == gpu_count(F, p) == oracle.count(text, n)
+
+
+def test_batch_equals_solo_and_oracle(F):
+    rng = random.Random(42)
+    progs, want = [], []
+    for i in range(40):
+        n = rng.choice([4, 9, 12, 15, 18, 20, 22])
+        if i % 3 == 0:
+            text, n = workloads.random_dag(n, rng.randrange(50, 800), i)
+        else:
+            text = random_cnf(rng, n, rng.randrange(1, 30))
+        progs.append(F.Program(text, n))
+        want.append(oracle.count(text, n))
+    for wpl in (0, 1, 4, 16):
+        got = host(F.count_batch(progs, words_per_lane=wpl))
+        assert got.tolist() == want, wpl
+    b = F.Batch(progs)
+    for _ in range(3):
+        assert host(b.count()).tolist() == want
+    solo = [gpu_count(F, p) for p in progs]
+    assert solo == want
+
+
+def test_argument_errors(F):
+    import torch
+    p = F.Program("x0 | x9", 12)
+    small = torch.empty(3, dtype=torch.int64, device="cuda")
+    with pytest.raises(F.FbgError) as ei:
+        F.eval_dnf(p, out=small)
+    assert ei.value.status == F.FBG_E_INVAL
+    with pytest.raises(F.FbgError):
+        F.count(p, words_per_lane=3)
+    big = F.Program("x40", 41)
+    with pytest.raises(F.FbgError) as ei:
+        F.eval_dnf(big, out=small)
+    assert ei.value.status == F.FBG_E_RANGE

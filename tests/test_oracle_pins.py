@@ -441,3 +441,13 @@ def test_parse_errors(bad):
 def test_variable_out_of_range():
     with pytest.raises(oracle.OracleError):
         oracle.count("x5", 5)
+
+
+def test_count_range_partitions_the_count():
+    text, n = workloads.random_3cnf(16, 50, 2)
+    total = oracle.count(text, n)
+    cuts = [0, 1, 63, 64, 1000, 4097, 30000, 1 << n]
+    parts = sum(oracle.count_range(text, n, a, b) for a, b in zip(cuts, cuts[1:]))
+    assert parts == total
+    want = oracle.models(text, n)[0]
+    assert oracle.count_range(text, n, 1000, 30000) == int(((want >= 1000) & (want < 30000)).sum())
