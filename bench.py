@@ -10,8 +10,9 @@ programs resident on the device:
   * compile       residency lookup of the 16 compiled programs
   * count         one persistent batched launch over all 16 programs
                   (generator synthesis, evaluation, popcount reduction)
-  * enumerate     ascending model indices of every instance
   * DNF           the 2^32-bit DNF vector of every instance (512 MiB each)
+  * enumerate     ascending model indices of every instance, read off its
+                  stored DNF vector
 
 value = 16 * 2^32 valuations per step / step time.  The JSON line also
 carries the roofline of the dominant kernel (the evaluator: integer VALU
@@ -21,6 +22,10 @@ bounded sample on this host.
 
 Workload c3: 4096 random DAG formulas (n in [10,30], 50..2000 ops), counts
 only, one batched launch per step, compared with 4096 plain launches.
+Workload c4: the serving loop (Poisson arrivals, continuous batching),
+reporting p50/p99 latency beside valuations/s.
+Workload copy: a 1 GiB device copy, the calibration kernel for the HBM byte
+counters.
 """
 
 import argparse
@@ -122,10 +127,9 @@ def bench_c1(args, torch, fbg):
         if record:
             b.record(stream)
             ev.append((a, b))
-        for p, ii, tt in zip(ps, idx, tots):                         # enumerate
-            fbg.enumerate_models(p, cap, out=ii, total=tt, stream=stream)
-        for p, d in zip(ps, dnfs):                                   # DNF write-out
-            fbg.eval_dnf(p, out=d, stream=stream)
+        for p, d, ii, tt in zip(ps, dnfs, idx, tots):
+            fbg.eval_dnf(p, out=d, stream=stream)                    # DNF write-out
+            fbg.enumerate_dnf(d, n, cap, out=ii, total=tt, stream=stream)  # models, from the DNF
 
     for _ in range(args.warmup):
         step(False)
@@ -235,13 +239,81 @@ def bench_c3(args, torch, fbg):
     }
 
 
+def bench_c4(args, torch, fbg):
+    """Serving: Poisson arrivals of model-counting requests (90% random 3-CNF
+    with n uniform in [12,36] and ratio 4.25, 10% the theories of the k=9
+    equivalence, 5x5 permutation and k=8 triangle-free workloads), continuous
+    batching.  First the saturation rate is measured with every request
+    arriving at once; then arrivals come at `load` x that rate."""
+    import oracle
+    from paper_1310_6978_amd.serve import ServeLoop
+    from workloads.serving import request_stream
+    loop = ServeLoop(words_per_lane=16, slice_words=args.slice_words, max_active=256)
+    warm = request_stream(50, 0.0, seed=99)
+    loop.run(warm, realtime=False)
+    sat = loop.run(request_stream(args.sat_requests, 0.0, seed=1), realtime=False)
+    rate = sat["requests_per_s"]
+    qps = args.load * rate
+    reqs = request_stream(args.requests, qps, seed=0)
+    res = loop.run(reqs, realtime=True)
+    loop.close()
+    closed = {"equivalence_k9": 21147, "permutations_k5": 120, "triangle_free_k8": 4682270}
+    ok = True
+    checked = 0
+    for r in reqs:
+        c = res["counts"][r["id"]]
+        if r["kind"] in closed:
+            ok = ok and c == closed[r["kind"]]
+            checked += 1
+        elif r["n"] <= 20 and checked < 400:
+            ok = ok and c == oracle.count(r["text"], r["n"])
+            checked += 1
+    return {
+        "metric": METRIC, "value": res["valuations_per_s"], "unit": "valuations/s",
+        "ms_per_step": res["wall_s"] * 1e3, "dtype": "u32",
+        "config": {"workload": "serving: %d requests, Poisson arrivals at %.0f req/s (%.2f x saturation); 90%% "
+                               "random 3-CNF n in [12,36] ratio 4.25, 10%% theories (equivalence k=9, 5x5 "
+                               "permutations, triangle-free k=8)" % (args.requests, qps, args.load),
+                   "requests": args.requests, "qps": qps, "load": args.load},
+        "serving": {"latency_p50_ms": res["latency_p50_ms"], "latency_p99_ms": res["latency_p99_ms"],
+                    "latency_mean_ms": res["latency_mean_ms"], "requests_per_s": res["requests_per_s"],
+                    "saturation_requests_per_s": rate, "saturation_valuations_per_s": sat["valuations_per_s"],
+                    "gpu_busy": res["gpu_busy"], "slices": res["slices"],
+                    "program_cache_hits": res["cache_hits"]},
+        "bit_exact_vs_oracle": ok, "requests_checked": checked,
+    }
+
+
+def bench_copy(args, torch):
+    """A plain device-to-device copy of 1 GiB: the calibration kernel for the
+    FETCH_SIZE / WRITE_SIZE counters (it must read and write 1 GiB)."""
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").fill_(7)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    return {"metric": "copy bandwidth (counter calibration)", "value": 2 * nbytes / (ms / 1e3) / 1e9,
+            "unit": "GB/s", "ms_per_step": ms, "dtype": "u64",
+            "config": {"workload": "device copy of 1 GiB (reads 1 GiB, writes 1 GiB)", "bytes": nbytes}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=20000, help="c4: requests in the timed run")
+    ap.add_argument("--sat-requests", type=int, default=1000, help="c4: requests of the saturation run")
+    ap.add_argument("--load", type=float, default=0.6, help="c4: arrival rate as a fraction of saturation")
+    ap.add_argument("--slice-words", type=float, default=4e10, help="c4: clause-word work per slice")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path needs no collective, and this build measures "
@@ -253,7 +325,14 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     from paper_1310_6978_amd import fbg
-    res = bench_c1(args, torch, fbg) if args.workload == "c1" else bench_c3(args, torch, fbg)
+    if args.workload == "c1":
+        res = bench_c1(args, torch, fbg)
+    elif args.workload == "c3":
+        res = bench_c3(args, torch, fbg)
+    elif args.workload == "c4":
+        res = bench_c4(args, torch, fbg)
+    else:
+        res = bench_copy(args, torch)
     out = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"),

@@ -60,7 +60,7 @@ typedef enum {
 #define FBG_MAX_DNF_VARS 40
 
 /* Largest number of words (32-bit slices) one lane evaluates per tile. */
-#define FBG_MAX_WORDS_PER_LANE 16
+#define FBG_MAX_WORDS_PER_LANE 32
 
 typedef struct fbg_program fbg_program; /* opaque, library-owned */
 typedef struct fbg_batch fbg_batch;     /* opaque, library-owned */
@@ -81,7 +81,7 @@ typedef struct {
 
 /* Launch tuning.  Zero fields mean "let the library choose". */
 typedef struct {
-  int32_t words_per_lane;  /* 1, 2, 4, 8 or 16 (32-bit words per lane per tile) */
+  int32_t words_per_lane;  /* 1, 2, 4, 8, 16 or 32 (32-bit words per lane per tile) */
   int32_t grid_blocks;     /* blocks of 256 threads for persistent launches */
   int32_t reserved0;
   int32_t reserved1;
@@ -160,6 +160,55 @@ fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream);
 void fbg_batch_free(fbg_batch *b);
 fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d_counts, const fbg_tune *tune,
                            void *stream);
+
+/*
+ * fbg_enumerate_dnf -- the models read off a stored DNF vector (Section 3.2:
+ * all models of T* come from b), in ascending order: the same outputs and
+ * conventions as fbg_enumerate, for a vector d_dnf of max(1, 2^(n-6)) words
+ * that a previous fbg_eval_dnf wrote (bits at or above 2^n must be zero).
+ * Reads 2^n/8 bytes instead of evaluating the program again.  n <=
+ * FBG_MAX_DNF_VARS.  Allocates temporary device memory on `stream`.
+ */
+fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_idx, uint64_t capacity,
+                             uint64_t *d_total, void *stream);
+
+/*
+ * Serving (continuous batching of many requests on one GPU; the slicing of
+ * the search space into blocks of Section 4.1 applied across requests).
+ *
+ * A request's valuation space is cut into tiles of 64 * words_per_lane
+ * 32-bit words; fbg_program_tiles gives their number (0 for a bad argument).
+ * A work item names a program of the launch (`prog`, index into ps), a
+ * counter (`slot`, index into d_counts) and a tile range [tile_begin,
+ * tile_end).  fbg_server_launch adds the models found in every item to
+ * d_counts[slot] (it does not clear them), so one request may be spread over
+ * many launches and many requests share one launch.
+ *
+ * fbg_server_create -- staging for up to max_programs programs and max_items
+ *   items per launch, nbuf launches in flight (pinned host and device buffers
+ *   allocated here, once).  words_per_lane fixes the tile size.
+ * fbg_server_launch -- upload the program table and the items (asynchronous,
+ *   from pinned memory) and launch one persistent batched kernel on `stream`.
+ *   Items are validated on the host (FBG_E_INVAL on a bad index or range).
+ *   A staging buffer is reused only after its previous launch has finished.
+ *   Not thread-safe: one server object per host thread.
+ * fbg_server_free -- waits for the launches in flight, then releases.
+ */
+typedef struct {
+  int32_t prog;
+  int32_t slot;
+  uint64_t tile_begin;
+  uint64_t tile_end;
+} fbg_item;
+
+typedef struct fbg_server fbg_server; /* opaque, library-owned */
+
+uint64_t fbg_program_tiles(const fbg_program *p, int32_t words_per_lane);
+fbg_status fbg_server_create(int32_t max_programs, int32_t max_items, int32_t words_per_lane, int32_t nbuf,
+                             fbg_server **out);
+fbg_status fbg_server_launch(fbg_server *s, const fbg_program *const *ps, int32_t np, const fbg_item *items,
+                             int32_t nitems, uint64_t *d_counts, int32_t ncounts, void *stream);
+void fbg_server_free(fbg_server *s);
 
 /*
  * Tuned single-program variants: as fbg_count / fbg_eval_dnf but with an

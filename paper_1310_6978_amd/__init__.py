@@ -14,7 +14,10 @@ from .fbg import (  # noqa: F401
     count,
     count_batch,
     dnf_words,
+    enumerate_dnf,
     enumerate_models,
     eval_dnf,
+    program_tiles,
+    Server,
     version,
 )

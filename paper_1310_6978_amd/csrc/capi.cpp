@@ -1,5 +1,5 @@
 // capi.cpp -- the C ABI of include/fbg.h: program residency, launch
-// geometry, work plans for batches, and argument checking.
+// geometry, work plans for batches and serving, and argument checking.
 #include <hip/hip_runtime_api.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -34,7 +34,7 @@ fbg_status hip_fail(hipError_t e, const char *what) {
   return fail(FBG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-constexpr int kMaxLog2W = 4;
+constexpr int kMaxLog2W = 5;
 constexpr int kWavesPerBlock = 4;
 constexpr size_t kMaxLdsPerBlock = 64 * 1024;
 
@@ -60,22 +60,92 @@ uint64_t tiles_of(uint64_t nslices, int log2w) {
 
 size_t lds_per_wave(uint32_t nregs, int log2w) { return (size_t)nregs * (64u << log2w) * 4u; }
 
+// Device memory for programs: size classes of powers of two (>= 4 KiB) carved
+// out of 64 MiB chunks and recycled through free lists, so that compiling a
+// request costs one small copy and no hipMalloc.  One arena per device.
+class CodeArena {
+ public:
+  static CodeArena &of(int dev) {
+    static std::mutex m;
+    static std::vector<CodeArena *> arenas;
+    std::lock_guard<std::mutex> g(m);
+    if ((size_t)dev >= arenas.size()) arenas.resize((size_t)dev + 1, nullptr);
+    if (!arenas[(size_t)dev]) arenas[(size_t)dev] = new CodeArena();
+    return *arenas[(size_t)dev];
+  }
+
+  hipError_t alloc(size_t bytes, void **out, int &cls) {
+    std::lock_guard<std::mutex> g(mu_);
+    cls = 12;
+    while (((size_t)1 << cls) < bytes) cls++;
+    const size_t sz = (size_t)1 << cls;
+    if (sz > kChunk) {  // very large programs get their own allocation
+      cls = -1;
+      return hipMalloc(out, bytes);
+    }
+    auto &fl = free_[(size_t)cls];
+    if (!fl.empty()) {
+      *out = fl.back();
+      fl.pop_back();
+      return hipSuccess;
+    }
+    if (!cur_ || used_ + sz > kChunk) {
+      void *c = nullptr;
+      hipError_t e = hipMalloc(&c, kChunk);
+      if (e != hipSuccess) return e;
+      cur_ = (char *)c;
+      used_ = 0;
+    }
+    *out = cur_ + used_;
+    used_ += sz;
+    return hipSuccess;
+  }
+
+  void release(void *p, int cls) {
+    if (!p) return;
+    if (cls < 0) {
+      (void)hipFree(p);
+      return;
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    free_[(size_t)cls].push_back(p);
+  }
+
+ private:
+  static constexpr size_t kChunk = (size_t)64 << 20;
+  std::mutex mu_;
+  char *cur_ = nullptr;
+  size_t used_ = 0;
+  std::vector<void *> free_[64];
+};
+
+fbg_status parse_wpl(int w, int &log2w) {
+  if (w < 1 || w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1)))
+    return fail(FBG_E_INVAL, "words_per_lane must be 1, 2, 4, 8, 16 or 32 (got %d)", w);
+  log2w = __builtin_ctz((unsigned)w);
+  return FBG_OK;
+}
+
 }  // namespace
 
 struct fbg_program {
   fbg::Compiled c;
-  int device = -1;                 // -1: compiled without a device (host only)
+  int device = -1;  // -1: compiled without a device (host only)
   uint32_t *d_code = nullptr;
+  int code_class = 0;  // size class in the device's code arena
   std::vector<uint32_t> words[kMaxLog2W + 1];
-  uint64_t dev_off[kMaxLog2W + 1] = {0, 0, 0, 0, 0};
-  uint32_t nins[kMaxLog2W + 1] = {0, 0, 0, 0, 0};
+  uint64_t dev_off[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
+  uint32_t nins[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
+  uint32_t ncl = 0;  // leading clause instructions
   int auto_log2w = 0;
   uint64_t nslices = 1;
+  bool general() const { return c.code.size() > ncl; }
 };
 
 struct fbg_batch {
   int device = -1;
   int log2w = 0;
+  bool gen = false;
   int grid = 1;
   int block = 256;
   size_t lds = 0;
@@ -85,6 +155,20 @@ struct fbg_batch {
   fbg::BatchProg *d_progs = nullptr;
   fbg::BatchItem *d_items = nullptr;
   uint32_t *d_head = nullptr;
+};
+
+struct fbg_server {
+  int device = -1;
+  int log2w = 0;
+  int32_t max_programs = 0, max_items = 0, nbuf = 0, next = 0;
+  struct Slot {
+    char *h = nullptr;  // pinned staging: programs then items
+    char *d = nullptr;  // device copy
+    uint32_t *d_head = nullptr;
+    hipEvent_t done = nullptr;
+    bool used = false;
+  };
+  std::vector<Slot> slots;
 };
 
 namespace {
@@ -110,41 +194,45 @@ struct Geometry {
   size_t lds;
 };
 
-fbg_status geometry(const fbg_program *p, const fbg_tune *tune, uint64_t min_tiles_per_wave, Geometry &g) {
-  int l = p->auto_log2w;
-  if (tune && tune->words_per_lane) {
-    int w = tune->words_per_lane;
-    if (w < 1 || w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1)))
-      return fail(FBG_E_INVAL, "words_per_lane must be 1, 2, 4, 8 or 16 (got %d)", w);
-    l = __builtin_ctz((unsigned)w);
-  }
-  const size_t lw = lds_per_wave((uint32_t)p->c.nregs, l);
-  int wpb = kWavesPerBlock;
+fbg_status block_shape(uint32_t nregs, int l, int &wpb, size_t &lds) {
+  const size_t lw = lds_per_wave(nregs, l);
+  wpb = kWavesPerBlock;
   if (lw * wpb > kMaxLdsPerBlock) wpb = 1;
   if (lw * wpb > kMaxLdsPerBlock)
-    return fail(FBG_E_RANGE, "program needs %d registers x %d words per lane: %zu bytes of LDS per wave (max %zu)",
-                p->c.nregs, 1 << l, lw, kMaxLdsPerBlock);
+    return fail(FBG_E_RANGE, "program needs %u registers x %d words per lane: %zu bytes of LDS per wave (max %zu)",
+                nregs, 1 << l, lw, kMaxLdsPerBlock);
+  lds = lw * wpb;
+  return FBG_OK;
+}
+
+fbg_status geometry(const fbg_program *p, const fbg_tune *tune, Geometry &g) {
+  int l = p->auto_log2w;
+  fbg_status st;
+  if (tune && tune->words_per_lane && (st = parse_wpl(tune->words_per_lane, l))) return st;
+  int wpb;
+  if ((st = block_shape((uint32_t)p->c.nregs, l, wpb, g.lds))) return st;
   const uint64_t ntiles = tiles_of(p->nslices, l);
-  uint64_t blocks = (ntiles + wpb - 1) / wpb;
-  (void)min_tiles_per_wave;
+  const uint64_t blocks = (ntiles + wpb - 1) / wpb;
   uint64_t maxb = (uint64_t)cu_count(p->device) * (32 / wpb);
   if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
   g.log2w = l;
   g.block = 64 * wpb;
   g.grid = (int)std::max<uint64_t>(1, std::min(blocks, maxb));
-  g.lds = lw * wpb;
+  return FBG_OK;
+}
+
+fbg_status check_device(int want) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != want) return fail(FBG_E_INVAL, "object lives on device %d but the current device is %d", want, dev);
   return FBG_OK;
 }
 
 fbg_status check_program(const fbg_program *p) {
   if (!p) return fail(FBG_E_INVAL, "program is NULL");
   if (p->device < 0 || !p->d_code) return fail(FBG_E_DEVICE, "program was compiled without a HIP device");
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (dev != p->device)
-    return fail(FBG_E_INVAL, "program lives on device %d but the current device is %d", p->device, dev);
-  return FBG_OK;
+  return check_device(p->device);
 }
 
 fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
@@ -152,6 +240,7 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   memset(&a, 0, sizeof a);
   a.code = p->d_code + p->dev_off[log2w];
   a.nins = p->nins[log2w];
+  a.ncl = p->ncl;
   a.nregs = (uint32_t)p->c.nregs;
   a.n = p->c.n;
   a.nslices = p->nslices;
@@ -159,11 +248,56 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   return a;
 }
 
+fbg::BatchProg batch_prog(const fbg_program *p, int l) {
+  fbg::BatchProg b;
+  memset(&b, 0, sizeof b);
+  b.code = p->d_code + p->dev_off[l];
+  b.nins = p->nins[l];
+  b.ncl = p->ncl;
+  b.nregs = (uint32_t)p->c.nregs;
+  b.n = p->c.n;
+  b.nslices = p->nslices;
+  b.ntiles = tiles_of(p->nslices, l);
+  return b;
+}
+
+// Two-pass enumeration given the pass launcher: counts -> scan -> compaction.
+template <typename Pass>
+fbg_status enumerate_with(fbg::EvalArgs a, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total, hipStream_t s,
+                          Pass pass) {
+  const uint64_t nt = a.ntiles;
+  const uint64_t nb = fbg::scan_block_count(nt);
+  const size_t bytes_cnt = ((nt * 4 + 255) / 256) * 256;
+  const size_t bytes_off = ((nt * 8 + 255) / 256) * 256;
+  const size_t bytes_blk = (nb + 1) * 8;
+  char *tmp = nullptr;
+  hipError_t e = hipMallocAsync((void **)&tmp, bytes_cnt + bytes_off + bytes_blk, s);
+  if (e != hipSuccess)
+    return fail(FBG_E_NOMEM, "hipMallocAsync of %zu bytes: %s", bytes_cnt + bytes_off + bytes_blk,
+                hipGetErrorString(e));
+  uint32_t *cnt = (uint32_t *)tmp;
+  uint64_t *off = (uint64_t *)(tmp + bytes_cnt);
+  uint64_t *blk = (uint64_t *)(tmp + bytes_cnt + bytes_off);
+  a.tile_counts = cnt;
+  e = pass(fbg::EVAL_TILECNT, a);
+  if (e == hipSuccess) e = fbg::launch_scan(cnt, nt, off, blk, d_total, s);
+  if (e == hipSuccess && capacity > 0) {
+    a.tile_offsets = off;
+    a.out_idx = d_idx;
+    a.capacity = capacity;
+    e = pass(fbg::EVAL_ENUM, a);
+  }
+  hipError_t e2 = hipFreeAsync(tmp, s);
+  if (e != hipSuccess) return hip_fail(e, "launch of an enumeration kernel");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return FBG_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *fbg_version(void) { return "fbg 0.1 (gfx950)"; }
+const char *fbg_version(void) { return "fbg 0.2 (gfx950)"; }
 const char *fbg_last_error(void) { return g_err.c_str(); }
 int64_t fbg_last_error_offset(void) { return g_err_off; }
 
@@ -186,6 +320,7 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
     return (fbg_status)st;
   }
   p->nslices = slices_of(n_vars);
+  p->ncl = fbg::leading_clauses(p->c);
   size_t total = 0;
   for (int l = 0; l <= kMaxLog2W; l++) {
     p->nins[l] = fbg::encode_program(p->c, l, p->words[l]);
@@ -202,17 +337,17 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
     }
     p->device = dev;
     std::vector<uint32_t> all;
-    all.reserve(total + 8);
+    all.reserve(total + 64);
     for (int l = 0; l <= kMaxLog2W; l++) all.insert(all.end(), p->words[l].begin(), p->words[l].end());
-    all.resize(all.size() + 8, 0);  // padding: never read, keeps the allocation non-empty
-    e = hipMalloc((void **)&p->d_code, all.size() * sizeof(uint32_t));
+    all.resize(all.size() + 64, 0);  // padding: scalar loads never run past the allocation
+    e = CodeArena::of(dev).alloc(all.size() * sizeof(uint32_t), (void **)&p->d_code, p->code_class);
     if (e != hipSuccess) {
       delete p;
-      return fail(FBG_E_NOMEM, "hipMalloc of the program: %s", hipGetErrorString(e));
+      return fail(FBG_E_NOMEM, "device memory for the program: %s", hipGetErrorString(e));
     }
     e = hipMemcpy(p->d_code, all.data(), all.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-      (void)hipFree(p->d_code);
+      CodeArena::of(dev).release(p->d_code, p->code_class);
       delete p;
       return hip_fail(e, "hipMemcpy of the program");
     }
@@ -226,7 +361,7 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
 
 void fbg_program_free(fbg_program *p) {
   if (!p) return;
-  if (p->d_code) (void)hipFree(p->d_code);
+  if (p->d_code) CodeArena::of(p->device).release(p->d_code, p->code_class);
   delete p;
 }
 
@@ -238,10 +373,16 @@ fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out) {
   out->l2in = p->c.l2in;
   out->n_instr = (int32_t)p->nins[p->auto_log2w];
   out->n_regs = p->c.nregs;
-  out->n_clause_instr = p->c.n_clause_instr;
+  out->n_clause_instr = (int32_t)p->ncl;
   out->words_per_lane = 1 << p->auto_log2w;
   out->dnf_words = dnf_words_of(p->c.n);
   return FBG_OK;
+}
+
+uint64_t fbg_program_tiles(const fbg_program *p, int32_t words_per_lane) {
+  int l;
+  if (!p || parse_wpl(words_per_lane, l)) return 0;
+  return tiles_of(p->nslices, l);
 }
 
 fbg_status fbg_count_tuned(const fbg_program *p, uint64_t *d_count, const fbg_tune *tune, void *stream) {
@@ -255,12 +396,12 @@ fbg_status fbg_count_tuned(const fbg_program *p, uint64_t *d_count, const fbg_tu
     return e == hipSuccess ? FBG_OK : hip_fail(e, "launch");
   }
   Geometry g;
-  if ((st = geometry(p, tune, 1, g))) return st;
+  if ((st = geometry(p, tune, g))) return st;
   fbg::EvalArgs a = base_args(p, g.log2w);
   a.out_count = d_count;
   e = fbg::launch_set_u64(d_count, 0, s);
   if (e != hipSuccess) return hip_fail(e, "launch");
-  e = fbg::launch_eval(fbg::EVAL_COUNT, g.log2w, a, g.grid, g.block, g.lds, s);
+  e = fbg::launch_eval(fbg::EVAL_COUNT, g.log2w, p->general(), a, g.grid, g.block, g.lds, s);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the count kernel");
 }
 
@@ -278,11 +419,12 @@ fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t ou
   if (out_words < need)
     return fail(FBG_E_INVAL, "out_words=%llu < %llu", (unsigned long long)out_words, (unsigned long long)need);
   Geometry g;
-  if ((st = geometry(p, tune, 1, g))) return st;
+  if ((st = geometry(p, tune, g))) return st;
   fbg::EvalArgs a = base_args(p, g.log2w);
   a.out32 = (uint32_t *)d_out;
   a.out_slices = 2 * need;
-  hipError_t e = fbg::launch_eval(fbg::EVAL_DNF, g.log2w, a, g.grid, g.block, g.lds, (hipStream_t)stream);
+  hipError_t e =
+      fbg::launch_eval(fbg::EVAL_DNF, g.log2w, p->general(), a, g.grid, g.block, g.lds, (hipStream_t)stream);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the DNF kernel");
 }
 
@@ -295,36 +437,39 @@ fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacit
   fbg_status st = check_program(p);
   if (st) return st;
   if (!d_total) return fail(FBG_E_INVAL, "d_total is NULL");
-  if (capacity > 0 && !d_idx) return fail(FBG_E_INVAL, "d_idx is NULL with capacity %llu", (unsigned long long)capacity);
+  if (capacity > 0 && !d_idx)
+    return fail(FBG_E_INVAL, "d_idx is NULL with capacity %llu", (unsigned long long)capacity);
   Geometry g;
-  if ((st = geometry(p, nullptr, 1, g))) return st;
+  if ((st = geometry(p, nullptr, g))) return st;
   hipStream_t s = (hipStream_t)stream;
-  fbg::EvalArgs a = base_args(p, g.log2w);
-  const uint64_t nt = a.ntiles;
-  const uint64_t nb = fbg::scan_block_count(nt);
-  const size_t bytes_cnt = ((nt * 4 + 255) / 256) * 256;
-  const size_t bytes_off = nt * 8;
-  const size_t bytes_blk = (nb + 1) * 8;
-  char *tmp = nullptr;
-  hipError_t e = hipMallocAsync((void **)&tmp, bytes_cnt + bytes_off + bytes_blk, s);
-  if (e != hipSuccess) return fail(FBG_E_NOMEM, "hipMallocAsync of %zu bytes: %s", bytes_cnt + bytes_off + bytes_blk,
-                                   hipGetErrorString(e));
-  uint32_t *cnt = (uint32_t *)tmp;
-  uint64_t *off = (uint64_t *)(tmp + bytes_cnt);
-  uint64_t *blk = (uint64_t *)(tmp + bytes_cnt + bytes_off);
-  a.tile_counts = cnt;
-  e = fbg::launch_eval(fbg::EVAL_TILECNT, g.log2w, a, g.grid, g.block, g.lds, s);
-  if (e == hipSuccess) e = fbg::launch_scan(cnt, nt, off, blk, d_total, s);
-  if (e == hipSuccess && capacity > 0) {
-    a.tile_offsets = off;
-    a.out_idx = d_idx;
-    a.capacity = capacity;
-    e = fbg::launch_eval(fbg::EVAL_ENUM, g.log2w, a, g.grid, g.block, g.lds, s);
-  }
-  hipError_t e2 = hipFreeAsync(tmp, s);
-  if (e != hipSuccess) return hip_fail(e, "launch of an enumeration kernel");
-  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
-  return FBG_OK;
+  const bool gen = p->general();
+  return enumerate_with(base_args(p, g.log2w), d_idx, capacity, d_total, s,
+                        [&](int mode, const fbg::EvalArgs &a) {
+                          return fbg::launch_eval(mode, g.log2w, gen, a, g.grid, g.block, g.lds, s);
+                        });
+}
+
+fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_idx, uint64_t capacity,
+                             uint64_t *d_total, void *stream) {
+  if (!d_dnf || !d_total) return fail(FBG_E_INVAL, "NULL device pointer");
+  if (capacity > 0 && !d_idx)
+    return fail(FBG_E_INVAL, "d_idx is NULL with capacity %llu", (unsigned long long)capacity);
+  if (n_vars < 0 || n_vars > FBG_MAX_DNF_VARS) return fail(FBG_E_RANGE, "n=%d out of range", n_vars);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  fbg::EvalArgs a;
+  memset(&a, 0, sizeof a);
+  a.n = n_vars;
+  a.nslices = 2 * dnf_words_of(n_vars);  // bits at or above 2^n are zero in a DNF vector
+  a.ntiles = tiles_of(a.nslices, 5);
+  a.out32 = (uint32_t *)d_dnf;
+  const uint64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)cu_count(dev) * 8));
+  hipStream_t s = (hipStream_t)stream;
+  return enumerate_with(a, d_idx, capacity, d_total, s, [&](int mode, const fbg::EvalArgs &aa) {
+    return fbg::launch_dnf_scan(mode, aa, grid, 64 * kWavesPerBlock, s);
+  });
 }
 
 // ------------------------------------------------------------------ batches
@@ -341,15 +486,13 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   }
   // words per lane: the tuning, else the choice for the largest program
   int l = 0;
+  fbg_status st;
   if (tune && tune->words_per_lane) {
-    int w = tune->words_per_lane;
-    if (w < 1 || w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1)))
-      return fail(FBG_E_INVAL, "words_per_lane must be 1, 2, 4, 8 or 16 (got %d)", w);
-    l = __builtin_ctz((unsigned)w);
+    if ((st = parse_wpl(tune->words_per_lane, l))) return st;
   } else {
     uint64_t best = 0;
     for (int32_t i = 0; i < np; i++) {
-      uint64_t cost = ps[i]->nslices * (uint64_t)std::max<size_t>(1, ps[i]->c.code.size());
+      const uint64_t cost = ps[i]->nslices * (uint64_t)std::max<size_t>(1, ps[i]->c.code.size());
       if (cost >= best) {
         best = cost;
         l = ps[i]->auto_log2w;
@@ -357,26 +500,21 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     }
   }
   uint32_t max_regs = 0;
-  for (int32_t i = 0; i < np; i++) max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
+  bool gen = false;
+  for (int32_t i = 0; i < np; i++) {
+    max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
+    gen = gen || ps[i]->general();
+  }
   while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
-  const size_t lw = lds_per_wave(max_regs, l);
-  int wpb = kWavesPerBlock;
-  if (lw * wpb > kMaxLdsPerBlock) wpb = 1;
-  if (lw * wpb > kMaxLdsPerBlock) return fail(FBG_E_RANGE, "a program of the batch needs %u registers", max_regs);
+  int wpb;
+  size_t lds;
+  if ((st = block_shape(max_regs, l, wpb, lds))) return st;
 
   std::vector<fbg::BatchProg> progs((size_t)np);
   double total_cost = 0;
   for (int32_t i = 0; i < np; i++) {
-    const fbg_program *p = ps[i];
-    fbg::BatchProg &b = progs[(size_t)i];
-    b.code = p->d_code + p->dev_off[l];
-    b.nins = p->nins[l];
-    b.nregs = (uint32_t)p->c.nregs;
-    b.n = p->c.n;
-    b.pad0 = 0;
-    b.nslices = p->nslices;
-    b.ntiles = tiles_of(p->nslices, l);
-    total_cost += (double)b.ntiles * (b.nins + 4);
+    progs[(size_t)i] = batch_prog(ps[i], l);
+    total_cost += (double)progs[(size_t)i].ntiles * (progs[(size_t)i].nins + 4);
   }
   const int cus = cu_count(dev);
   const uint64_t waves = (uint64_t)cus * 32;
@@ -387,11 +525,11 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   for (int32_t i = 0; i < np; i++) {
     const fbg::BatchProg &b = progs[(size_t)i];
     const double per_tile = b.nins + 4.0;
-    uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
+    const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
     for (uint64_t t = 0; t < b.ntiles; t += chunk) {
       fbg::BatchItem it;
       it.prog = (uint32_t)i;
-      it.pad0 = 0;
+      it.slot = (uint32_t)i;
       it.t0 = t;
       it.t1 = std::min(b.ntiles, t + chunk);
       items.push_back(it);
@@ -410,11 +548,12 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   if (!b) return fail(FBG_E_NOMEM, "out of host memory");
   b->device = dev;
   b->log2w = l;
+  b->gen = gen;
   b->np = np;
   b->nitems = (uint32_t)sorted.size();
   b->max_regs = max_regs;
   b->block = 64 * wpb;
-  b->lds = lw * wpb;
+  b->lds = lds;
   uint64_t maxb = (uint64_t)cus * (32 / wpb);
   if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
   b->grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((b->nitems + wpb - 1) / wpb, maxb));
@@ -436,12 +575,10 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
 fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream) {
   if (!b) return fail(FBG_E_INVAL, "batch is NULL");
   if (!d_counts) return fail(FBG_E_INVAL, "d_counts is NULL");
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (dev != b->device) return fail(FBG_E_INVAL, "batch lives on device %d, current device is %d", b->device, dev);
+  fbg_status st = check_device(b->device);
+  if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  e = fbg::launch_zero(d_counts, (uint64_t)b->np, b->d_head, s);
+  hipError_t e = fbg::launch_zero(d_counts, (uint64_t)b->np, b->d_head, s);
   if (e != hipSuccess) return hip_fail(e, "launch of the zero fill");
   fbg::BatchArgs a;
   a.progs = b->d_progs;
@@ -450,7 +587,7 @@ fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream) {
   a.max_regs = b->max_regs;
   a.head = b->d_head;
   a.counts = d_counts;
-  e = fbg::launch_batch(b->log2w, a, b->grid, b->block, b->lds, s);
+  e = fbg::launch_batch(b->log2w, b->gen, a, b->grid, b->block, b->lds, s);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the batch kernel");
 }
 
@@ -475,15 +612,128 @@ fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d
   return e == hipSuccess ? FBG_OK : hip_fail(e, "hipStreamSynchronize");
 }
 
+// ------------------------------------------------------------------ serving
+
+fbg_status fbg_server_create(int32_t max_programs, int32_t max_items, int32_t words_per_lane, int32_t nbuf,
+                             fbg_server **out) {
+  if (!out) return fail(FBG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (max_programs <= 0 || max_items <= 0 || nbuf <= 0 || nbuf > 64) return fail(FBG_E_INVAL, "bad server sizes");
+  int l;
+  fbg_status st = parse_wpl(words_per_lane, l);
+  if (st) return st;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  fbg_server *sv = new (std::nothrow) fbg_server();
+  if (!sv) return fail(FBG_E_NOMEM, "out of host memory");
+  sv->device = dev;
+  sv->log2w = l;
+  sv->max_programs = max_programs;
+  sv->max_items = max_items;
+  sv->nbuf = nbuf;
+  sv->slots.resize((size_t)nbuf);
+  const size_t bytes = (size_t)max_programs * sizeof(fbg::BatchProg) + (size_t)max_items * sizeof(fbg::BatchItem);
+  for (auto &sl : sv->slots) {
+    e = hipHostMalloc((void **)&sl.h, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)&sl.d, bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&sl.d_head, 256);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      fbg_server_free(sv);
+      return fail(FBG_E_NOMEM, "server buffers: %s", hipGetErrorString(e));
+    }
+  }
+  *out = sv;
+  return FBG_OK;
+}
+
+fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32_t np, const fbg_item *items,
+                             int32_t nitems, uint64_t *d_counts, int32_t ncounts, void *stream) {
+  if (!sv) return fail(FBG_E_INVAL, "server is NULL");
+  if (np <= 0 || np > sv->max_programs || !ps) return fail(FBG_E_INVAL, "np=%d out of range", np);
+  if (nitems <= 0 || nitems > sv->max_items || !items) return fail(FBG_E_INVAL, "nitems=%d out of range", nitems);
+  if (!d_counts || ncounts <= 0) return fail(FBG_E_INVAL, "no counts array");
+  fbg_status st = check_device(sv->device);
+  if (st) return st;
+  const int l = sv->log2w;
+  uint32_t max_regs = 0;
+  bool gen = false;
+  for (int32_t i = 0; i < np; i++) {
+    if ((st = check_program(ps[i]))) return st;
+    max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
+    gen = gen || ps[i]->general();
+  }
+  // validate every item on the host: the kernel trusts them
+  for (int32_t k = 0; k < nitems; k++) {
+    const fbg_item &it = items[k];
+    if (it.prog < 0 || it.prog >= np) return fail(FBG_E_INVAL, "item %d: program %d out of range", k, it.prog);
+    if (it.slot < 0 || it.slot >= ncounts) return fail(FBG_E_INVAL, "item %d: slot %d out of range", k, it.slot);
+    const uint64_t nt = tiles_of(ps[it.prog]->nslices, l);
+    if (it.tile_begin > it.tile_end || it.tile_end > nt)
+      return fail(FBG_E_INVAL, "item %d: tiles [%llu,%llu) outside [0,%llu)", k, (unsigned long long)it.tile_begin,
+                  (unsigned long long)it.tile_end, (unsigned long long)nt);
+  }
+  int wpb;
+  size_t lds;
+  if ((st = block_shape(max_regs, l, wpb, lds))) return st;
+  fbg_server::Slot &sl = sv->slots[(size_t)sv->next];
+  sv->next = (sv->next + 1) % sv->nbuf;
+  hipError_t e;
+  if (sl.used && (e = hipEventSynchronize(sl.done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  fbg::BatchProg *hp = (fbg::BatchProg *)sl.h;
+  fbg::BatchItem *hi = (fbg::BatchItem *)(sl.h + (size_t)sv->max_programs * sizeof(fbg::BatchProg));
+  for (int32_t i = 0; i < np; i++) hp[i] = batch_prog(ps[i], l);
+  for (int32_t k = 0; k < nitems; k++) {
+    hi[k].prog = (uint32_t)items[k].prog;
+    hi[k].slot = (uint32_t)items[k].slot;
+    hi[k].t0 = items[k].tile_begin;
+    hi[k].t1 = items[k].tile_end;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char *dp = sl.d;
+  char *di = sl.d + (size_t)sv->max_programs * sizeof(fbg::BatchProg);
+  e = hipMemcpyAsync(dp, hp, (size_t)np * sizeof(fbg::BatchProg), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(di, hi, (size_t)nitems * sizeof(fbg::BatchItem), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = fbg::launch_zero(nullptr, 0, sl.d_head, s);
+  if (e != hipSuccess) return hip_fail(e, "server upload");
+  fbg::BatchArgs a;
+  a.progs = (const fbg::BatchProg *)dp;
+  a.items = (const fbg::BatchItem *)di;
+  a.nitems = (uint32_t)nitems;
+  a.max_regs = max_regs;
+  a.head = sl.d_head;
+  a.counts = d_counts;
+  const int cus = cu_count(sv->device);
+  const int grid =
+      (int)std::max<int64_t>(1, std::min<int64_t>((nitems + wpb - 1) / wpb, (int64_t)cus * (32 / wpb)));
+  e = fbg::launch_batch(l, gen, a, grid, 64 * wpb, lds, s);
+  if (e == hipSuccess) e = hipEventRecord(sl.done, s);
+  sl.used = true;
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the server slice");
+}
+
+void fbg_server_free(fbg_server *sv) {
+  if (!sv) return;
+  for (auto &sl : sv->slots) {
+    if (sl.used && sl.done) (void)hipEventSynchronize(sl.done);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.h) (void)hipHostFree(sl.h);
+    if (sl.d) (void)hipFree(sl.d);
+    if (sl.d_head) (void)hipFree(sl.d_head);
+  }
+  delete sv;
+}
+
 // --------------------------------------------------------------- debugging
 
 fbg_status fbg_program_emulate(const fbg_program *p, int32_t words_per_lane, uint64_t *h_dnf, uint64_t out_words,
                                uint64_t *h_count) {
   if (!p) return fail(FBG_E_INVAL, "program is NULL");
   if (p->c.n > 30) return fail(FBG_E_RANGE, "emulation is limited to n <= 30");
-  int w = words_per_lane;
-  if (w < 1 || w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1))) return fail(FBG_E_INVAL, "bad words_per_lane %d", w);
-  const int l = __builtin_ctz((unsigned)w);
+  int l;
+  fbg_status st = parse_wpl(words_per_lane, l);
+  if (st) return st;
   const uint64_t need = dnf_words_of(p->c.n);
   if (h_dnf && out_words < need) return fail(FBG_E_INVAL, "out_words too small");
   std::vector<uint32_t> s32((size_t)std::max<uint64_t>(2, p->nslices), 0u);
@@ -499,9 +749,8 @@ fbg_status fbg_program_emulate(const fbg_program *p, int32_t words_per_lane, uin
 
 int64_t fbg_program_disasm(const fbg_program *p, int32_t words_per_lane, char *buf, int64_t cap) {
   if (!p) return -1;
-  int w = words_per_lane <= 0 ? (1 << p->auto_log2w) : words_per_lane;
-  if (w > FBG_MAX_WORDS_PER_LANE || (w & (w - 1))) return -1;
-  const int l = __builtin_ctz((unsigned)w);
+  int l = p->auto_log2w;
+  if (words_per_lane > 0 && parse_wpl(words_per_lane, l)) return -1;
   std::string s = fbg::disasm_program(p->words[l], p->nins[l], l);
   if (buf && cap > 0) {
     size_t k = std::min<size_t>((size_t)cap - 1, s.size());

@@ -604,28 +604,36 @@ struct Codegen {
         n_clause = 1;
         return;
       }
-    // literal-set conjuncts first (they need no registers), then the rest
+    // Clauses first, as one prefix of CL instructions (the kernels run that
+    // prefix in a loop of its own); then XOR / AND sets of literals through
+    // cur; then the general conjuncts.
     n_clause = 0;
     std::vector<Edge> general;
+    std::vector<LitSet> other_sets;
     for (Edge e : uniq) {
       LitSet ls;
       if (literal_set(e, ls)) {
-        HIns h;
-        h.ls = ls;
-        if (!ls.is_xor && !ls.inv) {  // a clause: one CL instruction
+        if (!ls.is_xor && !ls.inv) {
+          HIns h;
           h.op = FBG_OP_CL;
+          h.ls = ls;
           emit(h);
           n_clause++;
-        } else {  // XOR or AND of literals: through cur
-          h.op = FBG_OP_LDL;
-          emit(h);
-          HIns a;
-          a.op = FBG_OP_ACC;
-          emit(a);
+        } else {
+          other_sets.push_back(ls);
         }
       } else {
         general.push_back(e);
       }
+    }
+    for (const LitSet &ls : other_sets) {
+      HIns h;
+      h.op = FBG_OP_LDL;
+      h.ls = ls;
+      emit(h);
+      HIns a;
+      a.op = FBG_OP_ACC;
+      emit(a);
     }
     for (Edge e : general) {
       gen_node(e >> 1);
@@ -812,14 +820,12 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
     if (h.op == FBG_OP_CL || h.op == FBG_OP_LDL || h.op == FBG_OP_OPL) {
       SetWords s = encode_set(h.ls, log2w);
       // CL carries plain OR-sets only (the kernel's clause loop relies on it)
-      if (h.op == FBG_OP_CL) {
-        s.flags &= ~(uint32_t)(FBG_XORSET | FBG_INV);
-        size_t e = 0;
-        while (e < pats.size() && pats[e] != s.pat) e++;
-        if (e == pats.size()) pats.push_back(s.pat);
-        w[0] |= (uint32_t)e << FBG_F_SHIFT;  // at most 81 entries
-      }
-      w[0] |= s.flags | (s.pat << FBG_ARG_SHIFT);
+      if (h.op == FBG_OP_CL) s.flags &= ~(uint32_t)(FBG_XORSET | FBG_INV);
+      size_t e = 0;
+      while (e < pats.size() && pats[e] != s.pat) e++;
+      if (e == pats.size()) pats.push_back(s.pat);
+      // at most 3^5 = 243 entries of at most 32 words: the offset fits 16 bits
+      w[0] |= s.flags | ((uint32_t)(e * (size_t)W) << FBG_ARG_SHIFT);
       w[1] = s.mconst;
       w[2] = (uint32_t)s.lanemask;
       w[3] = (uint32_t)(s.lanemask >> 32);
@@ -836,15 +842,36 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
     words.insert(words.end(), w, w + FBG_INS_WORDS);
   }
   const uint32_t nins = (uint32_t)((words.size() - base) / FBG_INS_WORDS);
+  // Each clause of the prefix carries the pattern entry of the next clause in
+  // w0 bits 8..15 (0 after the last), so the kernel can fetch it one clause
+  // ahead.
+  for (uint32_t k = 0; k < nins && (words[base + (size_t)k * FBG_INS_WORDS] & 15u) == FBG_OP_CL; k++) {
+    uint32_t &w0 = words[base + (size_t)k * FBG_INS_WORDS];
+    uint32_t next = 0;
+    if (k + 1 < nins) {
+      const uint32_t w1 = words[base + (size_t)(k + 1) * FBG_INS_WORDS];
+      if ((w1 & 15u) == FBG_OP_CL) next = (w1 >> FBG_ARG_SHIFT) / (uint32_t)W;
+    }
+    w0 |= (next & 0xFFu) << FBG_F_SHIFT;
+  }
   for (uint32_t pat : pats)
     for (int i = 0; i < W; i++) words.push_back(((pat >> i) & 1u) ? ~0u : 0u);
   return nins;
 }
 
+uint32_t leading_clauses(const Compiled &c) {
+  // the code generator emits every clause before any other instruction
+  uint32_t k = 0;
+  while (k < c.code.size() && c.code[k].op == FBG_OP_CL) k++;
+  return k;
+}
+
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
   static const char *ops[] = {"?", "CL", "LDL", "OPL", "ST", "OPR", "ACC", "LDR", "NOT"};
   static const char *fs[] = {"and", "or", "xor", "?"};
-  std::string out = "; words per lane " + std::to_string(1 << log2w) + "\n";
+  const int W = 1 << log2w;
+  const uint32_t *table = words.data() + (size_t)nins * FBG_INS_WORDS;
+  std::string out = "; words per lane " + std::to_string(W) + "\n";
   char buf[256];
   for (size_t pc = 0; pc < (size_t)nins * FBG_INS_WORDS; pc += FBG_INS_WORDS) {
     const uint32_t *w = &words[pc];
@@ -852,11 +879,14 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
     uint32_t arg = w[0] >> FBG_ARG_SHIFT;
     const char *name = op <= 8 ? ops[op] : "?";
     if (op == FBG_OP_CL || op == FBG_OP_LDL || op == FBG_OP_OPL) {
+      uint32_t pat = 0;
+      for (int i = 0; i < W; i++)
+        if (table[arg + i]) pat |= 1u << i;
       snprintf(buf, sizeof buf,
-               "%4zu %-3s %s%s%s set=%s%s mconst=%08x lane=%08x%08x pat=%04x sel=%08x%08x neg=%08x%08x\n",
+               "%4zu %-3s %s%s set=%s%s mconst=%08x lane=%08x%08x pat=%08x sel=%08x%08x neg=%08x%08x\n",
                pc / FBG_INS_WORDS, name, op == FBG_OP_OPL ? fs[(w[0] >> FBG_F_SHIFT) & 3u] : "",
-               (w[0] & FBG_INVOUT) ? " invout" : "", "", (w[0] & FBG_XORSET) ? "xor" : "or",
-               (w[0] & FBG_INV) ? " inv" : "", w[1], w[3], w[2], arg, w[5], w[4], w[7], w[6]);
+               (w[0] & FBG_INVOUT) ? " invout" : "", (w[0] & FBG_XORSET) ? "xor" : "or",
+               (w[0] & FBG_INV) ? " inv" : "", w[1], w[3], w[2], pat, w[5], w[4], w[7], w[6]);
     } else {
       snprintf(buf, sizeof buf, "%4zu %-3s %s r%u%s%s\n", pc / FBG_INS_WORDS, name,
                op == FBG_OP_OPR ? fs[(w[0] >> FBG_F_SHIFT) & 3u] : "", arg, (w[0] & FBG_INV) ? " inv" : "",
@@ -871,14 +901,15 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
 
 namespace {
 
-inline uint32_t set_value(const uint32_t *w, uint32_t lane, uint32_t i, uint64_t U0) {
+// A literal set at (lane, word index i, tile group U0), read the way the
+// kernels read it: P(i) from the pattern table.
+inline uint32_t set_value(const uint32_t *w, const uint32_t *table, uint32_t lane, uint32_t i, uint64_t U0) {
   bool x = (w[0] & FBG_XORSET) != 0;
   uint64_t lanemask = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
   uint64_t sel = (uint64_t)w[4] | ((uint64_t)w[5] << 32);
   uint64_t neg = (uint64_t)w[6] | ((uint64_t)w[7] << 32);
-  uint32_t pat = w[0] >> FBG_ARG_SHIFT;
   uint32_t V = ((lanemask >> lane) & 1u) ? ~0u : 0u;
-  uint32_t P = ((pat >> i) & 1u) ? ~0u : 0u;
+  uint32_t P = table[(w[0] >> FBG_ARG_SHIFT) + i];
   uint32_t Q;
   if (x)
     Q = (__builtin_popcountll(U0 & sel) & 1) ? ~0u : 0u;
@@ -907,25 +938,32 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
     uint32_t i = (uint32_t)(U & (W - 1));
     uint64_t U0 = U - i;
     uint32_t acc = ~0u, cur = 0;
+    // for W <= 16 the kernels find the pattern of clause k+1 through the
+    // index clause k carries in w0 bits 8..15; read it the same way
+    uint32_t chained = 0;
+    bool in_prefix = true;
     for (size_t pc = 0; pc < nins; pc++) {
       const uint32_t *w = &words[pc * FBG_INS_WORDS];
       uint32_t op = w[0] & 15u;
       uint32_t f = (w[0] >> FBG_F_SHIFT) & 3u;
       uint32_t arg = w[0] >> FBG_ARG_SHIFT;
       uint32_t inv = (w[0] & FBG_INV) ? ~0u : 0u;
+      if (op != FBG_OP_CL) in_prefix = false;
       switch (op) {
-        case FBG_OP_CL: {
-          // as the kernel reads it: P(i) from the pattern table, the rest
-          // from the instruction (pat cleared)
-          uint32_t wc[FBG_INS_WORDS];
-          for (int q = 0; q < FBG_INS_WORDS; q++) wc[q] = w[q];
-          wc[0] &= 0xFFFFu;
-          const uint32_t e = (w[0] >> FBG_F_SHIFT) & 0xFFu;
-          acc &= set_value(wc, lane, i, U0) | table[(size_t)e * W + i];
+        case FBG_OP_CL:
+          if (in_prefix && log2w <= 4) {
+            uint32_t wc[FBG_INS_WORDS];
+            for (int q = 0; q < FBG_INS_WORDS; q++) wc[q] = w[q];
+            const uint32_t own = pc == 0 ? (w[0] >> FBG_ARG_SHIFT) : chained * (uint32_t)W;
+            wc[0] = (wc[0] & 0xFFFFu) | (own << FBG_ARG_SHIFT);
+            acc &= set_value(wc, table, lane, i, U0);
+            chained = (w[0] >> FBG_F_SHIFT) & 0xFFu;
+          } else {
+            acc &= set_value(w, table, lane, i, U0);
+          }
           break;
-        }
-        case FBG_OP_LDL: cur = set_value(w, lane, i, U0); break;
-        case FBG_OP_OPL: cur = apply_f(f, cur, set_value(w, lane, i, U0)); break;
+        case FBG_OP_LDL: cur = set_value(w, table, lane, i, U0); break;
+        case FBG_OP_OPL: cur = apply_f(f, cur, set_value(w, table, lane, i, U0)); break;
         case FBG_OP_ST: R[arg] = cur; break;
         case FBG_OP_OPR: cur = apply_f(f, cur, R[arg] ^ inv); break;
         case FBG_OP_ACC: acc &= cur ^ inv; break;

@@ -52,6 +52,9 @@ int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int
 // per instruction, then the pattern table; returns the instruction count.
 uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words);
 
+// Number of leading clause (CL) instructions; no CL follows them.
+uint32_t leading_clauses(const Compiled &c);
+
 // Listing of an encoded program.
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w);
 

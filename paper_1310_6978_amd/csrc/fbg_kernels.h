@@ -8,15 +8,15 @@
 namespace fbg {
 
 struct EvalArgs {
-  const uint32_t *code;   // encoded program, FBG_INS_WORDS words per instruction
-  uint32_t nins;
+  const uint32_t *code;   // encoded program: instructions, then the pattern table
+  uint32_t nins;          // instructions
+  uint32_t ncl;           // leading clause instructions
   uint32_t nregs;         // LDS registers per word
   int32_t n;              // variables
-  int32_t pad0;
   uint64_t nslices;       // 2^max(n-5, 0) valid 32-bit words
   uint64_t ntiles;        // ceil(nslices / (64 W))
   uint64_t *out_count;    // MODE_COUNT
-  uint32_t *out32;        // MODE_DNF
+  uint32_t *out32;        // MODE_DNF (written); stored-DNF scans (read)
   uint64_t out_slices;    // MODE_DNF: words written (>= nslices, >= 2)
   uint32_t *tile_counts;  // MODE_TILECNT (out), MODE_ENUM (in)
   const uint64_t *tile_offsets;  // MODE_ENUM
@@ -27,16 +27,16 @@ struct EvalArgs {
 struct BatchProg {
   const uint32_t *code;
   uint32_t nins;
+  uint32_t ncl;
   uint32_t nregs;
   int32_t n;
-  int32_t pad0;
   uint64_t nslices;
   uint64_t ntiles;
 };
 
 struct BatchItem {
-  uint32_t prog;
-  uint32_t pad0;
+  uint32_t prog;    // index into the program table
+  uint32_t slot;    // index into the counts array
   uint64_t t0, t1;  // tile range [t0, t1)
 };
 
@@ -46,19 +46,20 @@ struct BatchArgs {
   uint32_t nitems;
   uint32_t max_regs;
   uint32_t *head;     // queue head, zeroed before the launch
-  uint64_t *counts;   // per program, zeroed before the launch
+  uint64_t *counts;   // per slot; the kernel adds to it
 };
 
 enum { EVAL_COUNT = 0, EVAL_DNF = 1, EVAL_TILECNT = 2, EVAL_ENUM = 3 };
 
-hipError_t launch_eval(int mode, int log2w, const EvalArgs &a, int grid, int block, size_t lds, hipStream_t s);
-hipError_t launch_batch(int log2w, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_eval(int mode, int log2w, bool gen, const EvalArgs &a, int grid, int block, size_t lds,
+                       hipStream_t s);
+hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_batch(int log2w, bool gen, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
                        hipStream_t s);
 uint64_t scan_block_count(uint64_t n);
 hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
-hipError_t launch_fill_words(uint64_t *p, uint64_t n, uint64_t v, uint64_t last, hipStream_t s);
 
 }  // namespace fbg
 

@@ -25,7 +25,7 @@ _STATUS = {0: "FBG_OK", -1: "FBG_E_INVAL", -2: "FBG_E_PARSE", -3: "FBG_E_RANGE",
 
 MAX_VARS = 48
 MAX_DNF_VARS = 40
-MAX_WORDS_PER_LANE = 16
+MAX_WORDS_PER_LANE = 32
 
 
 class FbgError(RuntimeError):
@@ -44,6 +44,11 @@ class ProgramInfo(ctypes.Structure):
 class Tune(ctypes.Structure):
     _fields_ = [("words_per_lane", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+class Item(ctypes.Structure):
+    _fields_ = [("prog", ctypes.c_int32), ("slot", ctypes.c_int32), ("tile_begin", ctypes.c_uint64),
+                ("tile_end", ctypes.c_uint64)]
 
 
 def _load():
@@ -66,6 +71,11 @@ def _load():
         "fbg_batch_count": (i32, [vp, vp, vp]),
         "fbg_batch_free": (None, [vp]),
         "fbg_count_batch": (i32, [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(Tune), vp]),
+        "fbg_enumerate_dnf": (i32, [vp, i32, vp, u64, vp, vp]),
+        "fbg_program_tiles": (u64, [vp, i32]),
+        "fbg_server_create": (i32, [i32, i32, i32, i32, ctypes.POINTER(vp)]),
+        "fbg_server_launch": (i32, [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(Item), i32, vp, i32, vp]),
+        "fbg_server_free": (None, [vp]),
         "fbg_program_emulate": (i32, [vp, i32, u64p, u64, u64p]),
         "fbg_program_disasm": (ctypes.c_int64, [vp, i32, ctypes.c_char_p, ctypes.c_int64]),
         "fbg_last_error": (ctypes.c_char_p, []),
@@ -83,9 +93,10 @@ lib = _load()
 
 # every symbol include/fbg.h declares
 EXPORTED = ("fbg_compile", "fbg_program_free", "fbg_program_get_info", "fbg_eval_dnf", "fbg_eval_dnf_tuned",
-            "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_batch_create", "fbg_batch_count",
-            "fbg_batch_free", "fbg_count_batch", "fbg_program_emulate", "fbg_program_disasm", "fbg_last_error",
-            "fbg_last_error_offset", "fbg_version")
+            "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_dnf", "fbg_batch_create",
+            "fbg_batch_count", "fbg_batch_free", "fbg_count_batch", "fbg_program_tiles", "fbg_server_create",
+            "fbg_server_launch", "fbg_server_free", "fbg_program_emulate", "fbg_program_disasm",
+            "fbg_last_error", "fbg_last_error_offset", "fbg_version")
 
 
 def _check(st):
@@ -210,6 +221,56 @@ def enumerate_models(prog, capacity, out=None, total=None, stream=None):
     ptr = _ptr(out) if capacity > 0 else ctypes.c_void_p(0)
     _check(lib.fbg_enumerate(prog.handle, ptr, int(capacity), _ptr(total), _stream(stream)))
     return out, total
+
+
+def enumerate_dnf(dnf, n, capacity, out=None, total=None, stream=None):
+    """fbg_enumerate_dnf: the models read off a stored DNF vector (device
+    tensor of max(1, 2^(n-6)) words)."""
+    if out is None:
+        out = _device_u64(capacity)
+    if total is None:
+        total = _device_u64(1)
+    ptr = _ptr(out) if capacity > 0 else ctypes.c_void_p(0)
+    _check(lib.fbg_enumerate_dnf(_ptr(dnf), int(n), ptr, int(capacity), _ptr(total), _stream(stream)))
+    return out, total
+
+
+def program_tiles(prog, words_per_lane):
+    """Tiles of 64 * words_per_lane words covering the program's valuations."""
+    return int(lib.fbg_program_tiles(prog.handle, int(words_per_lane)))
+
+
+class Server:
+    """fbg_server: launches over explicit work items that add into count
+    slots, with pinned staging buffers reused round-robin."""
+
+    def __init__(self, max_programs, max_items, words_per_lane, nbuf=4):
+        h = ctypes.c_void_p()
+        _check(lib.fbg_server_create(int(max_programs), int(max_items), int(words_per_lane), int(nbuf),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.words_per_lane = int(words_per_lane)
+        self.max_programs = int(max_programs)
+        self.max_items = int(max_items)
+
+    def launch(self, progs, items, counts, stream=None):
+        """progs: list of Program; items: list of (prog index, slot, tile_begin,
+        tile_end); counts: int64 device tensor of slots (added to)."""
+        arr = (ctypes.c_void_p * len(progs))(*[p.handle.value for p in progs])
+        its = (Item * len(items))(*[Item(int(a), int(b), int(c), int(d)) for a, b, c, d in items])
+        _check(lib.fbg_server_launch(self._h, arr, len(progs), its, len(items), _ptr(counts), counts.numel(),
+                                     _stream(stream)))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            lib.fbg_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Batch:

@@ -14,7 +14,7 @@ import workloads
 from paper_1310_6978_amd import fbg
 from tests.formula_gen import random_cnf, random_program
 
-WPL = [1, 2, 4, 8, 16]
+WPL = [1, 2, 4, 8, 16, 32]
 
 
 def check(text, n, wpl=WPL):
@@ -25,7 +25,19 @@ def check(text, n, wpl=WPL):
         got, c = p.emulate(w)
         assert np.array_equal(got, want), (w, text[:200])
         assert c == want_count
+    assert_clause_prefix(p)
     return p
+
+
+def assert_clause_prefix(p):
+    """The kernels run the CL instructions as a prefix loop: no CL may follow
+    another instruction, and the prefix length is n_clause_instr."""
+    ops = [line.split()[1] for line in p.disasm(1).splitlines()[1:]]
+    k = 0
+    while k < len(ops) and ops[k] == "CL":
+        k += 1
+    assert "CL" not in ops[k:], ops
+    assert k == p.info["n_clause_instr"]
 
 
 @pytest.mark.parametrize("seed", range(60))

@@ -22,7 +22,7 @@ from tests.formula_gen import random_cnf, random_program
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-WPL = [1, 2, 4, 8, 16]
+WPL = [1, 2, 4, 8, 16, 32]
 
 
 @pytest.fixture(scope="module")
@@ -256,3 +256,58 @@ def test_argument_errors(F):
     with pytest.raises(F.FbgError) as ei:
         F.eval_dnf(big, out=small)
     assert ei.value.status == F.FBG_E_RANGE
+
+
+def test_enumerate_from_stored_dnf(F):
+    for text, n in (workloads.triangle_free(6), workloads.baequ4(), workloads.random_3cnf(22, 93, 5),
+                    ("x0 | ~x0", 3), ("0", 9)):
+        want, total = oracle.models(text, n)
+        p = F.Program(text, n)
+        d = F.eval_dnf(p)
+        for cap in (0, 3, total + 1):
+            idx, tot = F.enumerate_dnf(d, n, cap)
+            got = host(idx)[:min(cap, total)]
+            assert int(host(tot)[0]) == total
+            assert np.array_equal(got, want[:min(cap, total)])
+
+
+def test_server_items_add_up(F):
+    import torch
+    rng = random.Random(7)
+    texts = [workloads.random_3cnf(rng.choice([12, 16, 20, 23]), 40, s) for s in range(6)]
+    texts.append(workloads.triangle_free(6))
+    texts.append(workloads.random_dag(18, 300, 4))
+    progs = [F.Program(t, n) for t, n in texts]
+    want = [oracle.count(t, n) for t, n in texts]
+    for wpl in (1, 8, 32):
+        sv = F.Server(len(progs), 64, wpl, nbuf=2)
+        counts = torch.zeros(len(progs) + 3, dtype=torch.int64, device="cuda")
+        # every program's tiles cut into random ranges, spread over launches
+        pending = []
+        for i, p in enumerate(progs):
+            nt = F.program_tiles(p, wpl)
+            cuts = sorted(set([0, nt] + [rng.randrange(0, nt + 1) for _ in range(3)]))
+            pending += [(i, i + 3, a, b) for a, b in zip(cuts, cuts[1:])]
+        rng.shuffle(pending)
+        while pending:
+            take, pending = pending[:5], pending[5:]
+            used = sorted(set(it[0] for it in take))
+            local = {g: k for k, g in enumerate(used)}
+            sv.launch([progs[g] for g in used], [(local[a], b, c, d) for a, b, c, d in take], counts)
+        got = host(counts).tolist()
+        assert got[:3] == [0, 0, 0]
+        assert got[3:] == want, wpl
+        sv.free()
+
+
+def test_server_rejects_bad_items(F):
+    import torch
+    p = F.Program("x1 | x7", 12)
+    sv = F.Server(4, 8, 4)
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    nt = F.program_tiles(p, 4)
+    for bad in ([(1, 0, 0, nt)], [(0, 2, 0, nt)], [(0, 0, 0, nt + 1)], [(0, 0, 2, 1)]):
+        with pytest.raises(F.FbgError) as ei:
+            sv.launch([p], bad, counts)
+        assert ei.value.status == F.FBG_E_INVAL
+    sv.free()
