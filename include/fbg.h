@@ -59,6 +59,10 @@ typedef enum {
 #define FBG_MAX_VARS 48
 #define FBG_MAX_DNF_VARS 40
 
+/* Largest number of variables in the text given to fbg_compile_assume (the
+   free ones must still number at most FBG_MAX_VARS). */
+#define FBG_MAX_TEXT_VARS 65536
+
 /* Largest number of words (32-bit slices) one lane evaluates per tile. */
 #define FBG_MAX_WORDS_PER_LANE 32
 
@@ -83,9 +87,15 @@ typedef struct {
 typedef struct {
   int32_t words_per_lane;  /* 1, 2, 4, 8, 16 or 32 (32-bit words per lane per tile) */
   int32_t grid_blocks;     /* blocks of 256 threads for persistent launches */
-  int32_t reserved0;
+  int32_t flags;           /* FBG_TUNE_* */
   int32_t reserved1;
 } fbg_tune;
+
+/* Uniform-cofactor evaluation: the index bits above the lane and word bits
+   are constant on a tile, so clauses with a true tile literal are skipped and
+   a clause made only of false tile literals ends the tile.  Same results;
+   data-dependent (usually much smaller) work. */
+#define FBG_TUNE_COFACTOR 1
 
 /*
  * fbg_compile -- turn formula text into a straight-line bitwise program and
@@ -101,12 +111,39 @@ typedef struct {
  */
 fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_program **out);
 
+/*
+ * fbg_compile_assume -- fbg_compile with killed variables (Section 3.3: a
+ * theory that fixes the value of a letter removes it from the search space;
+ * Section 3.4, step 3 of the counting procedure: each c-partition kills a set
+ * of letters; the reduced theory follows by substitution and Reduction,
+ * Section 4.1).
+ *   src     formula text over x0..x{n_vars-1}.
+ *   n_vars  0 <= n_vars <= FBG_MAX_TEXT_VARS.
+ *   assume  host array of n_vars entries (caller-owned, read during the
+ *           call): 0 or 1 kills xk to that constant, -1 leaves it free.  May
+ *           be NULL only when n_vars = 0.
+ *   flags   0 (reserved).
+ *   out     the program over the f free variables, renumbered in increasing
+ *           order: bit j of a valuation index is the j-th free variable.
+ * FBG_E_INVAL for an entry outside {-1, 0, 1}, FBG_E_RANGE if f exceeds
+ * FBG_MAX_VARS; otherwise as fbg_compile.  Synchronous.
+ */
+fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *assume, uint32_t flags,
+                              fbg_program **out);
+
 /* Release a program and its device copy.  NULL is a no-op.  The caller must
    make sure no launch that uses it is still pending. */
 void fbg_program_free(fbg_program *p);
 
 /* Metadata of a compiled program (host memory `out`). */
 fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out);
+
+/* Make tune->words_per_lane (non-zero) the program's default tiling, and
+   tune->flags (FBG_TUNE_COFACTOR) its default evaluation variant, for
+   fbg_count, fbg_eval_dnf, fbg_enumerate and new batches (the autotuner's
+   hook).  FBG_E_RANGE if the program's registers do not fit in LDS at that
+   tiling.  Not synchronised with launches in flight on other threads. */
+fbg_status fbg_program_set_tuning(fbg_program *p, const fbg_tune *tune);
 
 /*
  * fbg_eval_dnf -- write d = t(b_0..b_{n-1}) (Proposition "prop22") into
@@ -158,6 +195,15 @@ fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacit
 fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_tune *tune, fbg_batch **out);
 fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream);
 void fbg_batch_free(fbg_batch *b);
+
+/*
+ * fbg_batch_count_graph -- as fbg_batch_count, replayed from a HIP graph:
+ * the first call for a given d_counts captures the two launches (on a
+ * private stream) and instantiates the graph; later calls launch the graph on
+ * `stream`.  A different d_counts re-captures.  Same ordering rules as
+ * fbg_batch_count (one batch object per stream).
+ */
+fbg_status fbg_batch_count_graph(fbg_batch *b, uint64_t *d_counts, void *stream);
 fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d_counts, const fbg_tune *tune,
                            void *stream);
 
@@ -186,7 +232,8 @@ fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_
  *
  * fbg_server_create -- staging for up to max_programs programs and max_items
  *   items per launch, nbuf launches in flight (pinned host and device buffers
- *   allocated here, once).  words_per_lane fixes the tile size.
+ *   allocated here, once).  words_per_lane fixes the tile size; flags takes
+ *   FBG_TUNE_COFACTOR.
  * fbg_server_launch -- upload the program table and the items (asynchronous,
  *   from pinned memory) and launch one persistent batched kernel on `stream`.
  *   Items are validated on the host (FBG_E_INVAL on a bad index or range).
@@ -205,7 +252,7 @@ typedef struct fbg_server fbg_server; /* opaque, library-owned */
 
 uint64_t fbg_program_tiles(const fbg_program *p, int32_t words_per_lane);
 fbg_status fbg_server_create(int32_t max_programs, int32_t max_items, int32_t words_per_lane, int32_t nbuf,
-                             fbg_server **out);
+                             int32_t flags, fbg_server **out);
 fbg_status fbg_server_launch(fbg_server *s, const fbg_program *const *ps, int32_t np, const fbg_item *items,
                              int32_t nitems, uint64_t *d_counts, int32_t ncounts, void *stream);
 void fbg_server_free(fbg_server *s);

@@ -11,6 +11,7 @@ from .fbg import (  # noqa: F401
     Program,
     as_u64,
     compile,
+    compile_assume,
     count,
     count_batch,
     dnf_words,

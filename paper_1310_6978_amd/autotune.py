@@ -1,0 +1,97 @@
+"""Autotuner for the evaluator's tiling.
+
+The evaluator's cost per clause per tile is a fixed scalar part (instruction
+fetch, the lane and tile parts of the literal set) plus one VALU operation
+per word, so more words per lane amortise the fixed part, while fewer words
+per lane give small valuation spaces more tiles (and so more waves).  The
+tuner times fbg_count on the candidate tilings with HIP events, keeps the
+fastest, and caches the choice per (device architecture, n, program-size
+bucket, clause-only or not) in a JSON file (FBG_TUNE_CACHE, default
+~/.cache/fbg/tune.json).  It then makes the choice the program's default
+through fbg_program_set_tuning.
+"""
+
+import json
+import math
+import os
+
+from . import fbg
+
+CANDIDATES = (4, 8, 16, 32)
+
+
+def _cache_path():
+    return os.environ.get("FBG_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "fbg", "tune.json"))
+
+
+def _arch():
+    import torch
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def key_of(prog):
+    info = prog.info
+    size = max(1, int(info["n_instr"]))
+    general = int(info["n_instr"]) > int(info["n_clause_instr"])
+    return "%s|n=%d|L=%d|gen=%d" % (_arch(), prog.n, int(math.log2(size)), int(general))
+
+
+class Tuner:
+    def __init__(self, path=None, candidates=CANDIDATES, reps=3):
+        self.path = path or _cache_path()
+        self.candidates = tuple(candidates)
+        self.reps = reps
+        self.table = {}
+        if os.path.exists(self.path):
+            try:
+                with open(self.path) as f:
+                    self.table = json.load(f)
+            except (OSError, ValueError):
+                self.table = {}
+
+    def measure(self, prog):
+        """{words_per_lane: ms} for one count of `prog` at each candidate."""
+        import torch
+        out = torch.empty(1, dtype=torch.int64, device="cuda")
+        res = {}
+        for w in self.candidates:
+            try:
+                fbg.count(prog, out=out, words_per_lane=w)  # warm-up
+            except fbg.FbgError:
+                continue  # registers do not fit at this tiling
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(self.reps):
+                fbg.count(prog, out=out, words_per_lane=w)
+            b.record()
+            torch.cuda.synchronize()
+            res[w] = a.elapsed_time(b) / self.reps
+        return res
+
+    def apply(self, prog, save=True):
+        """Set the program's default tiling from the cache, measuring on a miss.
+        Returns the chosen words per lane."""
+        k = key_of(prog)
+        w = self.table.get(k, {}).get("words_per_lane")
+        if w is None:
+            times = self.measure(prog)
+            w = min(times, key=times.get)
+            self.table[k] = {"words_per_lane": w, "ms": times}
+            if save:
+                self.save()
+        prog.set_tuning(w)
+        return w
+
+    def save(self):
+        d = os.path.dirname(self.path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.table, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)

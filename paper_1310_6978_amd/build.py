@@ -1,6 +1,6 @@
 """Build libfbg.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc.
 
-    python -m paper_1310_6978_amd.build
+    python paper_1310_6978_amd/build.py
 """
 
 import os

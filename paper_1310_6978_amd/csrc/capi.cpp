@@ -139,13 +139,19 @@ struct fbg_program {
   uint32_t ncl = 0;  // leading clause instructions
   int auto_log2w = 0;
   uint64_t nslices = 1;
+  bool cofactor = false;  // default evaluation variant (fbg_program_set_tuning)
   bool general() const { return c.code.size() > ncl; }
+  // kernel variant: bit 0 = general code after the clauses, bit 1 = cofactor
+  int variant(const fbg_tune *tune) const {
+    const bool cof = cofactor || (tune && (tune->flags & FBG_TUNE_COFACTOR));
+    return (general() ? 1 : 0) | (cof ? 2 : 0);
+  }
 };
 
 struct fbg_batch {
   int device = -1;
   int log2w = 0;
-  bool gen = false;
+  int var = 0;
   int grid = 1;
   int block = 256;
   size_t lds = 0;
@@ -155,12 +161,17 @@ struct fbg_batch {
   fbg::BatchProg *d_progs = nullptr;
   fbg::BatchItem *d_items = nullptr;
   uint32_t *d_head = nullptr;
+  // captured graph of (zero fill, persistent kernel) for one counts pointer
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t *graph_counts = nullptr;
 };
 
 struct fbg_server {
   int device = -1;
   int log2w = 0;
   int32_t max_programs = 0, max_items = 0, nbuf = 0, next = 0;
+  bool cofactor = false;
   struct Slot {
     char *h = nullptr;  // pinned staging: programs then items
     char *d = nullptr;  // device copy
@@ -301,17 +312,16 @@ const char *fbg_version(void) { return "fbg 0.2 (gfx950)"; }
 const char *fbg_last_error(void) { return g_err.c_str(); }
 int64_t fbg_last_error_offset(void) { return g_err_off; }
 
-fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_program **out) {
-  if (!out) return fail(FBG_E_INVAL, "out is NULL");
-  *out = nullptr;
-  if (!src) return fail(FBG_E_INVAL, "src is NULL");
-  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
-  if (n_vars < 0 || n_vars > FBG_MAX_VARS) return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_VARS);
+}  // extern "C"
+
+namespace {
+
+fbg_status compile_common(const char *src, int32_t n_vars, const int8_t *assume, fbg_program **out) {
   fbg_program *p = new (std::nothrow) fbg_program();
   if (!p) return fail(FBG_E_NOMEM, "out of host memory");
   std::string msg;
   int64_t off = -1;
-  int st = fbg::compile_formula(src, n_vars, p->c, msg, off);
+  int st = fbg::compile_formula(src, n_vars, p->c, msg, off, assume);
   if (st != FBG_OK) {
     delete p;
     g_err = msg;
@@ -319,7 +329,7 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
     if (off >= 0) g_err += " (offset " + std::to_string(off) + ")";
     return (fbg_status)st;
   }
-  p->nslices = slices_of(n_vars);
+  p->nslices = slices_of(p->c.n);
   p->ncl = fbg::leading_clauses(p->c);
   size_t total = 0;
   for (int l = 0; l <= kMaxLog2W; l++) {
@@ -359,6 +369,38 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
   return FBG_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_program **out) {
+  if (!out) return fail(FBG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!src) return fail(FBG_E_INVAL, "src is NULL");
+  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
+  if (n_vars < 0 || n_vars > FBG_MAX_VARS) return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_VARS);
+  return compile_common(src, n_vars, nullptr, out);
+}
+
+fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *assume, uint32_t flags,
+                              fbg_program **out) {
+  if (!out) return fail(FBG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!src) return fail(FBG_E_INVAL, "src is NULL");
+  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
+  if (n_vars < 0 || n_vars > FBG_MAX_TEXT_VARS)
+    return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_TEXT_VARS);
+  if (n_vars > 0 && !assume) return fail(FBG_E_INVAL, "assume is NULL");
+  int32_t nfree = 0;
+  for (int32_t k = 0; k < n_vars; k++) {
+    if (assume[k] < -1 || assume[k] > 1)
+      return fail(FBG_E_INVAL, "assume[%d] = %d (must be -1, 0 or 1)", k, (int)assume[k]);
+    nfree += assume[k] < 0;
+  }
+  if (nfree > FBG_MAX_VARS) return fail(FBG_E_RANGE, "%d free variables (max %d)", nfree, FBG_MAX_VARS);
+  return compile_common(src, n_vars, assume, out);
+}
+
 void fbg_program_free(fbg_program *p) {
   if (!p) return;
   if (p->d_code) CodeArena::of(p->device).release(p->d_code, p->code_class);
@@ -376,6 +418,19 @@ fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out) {
   out->n_clause_instr = (int32_t)p->ncl;
   out->words_per_lane = 1 << p->auto_log2w;
   out->dnf_words = dnf_words_of(p->c.n);
+  return FBG_OK;
+}
+
+fbg_status fbg_program_set_tuning(fbg_program *p, const fbg_tune *tune) {
+  if (!p || !tune) return fail(FBG_E_INVAL, "NULL argument");
+  int l = p->auto_log2w;
+  fbg_status st;
+  if (tune->words_per_lane && (st = parse_wpl(tune->words_per_lane, l))) return st;
+  int wpb;
+  size_t lds;
+  if ((st = block_shape((uint32_t)p->c.nregs, l, wpb, lds))) return st;
+  p->auto_log2w = l;
+  p->cofactor = (tune->flags & FBG_TUNE_COFACTOR) != 0;
   return FBG_OK;
 }
 
@@ -401,7 +456,7 @@ fbg_status fbg_count_tuned(const fbg_program *p, uint64_t *d_count, const fbg_tu
   a.out_count = d_count;
   e = fbg::launch_set_u64(d_count, 0, s);
   if (e != hipSuccess) return hip_fail(e, "launch");
-  e = fbg::launch_eval(fbg::EVAL_COUNT, g.log2w, p->general(), a, g.grid, g.block, g.lds, s);
+  e = fbg::launch_eval(fbg::EVAL_COUNT, g.log2w, p->variant(tune), a, g.grid, g.block, g.lds, s);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the count kernel");
 }
 
@@ -424,7 +479,7 @@ fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t ou
   a.out32 = (uint32_t *)d_out;
   a.out_slices = 2 * need;
   hipError_t e =
-      fbg::launch_eval(fbg::EVAL_DNF, g.log2w, p->general(), a, g.grid, g.block, g.lds, (hipStream_t)stream);
+      fbg::launch_eval(fbg::EVAL_DNF, g.log2w, p->variant(tune), a, g.grid, g.block, g.lds, (hipStream_t)stream);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the DNF kernel");
 }
 
@@ -442,10 +497,10 @@ fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacit
   Geometry g;
   if ((st = geometry(p, nullptr, g))) return st;
   hipStream_t s = (hipStream_t)stream;
-  const bool gen = p->general();
+  const int var = p->variant(nullptr);
   return enumerate_with(base_args(p, g.log2w), d_idx, capacity, d_total, s,
                         [&](int mode, const fbg::EvalArgs &a) {
-                          return fbg::launch_eval(mode, g.log2w, gen, a, g.grid, g.block, g.lds, s);
+                          return fbg::launch_eval(mode, g.log2w, var, a, g.grid, g.block, g.lds, s);
                         });
 }
 
@@ -500,10 +555,10 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     }
   }
   uint32_t max_regs = 0;
-  bool gen = false;
+  int var = 0;
   for (int32_t i = 0; i < np; i++) {
     max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
-    gen = gen || ps[i]->general();
+    var |= ps[i]->variant(tune);
   }
   while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
   int wpb;
@@ -548,7 +603,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   if (!b) return fail(FBG_E_NOMEM, "out of host memory");
   b->device = dev;
   b->log2w = l;
-  b->gen = gen;
+  b->var = var;
   b->np = np;
   b->nitems = (uint32_t)sorted.size();
   b->max_regs = max_regs;
@@ -587,12 +642,45 @@ fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream) {
   a.max_regs = b->max_regs;
   a.head = b->d_head;
   a.counts = d_counts;
-  e = fbg::launch_batch(b->log2w, b->gen, a, b->grid, b->block, b->lds, s);
+  e = fbg::launch_batch(b->log2w, b->var, a, b->grid, b->block, b->lds, s);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the batch kernel");
+}
+
+fbg_status fbg_batch_count_graph(fbg_batch *b, uint64_t *d_counts, void *stream) {
+  if (!b) return fail(FBG_E_INVAL, "batch is NULL");
+  if (!d_counts) return fail(FBG_E_INVAL, "d_counts is NULL");
+  fbg_status st = check_device(b->device);
+  if (st) return st;
+  hipError_t e;
+  if (!b->graph_exec || b->graph_counts != d_counts) {
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+    hipStream_t cs;
+    if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      st = fbg_batch_count(b, d_counts, cs);  // kernels only: no memset node, no allocation
+      hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+      if (st == FBG_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
+      if (st == FBG_OK && (e2 = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+        st = hip_fail(e2, "hipGraphInstantiate");
+    } else {
+      st = hip_fail(e, "hipStreamBeginCapture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st) return st;
+    b->graph_counts = d_counts;
+  }
+  e = hipGraphLaunch(b->graph_exec, (hipStream_t)stream);
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 void fbg_batch_free(fbg_batch *b) {
   if (!b) return;
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_progs) (void)hipFree(b->d_progs);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_head) (void)hipFree(b->d_head);
@@ -615,7 +703,7 @@ fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d
 // ------------------------------------------------------------------ serving
 
 fbg_status fbg_server_create(int32_t max_programs, int32_t max_items, int32_t words_per_lane, int32_t nbuf,
-                             fbg_server **out) {
+                             int32_t flags, fbg_server **out) {
   if (!out) return fail(FBG_E_INVAL, "out is NULL");
   *out = nullptr;
   if (max_programs <= 0 || max_items <= 0 || nbuf <= 0 || nbuf > 64) return fail(FBG_E_INVAL, "bad server sizes");
@@ -632,6 +720,7 @@ fbg_status fbg_server_create(int32_t max_programs, int32_t max_items, int32_t wo
   sv->max_programs = max_programs;
   sv->max_items = max_items;
   sv->nbuf = nbuf;
+  sv->cofactor = (flags & FBG_TUNE_COFACTOR) != 0;
   sv->slots.resize((size_t)nbuf);
   const size_t bytes = (size_t)max_programs * sizeof(fbg::BatchProg) + (size_t)max_items * sizeof(fbg::BatchItem);
   for (auto &sl : sv->slots) {
@@ -658,11 +747,11 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   if (st) return st;
   const int l = sv->log2w;
   uint32_t max_regs = 0;
-  bool gen = false;
+  int var = sv->cofactor ? 2 : 0;
   for (int32_t i = 0; i < np; i++) {
     if ((st = check_program(ps[i]))) return st;
     max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
-    gen = gen || ps[i]->general();
+    var |= ps[i]->variant(nullptr);
   }
   // validate every item on the host: the kernel trusts them
   for (int32_t k = 0; k < nitems; k++) {
@@ -707,7 +796,7 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   const int cus = cu_count(sv->device);
   const int grid =
       (int)std::max<int64_t>(1, std::min<int64_t>((nitems + wpb - 1) / wpb, (int64_t)cus * (32 / wpb)));
-  e = fbg::launch_batch(l, gen, a, grid, 64 * wpb, lds, s);
+  e = fbg::launch_batch(l, var, a, grid, 64 * wpb, lds, s);
   if (e == hipSuccess) e = hipEventRecord(sl.done, s);
   sl.used = true;
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the server slice");

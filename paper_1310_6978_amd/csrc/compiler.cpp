@@ -115,6 +115,12 @@ struct Parser {
   int64_t off = -1;
   int status = FBG_OK;
 
+  // Killed variables (Section 3.3): assume[k] = 0 or 1 replaces xk by that
+  // constant, which the graph folds away (the Reduction of Section 4.1);
+  // free variables take the index renum[k].  Both null: every xk is free.
+  const int8_t *assume = nullptr;
+  const int32_t *renum = nullptr;
+
   Parser(const char *s, int nv, Graph &gr) : src(s), n(nv), g(gr) {}
 
   bool fail(int st, int64_t at, const std::string &m) {
@@ -207,7 +213,10 @@ struct Parser {
       case Tok::VAR:
         if (t.val >= n) return fail(FBG_E_RANGE, t.pos, "variable x" + std::to_string(t.val) + " >= n");
         p++;
-        e = g.var((int)t.val);
+        if (assume && assume[t.val] >= 0)
+          e = assume[t.val] ? kTrue : kFalse;
+        else
+          e = g.var(renum ? renum[t.val] : (int)t.val);
         return true;
       case Tok::NAME: {
         auto it = names.find(t.name);
@@ -691,7 +700,10 @@ int allocate_registers(std::vector<HIns> &code, int nv) {
 
 struct CompileJob {
   const char *src;
-  int n;
+  int n;        // variables of the text
+  int n_free;   // variables of the program
+  const int8_t *assume = nullptr;
+  const int32_t *renum = nullptr;
   Compiled *out;
   std::string msg;
   int64_t off = -1;
@@ -702,6 +714,8 @@ void *compile_thread(void *arg) {
   CompileJob *job = (CompileJob *)arg;
   Graph g;
   Parser ps(job->src, job->n, g);
+  ps.assume = job->assume;
+  ps.renum = job->renum;
   Edge root;
   if (!ps.program(root)) {
     job->status = ps.status;
@@ -711,7 +725,7 @@ void *compile_thread(void *arg) {
   }
   Compiled &c = *job->out;
   c = Compiled();
-  c.n = job->n;
+  c.n = job->n_free;
   if (root == kFalse || root == kTrue) {
     c.const_value = root == kTrue ? 1 : 0;
     if (root == kFalse) {
@@ -732,11 +746,22 @@ void *compile_thread(void *arg) {
 
 }  // namespace
 
-int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset) {
+int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset,
+                    const int8_t *assume) {
   CompileJob job;
   job.src = src;
   job.n = n;
+  job.n_free = n;
   job.out = &out;
+  std::vector<int32_t> renum;
+  if (assume) {
+    renum.resize((size_t)n);
+    int f = 0;
+    for (int k = 0; k < n; k++) renum[(size_t)k] = assume[k] < 0 ? f++ : -1;
+    job.n_free = f;
+    job.assume = assume;
+    job.renum = renum.data();
+  }
   // Deeply nested text recurses in the parser and code generator; give the
   // work a large stack of its own.
   pthread_attr_t attr;
@@ -814,7 +839,24 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
   const size_t base = words.size();
   const int W = 1 << log2w;
   std::vector<uint32_t> pats{0u};  // pattern table, entry 0 = no per-word literal
-  for (const HIns &h : c.code) {
+  // Clauses whose literals are all tile variables at this tiling go first
+  // (stable), so that the uniform-cofactor kernel meets a clause that kills a
+  // whole tile as early as possible.  Within the clause prefix the order is
+  // free: every clause is ANDed into the same accumulator.
+  const int tile_bit = FBG_TILE_BASE_BIT + log2w;
+  std::vector<size_t> order;
+  order.reserve(c.code.size());
+  size_t ncl = 0;
+  while (ncl < c.code.size() && c.code[ncl].op == FBG_OP_CL) ncl++;
+  for (int pass = 0; pass < 2; pass++)
+    for (size_t k = 0; k < ncl; k++) {
+      bool tile_only = true;
+      for (const Lit &l : c.code[k].ls.lits) tile_only = tile_only && l.k >= tile_bit;
+      if (tile_only == (pass == 0)) order.push_back(k);
+    }
+  for (size_t k = ncl; k < c.code.size(); k++) order.push_back(k);
+  for (size_t idx : order) {
+    const HIns &h = c.code[idx];
     uint32_t w[FBG_INS_WORDS] = {0, 0, 0, 0, 0, 0, 0, 0};
     w[0] = h.op;
     if (h.op == FBG_OP_CL || h.op == FBG_OP_LDL || h.op == FBG_OP_OPL) {

@@ -51,10 +51,10 @@ struct BatchArgs {
 
 enum { EVAL_COUNT = 0, EVAL_DNF = 1, EVAL_TILECNT = 2, EVAL_ENUM = 3 };
 
-hipError_t launch_eval(int mode, int log2w, bool gen, const EvalArgs &a, int grid, int block, size_t lds,
+hipError_t launch_eval(int mode, int log2w, int var, const EvalArgs &a, int grid, int block, size_t lds,
                        hipStream_t s);
 hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hipStream_t s);
-hipError_t launch_batch(int log2w, bool gen, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_batch(int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
                        hipStream_t s);
 uint64_t scan_block_count(uint64_t n);

@@ -8,14 +8,15 @@
 // synthesised in registers, and all bitwise work is VALU integer logic.
 //
 // Kernels:
-//   k_eval<LOG2W, MODE, GEN>  one program, persistent grid-stride over tiles;
+//   k_eval<LOG2W, MODE, VAR>  one program, persistent grid-stride over tiles;
 //                         MODE_COUNT   popcount -> wave sum -> 64-bit atomic
 //                         MODE_DNF     store the words (coalesced)
 //                         MODE_TILECNT per-tile model counts (enumeration 1)
 //                         MODE_ENUM    ascending model indices (enumeration 2)
-//                         GEN = false for programs made of clauses only
+//                         VAR bit 0 (GEN): programs with more than clauses
+//                         VAR bit 1 (COF): the uniform-cofactor variant
 //   k_dnf_scan<MODE>      the two enumeration passes over a stored DNF vector
-//   k_batch<LOG2W, GEN>   many programs, persistent waves popping work items
+//   k_batch<LOG2W, VAR>   many programs, persistent waves popping work items
 //                         (program, tile range) from a device queue
 //   k_scan_*              exclusive scan of per-tile counts
 //   k_zero_*, k_set_u64   fills (used instead of memset so that a caller may
@@ -55,7 +56,14 @@ __device__ __forceinline__ uint32_t lane_part(uint64_t lanemask) {
 // Interpret one program over the W words of this lane in tile group U0.
 // The first ncl instructions are clauses (the code generator emits them
 // first); GEN = false means there is nothing else.
-template <int LOG2W, bool GEN>
+//
+// COF = true is the uniform-cofactor variant: the tile bits of the index are
+// constants on the whole tile, so a clause with a true tile literal holds on
+// the tile and is skipped, and a clause whose only literals are false tile
+// literals is false on the whole tile, which ends the tile (acc = 0).  The
+// result is the same; the work depends on the data.  The encoder puts the
+// clauses made only of tile literals first.
+template <int LOG2W, bool GEN, bool COF>
 __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g, uint32_t nins, uint32_t ncl,
                                             uint64_t U0, uint32_t lane, uint32_t (&acc)[1 << LOG2W],
                                             uint32_t *__restrict__ regs) {
@@ -68,7 +76,25 @@ __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g,
   // ---- clauses: acc &= mconst | V(lane) | P(i) | Q(U0), one v_bitop3 per
   // word.  Branch-free, so acc stays in place across iterations.
   code_ptr w = code;
-  if (LOG2W <= 4 && ncl > 0) {
+  if (COF) {
+    for (uint32_t k = 0; k < ncl; ++k, w += FBG_INS_WORDS) {
+      const u32x8 ins = *(const __attribute__((address_space(4))) u32x8 *)w;
+      const uint64_t sel = (uint64_t)ins[4] | ((uint64_t)ins[5] << 32);
+      const uint64_t neg = (uint64_t)ins[6] | ((uint64_t)ins[7] << 32);
+      if ((U0 & sel) != neg) continue;  // a true tile literal: the clause holds on the tile
+      const uint64_t lm = (uint64_t)ins[2] | ((uint64_t)ins[3] << 32);
+      const uint32_t poff = ins[0] >> FBG_ARG_SHIFT;  // entry 0 is the all-zero pattern
+      if (lm == 0 && ins[1] == 0u && poff == 0u) {    // only false tile literals: the tile is dead
+#pragma unroll
+        for (int i = 0; i < W; i++) acc[i] = 0u;
+        return;
+      }
+      const uint32_t T = __builtin_amdgcn_inverse_ballot_w64(lm) ? ~0u : ins[1];
+      const code_ptr P = table + poff;
+#pragma unroll
+      for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
+    }
+  } else if (LOG2W <= 4 && ncl > 0) {
     // Software-pipelined: while clause k runs on the VALU, the scalar unit
     // already fetches clause k+1 and its pattern entry (whose index clause k
     // carries in w0 bits 8..15), so neither load latency is exposed.  Reads
@@ -270,7 +296,7 @@ __device__ __forceinline__ void tile_compact(const uint32_t (&acc)[1 << LOG2W], 
   }
 }
 
-template <int LOG2W, int MODE, bool GEN>
+template <int LOG2W, int MODE, int VAR>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
   constexpr int W = 1 << LOG2W;
   extern __shared__ uint32_t lds[];
@@ -287,7 +313,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
       if (a.tile_counts[t] == 0u) continue;  // no model in this tile
     }
     uint32_t acc[W];
-    run_program<LOG2W, GEN>(a.code, a.nins, a.ncl, U0, lane, acc, regs);
+    run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(a.code, a.nins, a.ncl, U0, lane, acc, regs);
     mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);
     if (MODE == MODE_COUNT) {
       uint32_t c = 0;
@@ -342,7 +368,7 @@ __global__ __launch_bounds__(256) void k_dnf_scan(EvalArgs a) {
 
 // ---------------------------------------------------------------- batches
 
-template <int LOG2W, bool GEN>
+template <int LOG2W, int VAR>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
   constexpr int W = 1 << LOG2W;
   extern __shared__ uint32_t lds[];
@@ -360,7 +386,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
     for (uint64_t t = it.t0; t < it.t1; ++t) {
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
-      run_program<LOG2W, GEN>(p.code, p.nins, p.ncl, U0, lane, acc, regs);
+      run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(p.code, p.nins, p.ncl, U0, lane, acc, regs);
       mask_tail<LOG2W>(acc, U0, lane, p.nslices, p.n);
       uint32_t c = 0;
 #pragma unroll
@@ -455,36 +481,41 @@ __global__ void k_set_u64(uint64_t *p, uint64_t v) {
 
 namespace {
 
-template <int MODE, bool GEN>
+template <int MODE, int VAR>
 hipError_t launch_eval_w(int log2w, const EvalArgs &a, int grid, int block, size_t lds, hipStream_t s) {
   switch (log2w) {
-    case 0: hipLaunchKernelGGL((dev::k_eval<0, MODE, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 1: hipLaunchKernelGGL((dev::k_eval<1, MODE, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((dev::k_eval<2, MODE, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((dev::k_eval<3, MODE, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((dev::k_eval<4, MODE, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((dev::k_eval<5, MODE, GEN>), dim3(grid), dim3(block), lds, s, a); break;
+    case 0: hipLaunchKernelGGL((dev::k_eval<0, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((dev::k_eval<1, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((dev::k_eval<2, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((dev::k_eval<3, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((dev::k_eval<4, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 5: hipLaunchKernelGGL((dev::k_eval<5, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <int MODE>
-hipError_t launch_eval_mode(int log2w, bool gen, const EvalArgs &a, int grid, int block, size_t lds,
+hipError_t launch_eval_mode(int log2w, int var, const EvalArgs &a, int grid, int block, size_t lds,
                             hipStream_t s) {
-  return gen ? launch_eval_w<MODE, true>(log2w, a, grid, block, lds, s)
-             : launch_eval_w<MODE, false>(log2w, a, grid, block, lds, s);
+  switch (var) {
+    case 0: return launch_eval_w<MODE, 0>(log2w, a, grid, block, lds, s);
+    case 1: return launch_eval_w<MODE, 1>(log2w, a, grid, block, lds, s);
+    case 2: return launch_eval_w<MODE, 2>(log2w, a, grid, block, lds, s);
+    case 3: return launch_eval_w<MODE, 3>(log2w, a, grid, block, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
-template <bool GEN>
+template <int VAR>
 hipError_t launch_batch_w(int log2w, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s) {
   switch (log2w) {
-    case 0: hipLaunchKernelGGL((dev::k_batch<0, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 1: hipLaunchKernelGGL((dev::k_batch<1, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((dev::k_batch<2, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((dev::k_batch<3, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((dev::k_batch<4, GEN>), dim3(grid), dim3(block), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((dev::k_batch<5, GEN>), dim3(grid), dim3(block), lds, s, a); break;
+    case 0: hipLaunchKernelGGL((dev::k_batch<0, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((dev::k_batch<1, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((dev::k_batch<2, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((dev::k_batch<3, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((dev::k_batch<4, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 5: hipLaunchKernelGGL((dev::k_batch<5, VAR>), dim3(grid), dim3(block), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -492,13 +523,13 @@ hipError_t launch_batch_w(int log2w, const BatchArgs &a, int grid, int block, si
 
 }  // namespace
 
-hipError_t launch_eval(int mode, int log2w, bool gen, const EvalArgs &a, int grid, int block, size_t lds,
+hipError_t launch_eval(int mode, int log2w, int var, const EvalArgs &a, int grid, int block, size_t lds,
                        hipStream_t s) {
   switch (mode) {
-    case dev::MODE_COUNT: return launch_eval_mode<dev::MODE_COUNT>(log2w, gen, a, grid, block, lds, s);
-    case dev::MODE_DNF: return launch_eval_mode<dev::MODE_DNF>(log2w, gen, a, grid, block, lds, s);
-    case dev::MODE_TILECNT: return launch_eval_mode<dev::MODE_TILECNT>(log2w, gen, a, grid, block, lds, s);
-    case dev::MODE_ENUM: return launch_eval_mode<dev::MODE_ENUM>(log2w, gen, a, grid, block, lds, s);
+    case dev::MODE_COUNT: return launch_eval_mode<dev::MODE_COUNT>(log2w, var, a, grid, block, lds, s);
+    case dev::MODE_DNF: return launch_eval_mode<dev::MODE_DNF>(log2w, var, a, grid, block, lds, s);
+    case dev::MODE_TILECNT: return launch_eval_mode<dev::MODE_TILECNT>(log2w, var, a, grid, block, lds, s);
+    case dev::MODE_ENUM: return launch_eval_mode<dev::MODE_ENUM>(log2w, var, a, grid, block, lds, s);
   }
   return hipErrorInvalidValue;
 }
@@ -513,9 +544,14 @@ hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hip
   return hipGetLastError();
 }
 
-hipError_t launch_batch(int log2w, bool gen, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s) {
-  return gen ? launch_batch_w<true>(log2w, a, grid, block, lds, s)
-             : launch_batch_w<false>(log2w, a, grid, block, lds, s);
+hipError_t launch_batch(int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s) {
+  switch (var) {
+    case 0: return launch_batch_w<0>(log2w, a, grid, block, lds, s);
+    case 1: return launch_batch_w<1>(log2w, a, grid, block, lds, s);
+    case 2: return launch_batch_w<2>(log2w, a, grid, block, lds, s);
+    case 3: return launch_batch_w<3>(log2w, a, grid, block, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,

@@ -43,7 +43,10 @@ class ProgramInfo(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("words_per_lane", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+TUNE_COFACTOR = 1
 
 
 class Item(ctypes.Structure):
@@ -54,14 +57,21 @@ class Item(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libfbg.so is not built (run __graft_entry__.build() or "
-                          "python -m paper_1310_6978_amd.build)")
+                          "python paper_1310_6978_amd/build.py)")
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # loading torch first makes libfbg bind to that runtime, so device
+    # pointers and streams from torch are valid in libfbg's calls (loading
+    # libfbg first would bring a second runtime into the process)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
     u64p = ctypes.POINTER(ctypes.c_uint64)
     sigs = {
         "fbg_compile": (i32, [ctypes.c_char_p, i32, u32, ctypes.POINTER(vp)]),
+        "fbg_compile_assume": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_int8), u32, ctypes.POINTER(vp)]),
         "fbg_program_free": (None, [vp]),
         "fbg_program_get_info": (i32, [vp, ctypes.POINTER(ProgramInfo)]),
+        "fbg_program_set_tuning": (i32, [vp, ctypes.POINTER(Tune)]),
         "fbg_eval_dnf": (i32, [vp, vp, u64, vp]),
         "fbg_eval_dnf_tuned": (i32, [vp, vp, u64, ctypes.POINTER(Tune), vp]),
         "fbg_count": (i32, [vp, vp, vp]),
@@ -69,11 +79,12 @@ def _load():
         "fbg_enumerate": (i32, [vp, vp, u64, vp, vp]),
         "fbg_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(Tune), ctypes.POINTER(vp)]),
         "fbg_batch_count": (i32, [vp, vp, vp]),
+        "fbg_batch_count_graph": (i32, [vp, vp, vp]),
         "fbg_batch_free": (None, [vp]),
         "fbg_count_batch": (i32, [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(Tune), vp]),
         "fbg_enumerate_dnf": (i32, [vp, i32, vp, u64, vp, vp]),
         "fbg_program_tiles": (u64, [vp, i32]),
-        "fbg_server_create": (i32, [i32, i32, i32, i32, ctypes.POINTER(vp)]),
+        "fbg_server_create": (i32, [i32, i32, i32, i32, i32, ctypes.POINTER(vp)]),
         "fbg_server_launch": (i32, [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(Item), i32, vp, i32, vp]),
         "fbg_server_free": (None, [vp]),
         "fbg_program_emulate": (i32, [vp, i32, u64p, u64, u64p]),
@@ -92,9 +103,10 @@ def _load():
 lib = _load()
 
 # every symbol include/fbg.h declares
-EXPORTED = ("fbg_compile", "fbg_program_free", "fbg_program_get_info", "fbg_eval_dnf", "fbg_eval_dnf_tuned",
+EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_program_free", "fbg_program_get_info", "fbg_program_set_tuning",
+            "fbg_eval_dnf", "fbg_eval_dnf_tuned",
             "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_dnf", "fbg_batch_create",
-            "fbg_batch_count", "fbg_batch_free", "fbg_count_batch", "fbg_program_tiles", "fbg_server_create",
+            "fbg_batch_count", "fbg_batch_count_graph", "fbg_batch_free", "fbg_count_batch", "fbg_program_tiles", "fbg_server_create",
             "fbg_server_launch", "fbg_server_free", "fbg_program_emulate", "fbg_program_disasm",
             "fbg_last_error", "fbg_last_error_offset", "fbg_version")
 
@@ -104,10 +116,10 @@ def _check(st):
         raise FbgError(st, lib.fbg_last_error().decode(errors="replace"), lib.fbg_last_error_offset())
 
 
-def _tune(words_per_lane=0, grid_blocks=0):
-    if not words_per_lane and not grid_blocks:
+def _tune(words_per_lane=0, grid_blocks=0, cofactor=False):
+    if not words_per_lane and not grid_blocks and not cofactor:
         return None
-    return ctypes.byref(Tune(int(words_per_lane), int(grid_blocks), 0, 0))
+    return ctypes.byref(Tune(int(words_per_lane), int(grid_blocks), TUNE_COFACTOR if cofactor else 0, 0))
 
 
 def _stream(stream):
@@ -138,16 +150,23 @@ def dnf_words(n):
 class Program:
     """A compiled formula, resident on the device it was compiled on."""
 
-    def __init__(self, src, n, flags=0):
+    def __init__(self, src, n, flags=0, assume=None):
         h = ctypes.c_void_p()
         if isinstance(src, str):
             src = src.encode()
-        _check(lib.fbg_compile(src, int(n), int(flags), ctypes.byref(h)))
+        if assume is None:
+            _check(lib.fbg_compile(src, int(n), int(flags), ctypes.byref(h)))
+        else:
+            a = np.ascontiguousarray(assume, dtype=np.int8)
+            if a.shape != (int(n),):
+                raise ValueError("assume needs %d entries, got shape %s" % (int(n), a.shape))
+            _check(lib.fbg_compile_assume(src, int(n), a.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                          int(flags), ctypes.byref(h)))
         self._h = h
-        self.n = int(n)
         info = ProgramInfo()
         _check(lib.fbg_program_get_info(h, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in ProgramInfo._fields_}
+        self.n = int(info.n_vars)
 
     @property
     def handle(self):
@@ -165,6 +184,15 @@ class Program:
             self.free()
         except Exception:
             pass
+
+    def set_tuning(self, words_per_lane, cofactor=False):
+        """Default words per lane and evaluation variant for this program
+        (fbg_program_set_tuning)."""
+        t = Tune(int(words_per_lane), 0, TUNE_COFACTOR if cofactor else 0, 0)
+        _check(lib.fbg_program_set_tuning(self.handle, ctypes.byref(t)))
+        info = ProgramInfo()
+        _check(lib.fbg_program_get_info(self.handle, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in ProgramInfo._fields_}
 
     def emulate(self, words_per_lane=1):
         """Host interpretation of the encoded program: (dnf uint64 array, count)."""
@@ -186,12 +214,18 @@ def compile(src, n, flags=0):  # noqa: A001 - the boundary's name
     return Program(src, n, flags)
 
 
-def eval_dnf(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0):
+def compile_assume(src, n, assume, flags=0):
+    """fbg_compile_assume: assume[k] in {-1, 0, 1} (-1 free); the program's
+    variables are the free ones, renumbered in increasing order."""
+    return Program(src, n, flags, assume=assume)
+
+
+def eval_dnf(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0, cofactor=False):
     """fbg_eval_dnf: the DNF vector as an int64 device tensor of uint64 words."""
     words = dnf_words(prog.n)
     if out is None:
         out = _device_u64(words)
-    tune = _tune(words_per_lane, grid_blocks)
+    tune = _tune(words_per_lane, grid_blocks, cofactor)
     if tune is None:
         _check(lib.fbg_eval_dnf(prog.handle, _ptr(out), out.numel(), _stream(stream)))
     else:
@@ -199,11 +233,11 @@ def eval_dnf(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0):
     return out
 
 
-def count(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0):
+def count(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0, cofactor=False):
     """fbg_count: one-element int64 device tensor holding the model count."""
     if out is None:
         out = _device_u64(1)
-    tune = _tune(words_per_lane, grid_blocks)
+    tune = _tune(words_per_lane, grid_blocks, cofactor)
     if tune is None:
         _check(lib.fbg_count(prog.handle, _ptr(out), _stream(stream)))
     else:
@@ -244,10 +278,10 @@ class Server:
     """fbg_server: launches over explicit work items that add into count
     slots, with pinned staging buffers reused round-robin."""
 
-    def __init__(self, max_programs, max_items, words_per_lane, nbuf=4):
+    def __init__(self, max_programs, max_items, words_per_lane, nbuf=4, cofactor=False):
         h = ctypes.c_void_p()
         _check(lib.fbg_server_create(int(max_programs), int(max_items), int(words_per_lane), int(nbuf),
-                                     ctypes.byref(h)))
+                                     TUNE_COFACTOR if cofactor else 0, ctypes.byref(h)))
         self._h = h
         self.words_per_lane = int(words_per_lane)
         self.max_programs = int(max_programs)
@@ -276,20 +310,24 @@ class Server:
 class Batch:
     """A work plan for counting many programs in one persistent launch."""
 
-    def __init__(self, progs, words_per_lane=0, grid_blocks=0):
+    def __init__(self, progs, words_per_lane=0, grid_blocks=0, cofactor=False):
         self._progs = list(progs)  # keep the programs alive
         arr = (ctypes.c_void_p * len(self._progs))(*[p.handle.value for p in self._progs])
         h = ctypes.c_void_p()
-        _check(lib.fbg_batch_create(arr, len(self._progs), _tune(words_per_lane, grid_blocks), ctypes.byref(h)))
+        _check(lib.fbg_batch_create(arr, len(self._progs), _tune(words_per_lane, grid_blocks, cofactor),
+                                    ctypes.byref(h)))
         self._h = h
 
     def __len__(self):
         return len(self._progs)
 
-    def count(self, out=None, stream=None):
+    def count(self, out=None, stream=None, graph=False):
+        """Counts of all programs; graph=True replays a captured HIP graph
+        (fbg_batch_count_graph)."""
         if out is None:
             out = _device_u64(len(self._progs))
-        _check(lib.fbg_batch_count(self._h, _ptr(out), _stream(stream)))
+        f = lib.fbg_batch_count_graph if graph else lib.fbg_batch_count
+        _check(f(self._h, _ptr(out), _stream(stream)))
         return out
 
     def free(self):
@@ -304,13 +342,13 @@ class Batch:
             pass
 
 
-def count_batch(progs, out=None, stream=None, words_per_lane=0, grid_blocks=0):
+def count_batch(progs, out=None, stream=None, words_per_lane=0, grid_blocks=0, cofactor=False):
     """fbg_count_batch: counts of all programs (one persistent launch)."""
     progs = list(progs)
     if out is None:
         out = _device_u64(len(progs))
     arr = (ctypes.c_void_p * len(progs))(*[p.handle.value for p in progs])
-    _check(lib.fbg_count_batch(arr, len(progs), _ptr(out), _tune(words_per_lane, grid_blocks),
+    _check(lib.fbg_count_batch(arr, len(progs), _ptr(out), _tune(words_per_lane, grid_blocks, cofactor),
                                _stream(stream)))
     return out
 

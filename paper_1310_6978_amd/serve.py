@@ -127,6 +127,7 @@ class ServeLoop:
         inflight = collections.deque()    # (end event, timing start event, stream index)
         done = []
         slice_ms = []
+        peak = 0                          # most requests admitted at once
         t0 = time.perf_counter()
         k = 0
 
@@ -151,6 +152,7 @@ class ServeLoop:
                 r.admitted_at = now()
                 r.slot = r.rid
                 active.append(r)
+                peak = max(peak, len(active) + len(issued))
             # ---- one slice over the admitted requests
             launched = False
             if active and len(inflight) < len(self.streams):
@@ -220,6 +222,7 @@ class ServeLoop:
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else 0.0,
             "latency_mean_ms": float(lat.mean() * 1e3) if len(lat) else 0.0,
             "slices": k,
+            "peak_admitted": peak,
             "gpu_busy": float(sum(slice_ms) / 1e3 / wall) if wall > 0 else 0.0,
             "cache_hits": self.cache.hits,
             "cache_misses": self.cache.misses,

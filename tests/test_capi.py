@@ -27,6 +27,13 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(fbg.EXPORTED)
 
 
+def test_one_hip_runtime_in_the_process():
+    # libfbg must use torch's HIP runtime, not load a second one
+    maps = open("/proc/self/maps").read()
+    libs = set(line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line)
+    assert len(libs) == 1, libs
+
+
 def test_version():
     assert "gfx950" in fbg.version()
 

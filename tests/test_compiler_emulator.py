@@ -165,3 +165,43 @@ def test_deep_nesting_compiles():
     for i in range(3000):
         text = "(%s %s x%d)" % (text, "&|^"[i % 3], (i * 7) % n)
     check(text, n, wpl=[1, 16])
+
+
+def test_set_tuning_changes_the_default():
+    p = fbg.Program(*workloads.random_3cnf(20, 85, 0))
+    for w in (1, 4, 32):
+        p.set_tuning(w)
+        assert p.info["words_per_lane"] == w
+    with pytest.raises(fbg.FbgError) as ei:
+        p.set_tuning(3)
+    assert ei.value.status == fbg.FBG_E_INVAL
+
+
+def test_autotune_cache_keys(tmp_path):
+    from paper_1310_6978_amd import autotune
+    p = fbg.Program(*workloads.random_3cnf(20, 85, 0))
+    k = autotune.key_of(p)
+    assert "n=20" in k and "gen=0" in k
+    t = autotune.Tuner(path=str(tmp_path / "t.json"))
+    t.table[k] = {"words_per_lane": 8}
+    assert t.apply(p, save=False) == 8          # a cached choice needs no device
+    assert p.info["words_per_lane"] == 8
+    t.save()
+    assert autotune.Tuner(path=str(tmp_path / "t.json")).table[k]["words_per_lane"] == 8
+
+
+def test_tile_only_clauses_lead_the_prefix():
+    """At every tiling the clauses made only of tile variables come first (the
+    uniform-cofactor kernel can then drop a dead tile early); the emulated
+    result is unchanged."""
+    text, n = workloads.random_3cnf(32, 136, 4)
+    p = fbg.Program(text, n)
+    for w in WPL:
+        rows = p.disasm(w).splitlines()[1:]
+        kinds = []
+        for r in rows:
+            f = dict(x.split("=") for x in r.split()[2:] if "=" in x)
+            kinds.append(int(f["mconst"], 16) == 0 and int(f["lane"], 16) == 0 and int(f["pat"], 16) == 0)
+        k = kinds.index(False) if False in kinds else len(kinds)
+        assert k > 0 and not any(kinds[k:]), w
+    check("(x0|x1) & (x22|~x23) & (x2|x12) & ~x21 & (x18|x20)", 24, wpl=[1, 32])

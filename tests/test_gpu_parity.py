@@ -311,3 +311,35 @@ def test_server_rejects_bad_items(F):
             sv.launch([p], bad, counts)
         assert ei.value.status == F.FBG_E_INVAL
     sv.free()
+
+
+def test_batch_graph_replays_match_eager(F):
+    import torch
+    rng = random.Random(3)
+    texts = [workloads.random_dag(rng.choice([12, 16, 20]), rng.randrange(50, 600), i) for i in range(30)]
+    texts += [workloads.random_3cnf(22, 93, s) for s in range(6)]
+    progs = [F.Program(t, n) for t, n in texts]
+    want = [oracle.count(t, n) for t, n in texts]
+    b = F.Batch(progs)
+    eager = host(b.count()).tolist()
+    assert eager == want
+    out = torch.zeros(len(progs), dtype=torch.int64, device="cuda")
+    for rep in range(4):
+        # eager work and synchronisation between replays
+        junk = torch.arange(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        out.fill_(-1)
+        b.count(out=out, graph=True)
+        assert host(out).tolist() == want, rep
+        del junk
+
+
+def test_autotuner_choice_is_exact(F, tmp_path):
+    from paper_1310_6978_amd import autotune
+    text, n = workloads.random_3cnf(24, 102, 9)
+    p = F.Program(text, n)
+    t = autotune.Tuner(path=str(tmp_path / "tune.json"), reps=2)
+    w = t.apply(p)
+    assert w in autotune.CANDIDATES and p.info["words_per_lane"] == w
+    assert gpu_count(F, p) == oracle.count(text, n)
+    assert t.table[autotune.key_of(p)]["ms"]

@@ -71,12 +71,17 @@ def test_tiny_arena_still_serves_everything():
     import torch
     if not torch.cuda.is_available():
         pytest.fail("GPU test needs a HIP device")
+    from paper_1310_6978_amd import fbg
     from paper_1310_6978_amd.serve import ServeLoop, program_bytes
     reqs = request_stream(30, 0.0, seed=5, n_lo=12, n_hi=20, theory_share=0.0)
-    # room for about two requests at a time: admission has to wait
+    # room for a handful of requests at a time: admission has to wait
     loop = ServeLoop(words_per_lane=8, slice_words=1e7, arena_bytes=2 * 200000, max_active=8)
     res = loop.run(reqs, realtime=False)
     loop.close()
     for r in reqs:
         assert res["counts"][r["id"]] == oracle.count(r["text"], r["n"])
-    assert res["slices"] >= 10
+    # admission bound the number of requests held at once, so the 30
+    # requests needed several slices
+    smallest = min(program_bytes(fbg.Program(r["text"], r["n"]).info) + 8 for r in reqs)
+    assert 1 <= res["peak_admitted"] <= (2 * 200000) // smallest < 30
+    assert res["slices"] >= -(-30 // res["peak_admitted"])
