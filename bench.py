@@ -24,6 +24,8 @@ Workload c3: 4096 random DAG formulas (n in [10,30], 50..2000 ops), counts
 only, one batched launch per step, compared with 4096 plain launches.
 Workload c4: the serving loop (Poisson arrivals, continuous batching),
 reporting p50/p99 latency beside valuations/s.
+Workload posets: labeled partial orders through the c-partition counting
+procedure (bounded posets on --posets-n elements).
 Workload copy: a 1 GiB device copy, the calibration kernel for the HBM byte
 counters.
 """
@@ -43,6 +45,14 @@ if ROOT not in sys.path:
 # operation per 32-bit lane per clock.
 VALU_BITWISE_PEAK = 256 * 64 * 32 * 2.4e9
 METRIC = "valuations/sec and % VALU bitwise peak (batched vs plain, bit-exact counts)"
+
+# HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
+# WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
+# the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
+# half the bytes copied, WRITE_SIZE all of them): 2 x 2511.5 KiB fetched and
+# 8389827.2 KiB written by k_batch<5, 0, 1> (16 x 2^32-bit DNF vectors).
+# Reset to None whenever that kernel changes, until measured again.
+C1_TRAFFIC = (2 * 2511.5 + 8389827.2) * 1024
 
 
 class ProgramCache:
@@ -111,6 +121,7 @@ def bench_c1(args, torch, fbg):
     batch = fbg.Batch(progs)
     counts = torch.empty(len(progs), dtype=torch.int64, device="cuda")
     dnfs = [torch.empty(words, dtype=torch.int64, device="cuda") for _ in progs]
+    batch.set_dnf_outputs(dnfs)
     cap = 4096
     idx = [torch.empty(cap, dtype=torch.int64, device="cuda") for _ in progs]
     tots = [torch.empty(1, dtype=torch.int64, device="cuda") for _ in progs]
@@ -118,17 +129,17 @@ def bench_c1(args, torch, fbg):
     ev = []
 
     def step(record):
-        ps = [cache.get(t, nn) for t, nn in texts]                   # compile (resident)
+        for t, nn in texts:                                          # compile (resident lookup)
+            cache.get(t, nn)
         if record:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
-        batch.count(out=counts, stream=stream)                       # count, batched
+        batch.eval_dnf(counts=counts, stream=stream)                 # evaluate + DNF + count, batched
         if record:
             b.record(stream)
             ev.append((a, b))
-        for p, d, ii, tt in zip(ps, dnfs, idx, tots):
-            fbg.eval_dnf(p, out=d, stream=stream)                    # DNF write-out
+        for d, ii, tt in zip(dnfs, idx, tots):
             fbg.enumerate_dnf(d, n, cap, out=ii, total=tt, stream=stream)  # models, from the DNF
 
     for _ in range(args.warmup):
@@ -147,34 +158,37 @@ def bench_c1(args, torch, fbg):
     exact = None
     if gold is not None and all(s in gold for s in seeds):
         exact = all(got[i] == gold[s] == totals[i] for i, s in enumerate(seeds))
-
-    # batched count alone vs 16 plain launches
     k_ms = sum(ev_ms(a, b) for a, b in ev) / len(ev)
+
+    # counting alone: one batched launch vs 16 plain launches, and the
+    # uniform-cofactor variant of the batched count
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return ev_ms(a, b) / reps
+
+    reps = max(args.steps, 3)
+    bc = torch.empty(len(progs), dtype=torch.int64, device="cuda")
+    batch_ms = timed(lambda: batch.count(out=bc, stream=stream), reps)
+    batch_same = bc.cpu().numpy().view("uint64").tolist() == got
     plain_out = torch.empty(1, dtype=torch.int64, device="cuda")
-    reps = 3
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record(stream)
-    for _ in range(reps):
+
+    def plain():
         for p in progs:
             fbg.count(p, out=plain_out, stream=stream)
-    b.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = ev_ms(a, b) / reps
-    # the uniform-cofactor variant of the batched count (same counts)
+    plain_ms = timed(plain, 3)
     cbatch = fbg.Batch(progs, cofactor=True)
-    ccounts = torch.empty(len(progs), dtype=torch.int64, device="cuda")
-    cbatch.count(out=ccounts, stream=stream)
-    torch.cuda.synchronize()
-    a.record(stream)
-    for _ in range(max(args.steps, 3)):
-        cbatch.count(out=ccounts, stream=stream)
-    b.record(stream)
-    torch.cuda.synchronize()
-    cof_ms = ev_ms(a, b) / max(args.steps, 3)
-    cof_same = ccounts.cpu().numpy().view("uint64").tolist() == got
+    cof_ms = timed(lambda: cbatch.count(out=bc, stream=stream), reps)
+    cof_same = bc.cpu().numpy().view("uint64").tolist() == got
     cbatch.free()
+
     vals = len(progs) * float(1 << n)
     l2in = sum(p.info["l2in"] for p in progs)
     achieved = l2in * float(1 << n) / (k_ms / 1e3)
@@ -185,19 +199,21 @@ def bench_c1(args, torch, fbg):
         "ms_per_step": ms_step,
         "dtype": "u32",
         "config": {"workload": "random 3-CNF model counting, n=32, m=136 (ratio 4.25), seeds 0-15; per step: "
-                               "batched count + enumerate + 2^32-bit DNF of each instance",
+                               "one batched launch writing the 2^32-bit DNF vector and the count of every "
+                               "instance, then every instance's models enumerated from its DNF vector",
                    "n": n, "clauses": 136, "instances": len(progs),
                    "words_per_lane": progs[0].info["words_per_lane"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_BITWISE_PEAK / 1e12,
-                     "unit": "Tbitop/s", "frac": achieved / VALU_BITWISE_PEAK, "traffic": None,
-                     "kernel": "k_batch (batched count over 16 programs)", "avg_ms": k_ms,
-                     "algorithmic_ops_per_launch": l2in * float(1 << n)},
-        "batched_vs_plain": {"batched_count_ms": k_ms, "plain_count_ms": plain_ms,
-                             "batched_valuations_per_s": vals / (k_ms / 1e3),
+                     "unit": "Tbitop/s", "frac": achieved / VALU_BITWISE_PEAK, "traffic": C1_TRAFFIC,
+                     "kernel": "k_batch MODE_DNF (16 programs: evaluation, DNF write-out, counts)",
+                     "avg_ms": k_ms, "algorithmic_ops_per_launch": l2in * float(1 << n),
+                     "dnf_bytes_per_launch": len(progs) * float(1 << n) / 8},
+        "batched_vs_plain": {"batched_count_ms": batch_ms, "plain_count_ms": plain_ms,
+                             "batched_valuations_per_s": vals / (batch_ms / 1e3),
                              "plain_valuations_per_s": vals / (plain_ms / 1e3),
-                             "speedup": plain_ms / k_ms},
+                             "speedup": plain_ms / batch_ms, "counts_equal": batch_same},
         "cofactor": {"batched_count_ms": cof_ms, "valuations_per_s": vals / (cof_ms / 1e3),
-                     "speedup_vs_full_evaluation": k_ms / cof_ms, "counts_equal": cof_same},
+                     "speedup_vs_full_evaluation": batch_ms / cof_ms, "counts_equal": cof_same},
         "pct_valu_bitwise_peak": 100.0 * achieved / VALU_BITWISE_PEAK,
         "counts": got,
         "bit_exact_vs_oracle": exact,
@@ -213,7 +229,7 @@ def bench_c3(args, torch, fbg):
     batch_f = random_dag_batch(4096, 0)
     progs = [fbg.Program(t, n) for t, n in batch_f]
     vals = float(sum(1 << n for _, n in batch_f))
-    l2in = sum(p.info["l2in"] for p in progs)
+    l2in = sum(p.info["l2in"] * float(1 << n) for p, (_, n) in zip(progs, batch_f))
     b = fbg.Batch(progs)
     counts = torch.empty(len(progs), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -247,7 +263,7 @@ def bench_c3(args, torch, fbg):
                                "per step one batched count launch", "formulas": len(progs)},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_BITWISE_PEAK / 1e12,
                      "unit": "Tbitop/s", "frac": achieved / VALU_BITWISE_PEAK, "traffic": None,
-                     "kernel": "k_batch"},
+                     "kernel": "k_batch MODE_COUNT (4096 programs)"},
         "batched_vs_plain": {"batched_ms": ms_step, "plain_ms": plain_ms, "speedup": plain_ms / ms_step,
                              "batched_equals_plain": same},
         "bit_exact_vs_oracle": exact,
@@ -299,6 +315,49 @@ def bench_c4(args, torch, fbg):
     }
 
 
+def bench_posets(args, torch, fbg):
+    """Labeled partial orders on n-2 elements by the counting procedure of
+    Section 3.4 (bounded posets of Section 5.2): one program per layering,
+    all counted in one batched launch, combined by formula (ltn).  The
+    whole theory has (n-2)(n-3) letters (56 at n = 10, beyond one
+    evaluation); a layering leaves at most C(n-2, 2)."""
+    import workloads
+    from paper_1310_6978_amd import tba
+    n = args.posets_n
+    text, nl = workloads.bounded_posets(n)
+    parts = list(tba.bounded_poset_parts(n))
+    t0 = time.perf_counter()
+    res = tba.bounded_posets(n, text, nl)                     # includes compiling every part
+    torch.cuda.synchronize()
+    wall_first = time.perf_counter() - t0
+    times = {}
+    for cof in (True, False):
+        progs = [fbg.compile_assume(text + extra, nl, assume) for _, assume, extra in parts]
+        b = fbg.Batch(progs, cofactor=cof)
+        out = torch.empty(len(progs), dtype=torch.int64, device="cuda")
+        for _ in range(args.warmup):
+            b.count(out=out)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.steps):
+            b.count(out=out)
+        e1.record(s)
+        torch.cuda.synchronize()
+        times[cof] = e0.elapsed_time(e1) / args.steps
+        assert out.cpu().numpy().view("uint64").tolist() == [q.count for q in res.parts]
+        b.free()
+    vals = float(sum(2 ** q.n_free for q in res.parts))
+    return {"metric": "labeled partial orders counted by c-partitions (valuations/s of the batched count)",
+            "value": vals / (times[True] / 1e3), "unit": "valuations/s", "ms_per_step": times[True],
+            "dtype": "u32",
+            "config": {"workload": "bounded partial orders n=%d (labeled posets on %d elements), %d layerings"
+                                   % (n, n - 2, len(parts)), "letters": nl,
+                       "max_free_letters": max(q.n_free for q in res.parts)},
+            "labeled_posets": res.total, "batched_count_ms_cofactor": times[True],
+            "batched_count_ms_full_evaluation": times[False], "first_run_wall_s_with_compile": wall_first}
+
+
 def bench_copy(args, torch):
     """A plain device-to-device copy of 1 GiB: the calibration kernel for the
     FETCH_SIZE / WRITE_SIZE counters (it must read and write 1 GiB)."""
@@ -323,7 +382,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "copy"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "posets", "copy"])
+    ap.add_argument("--posets-n", type=int, default=11, help="posets: bounded posets on n elements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=20000, help="c4: requests in the timed run")
     ap.add_argument("--sat-requests", type=int, default=1000, help="c4: requests of the saturation run")
@@ -347,6 +407,8 @@ def main():
         res = bench_c3(args, torch, fbg)
     elif args.workload == "c4":
         res = bench_c4(args, torch, fbg)
+    elif args.workload == "posets":
+        res = bench_posets(args, torch, fbg)
     else:
         res = bench_copy(args, torch)
     out = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,

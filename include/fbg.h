@@ -204,6 +204,24 @@ void fbg_batch_free(fbg_batch *b);
  * fbg_batch_count (one batch object per stream).
  */
 fbg_status fbg_batch_count_graph(fbg_batch *b, uint64_t *d_counts, void *stream);
+
+/*
+ * fbg_batch_set_dnf_outputs -- fix, for every program of the batch, the
+ * device buffer that fbg_batch_eval_dnf writes its DNF vector into (Section
+ * 2.3: one pass evaluates all blocks of every formula of the batch).
+ *   d_outs     host array of np device pointers (caller-owned buffers; the
+ *              array itself is read during the call only).
+ *   out_words  host array of np sizes in uint64 words; out_words[i] must be
+ *              at least max(1, 2^(n_i - 6)), and n_i <= FBG_MAX_DNF_VARS.
+ * Synchronous (uploads a table); must not run while a launch of this batch
+ * is pending.  May be called again to change the buffers.
+ * fbg_batch_eval_dnf -- for every program i: its DNF vector into d_outs[i]
+ *   (layout as fbg_eval_dnf) and d_counts[i] = its number of models
+ *   (overwritten), in one persistent launch that computes each word once.
+ *   FBG_E_INVAL if no outputs were set.  Allocates nothing.
+ */
+fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, const uint64_t *out_words);
+fbg_status fbg_batch_eval_dnf(fbg_batch *b, uint64_t *d_counts, void *stream);
 fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d_counts, const fbg_tune *tune,
                            void *stream);
 

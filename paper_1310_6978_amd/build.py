@@ -33,8 +33,12 @@ def build(verbose=False):
         obj = os.path.join(HERE, "_build", os.path.splitext(src)[0] + ".o")
         cmd = [hipcc()] + common
         if src.endswith(".hip"):
+            # uniform (scalar) branches are left as branches instead of being
+            # rewritten into flag-guarded regions, which keeps every case of
+            # the interpreter's dispatch working on cur in place
             cmd += ["-x", "hip", "--offload-arch=" + ARCH,
-                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-mllvm", "-structurizecfg-skip-uniform-regions=true"]
         else:
             cmd += ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]
         cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

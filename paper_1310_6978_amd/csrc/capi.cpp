@@ -58,7 +58,9 @@ uint64_t tiles_of(uint64_t nslices, int log2w) {
   return (nslices + per - 1) / per;
 }
 
-size_t lds_per_wave(uint32_t nregs, int log2w) { return (size_t)nregs * (64u << log2w) * 4u; }
+// Registers beyond the first kVgprRegs live in LDS: W*64 words each per wave.
+uint32_t lds_regs(uint32_t nregs) { return nregs > fbg::kVgprRegs ? nregs - fbg::kVgprRegs : 0u; }
+size_t lds_per_wave(uint32_t nregs, int log2w) { return (size_t)lds_regs(nregs) * (64u << log2w) * 4u; }
 
 // Device memory for programs: size classes of powers of two (>= 4 KiB) carved
 // out of 64 MiB chunks and recycled through free lists, so that compiling a
@@ -149,19 +151,27 @@ struct fbg_program {
 };
 
 struct fbg_batch {
+  // One persistent launch per plan: programs made only of clauses run at
+  // their own (wide) tiling, general programs at a narrower one whose
+  // registers fit; a batch holds one or two plans.
+  struct Plan {
+    int log2w = 0;
+    int var = 0;
+    int grid = 1, grid_dnf = 1;
+    int block = 256;
+    size_t lds = 0;
+    uint32_t nitems = 0;
+    uint32_t max_regs = 0;  // LDS registers per wave
+    fbg::BatchItem *d_items = nullptr;
+  };
   int device = -1;
-  int log2w = 0;
-  int var = 0;
-  int grid = 1;
-  int block = 256;
-  size_t lds = 0;
   int32_t np = 0;
-  uint32_t nitems = 0;
-  uint32_t max_regs = 0;
+  std::vector<Plan> plans;
   fbg::BatchProg *d_progs = nullptr;
-  fbg::BatchItem *d_items = nullptr;
-  uint32_t *d_head = nullptr;
-  // captured graph of (zero fill, persistent kernel) for one counts pointer
+  fbg::BatchProg *d_progs_dnf = nullptr;  // with DNF outputs (fbg_batch_set_dnf_outputs)
+  std::vector<fbg::BatchProg> host_progs;
+  uint32_t *d_head = nullptr;             // one queue head per plan
+  // captured graph of (zero fill, persistent kernels) for one counts pointer
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   uint64_t *graph_counts = nullptr;
@@ -186,10 +196,12 @@ namespace {
 
 // Largest words-per-lane that still gives every wave of a full grid a tile,
 // within the LDS budget of the program's registers.
-int pick_log2w(uint64_t nslices, uint32_t nregs, int dev) {
+int pick_log2w(uint64_t nslices, uint32_t nregs, bool general, int dev) {
   const uint64_t waves = (uint64_t)cu_count(dev) * 32;  // 8 waves per SIMD
   int best = 0;
-  for (int l = kMaxLog2W; l >= 0; l--) {
+  // the general interpreter keeps cur and four registers per word in VGPRs:
+  // beyond 8 words per lane it loses more occupancy than it gains
+  for (int l = general ? 3 : kMaxLog2W; l >= 0; l--) {
     if (lds_per_wave(nregs, l) > kMaxLdsPerBlock) continue;
     if (tiles_of(nslices, l) >= waves || l == 0) {
       best = l;
@@ -216,7 +228,10 @@ fbg_status block_shape(uint32_t nregs, int l, int &wpb, size_t &lds) {
   return FBG_OK;
 }
 
-fbg_status geometry(const fbg_program *p, const fbg_tune *tune, Geometry &g) {
+// Launch shape of an evaluator kernel: a persistent grid of exactly the
+// blocks that can be resident at once (more would only queue behind them and
+// finish in a tail), each wave striding over the tiles.
+fbg_status geometry(const fbg_program *p, const fbg_tune *tune, int mode, Geometry &g) {
   int l = p->auto_log2w;
   fbg_status st;
   if (tune && tune->words_per_lane && (st = parse_wpl(tune->words_per_lane, l))) return st;
@@ -224,7 +239,8 @@ fbg_status geometry(const fbg_program *p, const fbg_tune *tune, Geometry &g) {
   if ((st = block_shape((uint32_t)p->c.nregs, l, wpb, g.lds))) return st;
   const uint64_t ntiles = tiles_of(p->nslices, l);
   const uint64_t blocks = (ntiles + wpb - 1) / wpb;
-  uint64_t maxb = (uint64_t)cu_count(p->device) * (32 / wpb);
+  const int occ = fbg::eval_blocks_per_cu(mode, l, p->variant(tune), 64 * wpb, g.lds);
+  uint64_t maxb = (uint64_t)cu_count(p->device) * (uint64_t)occ;
   if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
   g.log2w = l;
   g.block = 64 * wpb;
@@ -252,7 +268,7 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   a.code = p->d_code + p->dev_off[log2w];
   a.nins = p->nins[log2w];
   a.ncl = p->ncl;
-  a.nregs = (uint32_t)p->c.nregs;
+  a.nregs = lds_regs((uint32_t)p->c.nregs);
   a.n = p->c.n;
   a.nslices = p->nslices;
   a.ntiles = tiles_of(p->nslices, log2w);
@@ -265,7 +281,7 @@ fbg::BatchProg batch_prog(const fbg_program *p, int l) {
   b.code = p->d_code + p->dev_off[l];
   b.nins = p->nins[l];
   b.ncl = p->ncl;
-  b.nregs = (uint32_t)p->c.nregs;
+  b.nregs = lds_regs((uint32_t)p->c.nregs);
   b.n = p->c.n;
   b.nslices = p->nslices;
   b.ntiles = tiles_of(p->nslices, l);
@@ -361,9 +377,9 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int8_t *assume,
       delete p;
       return hip_fail(e, "hipMemcpy of the program");
     }
-    p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, dev);
+    p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, p->general(), dev);
   } else {
-    p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, -1);
+    p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, p->general(), -1);
   }
   *out = p;
   return FBG_OK;
@@ -451,7 +467,7 @@ fbg_status fbg_count_tuned(const fbg_program *p, uint64_t *d_count, const fbg_tu
     return e == hipSuccess ? FBG_OK : hip_fail(e, "launch");
   }
   Geometry g;
-  if ((st = geometry(p, tune, g))) return st;
+  if ((st = geometry(p, tune, fbg::EVAL_COUNT, g))) return st;
   fbg::EvalArgs a = base_args(p, g.log2w);
   a.out_count = d_count;
   e = fbg::launch_set_u64(d_count, 0, s);
@@ -474,7 +490,7 @@ fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t ou
   if (out_words < need)
     return fail(FBG_E_INVAL, "out_words=%llu < %llu", (unsigned long long)out_words, (unsigned long long)need);
   Geometry g;
-  if ((st = geometry(p, tune, g))) return st;
+  if ((st = geometry(p, tune, fbg::EVAL_DNF, g))) return st;
   fbg::EvalArgs a = base_args(p, g.log2w);
   a.out32 = (uint32_t *)d_out;
   a.out_slices = 2 * need;
@@ -495,7 +511,7 @@ fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacit
   if (capacity > 0 && !d_idx)
     return fail(FBG_E_INVAL, "d_idx is NULL with capacity %llu", (unsigned long long)capacity);
   Geometry g;
-  if ((st = geometry(p, nullptr, g))) return st;
+  if ((st = geometry(p, nullptr, fbg::EVAL_TILECNT, g))) return st;
   hipStream_t s = (hipStream_t)stream;
   const int var = p->variant(nullptr);
   return enumerate_with(base_args(p, g.log2w), d_idx, capacity, d_total, s,
@@ -539,86 +555,111 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     if (st) return st;
     dev = ps[i]->device;
   }
-  // words per lane: the tuning, else the choice for the largest program
-  int l = 0;
   fbg_status st;
-  if (tune && tune->words_per_lane) {
-    if ((st = parse_wpl(tune->words_per_lane, l))) return st;
-  } else {
-    uint64_t best = 0;
-    for (int32_t i = 0; i < np; i++) {
-      const uint64_t cost = ps[i]->nslices * (uint64_t)std::max<size_t>(1, ps[i]->c.code.size());
-      if (cost >= best) {
-        best = cost;
-        l = ps[i]->auto_log2w;
-      }
-    }
-  }
-  uint32_t max_regs = 0;
-  int var = 0;
-  for (int32_t i = 0; i < np; i++) {
-    max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
-    var |= ps[i]->variant(tune);
-  }
-  while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
-  int wpb;
-  size_t lds;
-  if ((st = block_shape(max_regs, l, wpb, lds))) return st;
-
-  std::vector<fbg::BatchProg> progs((size_t)np);
-  double total_cost = 0;
-  for (int32_t i = 0; i < np; i++) {
-    progs[(size_t)i] = batch_prog(ps[i], l);
-    total_cost += (double)progs[(size_t)i].ntiles * (progs[(size_t)i].nins + 4);
-  }
+  int fixed_l = -1;
+  if (tune && tune->words_per_lane && (st = parse_wpl(tune->words_per_lane, fixed_l))) return st;
   const int cus = cu_count(dev);
   const uint64_t waves = (uint64_t)cus * 32;
-  // about four items per wave; never split below one tile
-  const double target = std::max(1.0, total_cost / (double)(waves * 4));
-  std::vector<fbg::BatchItem> items;
-  std::vector<double> cost;
-  for (int32_t i = 0; i < np; i++) {
-    const fbg::BatchProg &b = progs[(size_t)i];
-    const double per_tile = b.nins + 4.0;
-    const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
-    for (uint64_t t = 0; t < b.ntiles; t += chunk) {
-      fbg::BatchItem it;
-      it.prog = (uint32_t)i;
-      it.slot = (uint32_t)i;
-      it.t0 = t;
-      it.t1 = std::min(b.ntiles, t + chunk);
-      items.push_back(it);
-      cost.push_back((double)(it.t1 - it.t0) * per_tile);
-    }
-  }
-  if (items.size() > 0xFFFFFFF0ull) return fail(FBG_E_RANGE, "too many work items");
-  std::vector<size_t> order(items.size());
-  for (size_t i = 0; i < order.size(); i++) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-  std::vector<fbg::BatchItem> sorted;
-  sorted.reserve(items.size());
-  for (size_t i : order) sorted.push_back(items[i]);
 
   fbg_batch *b = new (std::nothrow) fbg_batch();
   if (!b) return fail(FBG_E_NOMEM, "out of host memory");
   b->device = dev;
-  b->log2w = l;
-  b->var = var;
   b->np = np;
-  b->nitems = (uint32_t)sorted.size();
-  b->max_regs = max_regs;
-  b->block = 64 * wpb;
-  b->lds = lds;
-  uint64_t maxb = (uint64_t)cus * (32 / wpb);
-  if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
-  b->grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((b->nitems + wpb - 1) / wpb, maxb));
-  hipError_t e = hipMalloc((void **)&b->d_progs, progs.size() * sizeof(fbg::BatchProg));
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_items, sorted.size() * sizeof(fbg::BatchItem));
+  b->host_progs.resize((size_t)np);
+  std::vector<std::vector<fbg::BatchItem>> plan_items;
+  for (int group = 0; group < 2; group++) {  // 0: clause-only programs, 1: general programs
+    std::vector<int32_t> members;
+    for (int32_t i = 0; i < np; i++)
+      if (ps[i]->general() == (group == 1)) members.push_back(i);
+    if (members.empty()) continue;
+    // words per lane: the tuning, else the choice for the largest program
+    int l = fixed_l;
+    if (l < 0) {
+      uint64_t best = 0;
+      l = 0;
+      for (int32_t i : members) {
+        const uint64_t cost = ps[i]->nslices * (uint64_t)std::max<size_t>(1, ps[i]->c.code.size());
+        if (cost >= best) {
+          best = cost;
+          l = ps[i]->auto_log2w;
+        }
+      }
+    }
+    uint32_t max_regs = 0;
+    int var = 0;
+    for (int32_t i : members) {
+      max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
+      var |= ps[i]->variant(tune);
+    }
+    while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
+    int wpb;
+    size_t lds;
+    if ((st = block_shape(max_regs, l, wpb, lds))) {
+      fbg_batch_free(b);
+      return st;
+    }
+    double total_cost = 0;
+    for (int32_t i : members) {
+      fbg::BatchProg &q = b->host_progs[(size_t)i];
+      q = batch_prog(ps[i], l);
+      total_cost += (double)q.ntiles * (q.nins + 4);
+    }
+    // about four items per wave; never split below one tile
+    const double target = std::max(1.0, total_cost / (double)(waves * 4));
+    std::vector<fbg::BatchItem> items;
+    std::vector<double> cost;
+    for (int32_t i : members) {
+      const fbg::BatchProg &q = b->host_progs[(size_t)i];
+      const double per_tile = q.nins + 4.0;
+      const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
+      for (uint64_t t = 0; t < q.ntiles; t += chunk) {
+        fbg::BatchItem it;
+        it.prog = (uint32_t)i;
+        it.slot = (uint32_t)i;
+        it.t0 = t;
+        it.t1 = std::min(q.ntiles, t + chunk);
+        items.push_back(it);
+        cost.push_back((double)(it.t1 - it.t0) * per_tile);
+      }
+    }
+    if (items.size() > 0xFFFFFFF0ull) {
+      fbg_batch_free(b);
+      return fail(FBG_E_RANGE, "too many work items");
+    }
+    // largest first, so that the queue ends on small items
+    std::vector<size_t> order(items.size());
+    for (size_t k = 0; k < order.size(); k++) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<fbg::BatchItem> sorted;
+    sorted.reserve(items.size());
+    for (size_t k : order) sorted.push_back(items[k]);
+
+    fbg_batch::Plan pl;
+    pl.log2w = l;
+    pl.var = var;
+    pl.block = 64 * wpb;
+    pl.lds = lds;
+    pl.nitems = (uint32_t)sorted.size();
+    pl.max_regs = lds_regs(max_regs);
+    const uint64_t want = (pl.nitems + wpb - 1) / wpb;
+    for (int mode : {fbg::EVAL_COUNT, fbg::EVAL_DNF}) {
+      uint64_t maxb = (uint64_t)cus * (uint64_t)fbg::batch_blocks_per_cu(mode, l, var, pl.block, lds);
+      if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
+      (mode == fbg::EVAL_COUNT ? pl.grid : pl.grid_dnf) = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, maxb));
+    }
+    b->plans.push_back(pl);
+    plan_items.push_back(std::move(sorted));
+  }
+  hipError_t e = hipMalloc((void **)&b->d_progs, (size_t)np * sizeof(fbg::BatchProg));
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_head, 256);
+  for (size_t k = 0; k < b->plans.size() && e == hipSuccess; k++) {
+    e = hipMalloc((void **)&b->plans[k].d_items, plan_items[k].size() * sizeof(fbg::BatchItem));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->plans[k].d_items, plan_items[k].data(), plan_items[k].size() * sizeof(fbg::BatchItem),
+                    hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_progs, progs.data(), progs.size() * sizeof(fbg::BatchProg), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_items, sorted.data(), sorted.size() * sizeof(fbg::BatchItem), hipMemcpyHostToDevice);
+    e = hipMemcpy(b->d_progs, b->host_progs.data(), (size_t)np * sizeof(fbg::BatchProg), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     fbg_batch_free(b);
     return fail(FBG_E_NOMEM, "batch upload: %s", hipGetErrorString(e));
@@ -627,23 +668,73 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   return FBG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, uint64_t *d_counts, hipStream_t s) {
+  // zero the counts and every plan's queue head, then one persistent kernel per plan
+  hipError_t e = fbg::launch_zero(d_counts, (uint64_t)b->np, b->d_head, s);
+  if (e != hipSuccess) return hip_fail(e, "launch of the zero fill");
+  for (size_t k = 0; k < b->plans.size(); k++) {
+    const fbg_batch::Plan &pl = b->plans[k];
+    fbg::BatchArgs a;
+    a.progs = d_progs;
+    a.items = pl.d_items;
+    a.nitems = pl.nitems;
+    a.max_regs = pl.max_regs;
+    a.head = b->d_head + k;
+    a.counts = d_counts;
+    e = fbg::launch_batch(mode, pl.log2w, pl.var, a, mode == fbg::EVAL_DNF ? pl.grid_dnf : pl.grid, pl.block, pl.lds,
+                          s);
+    if (e != hipSuccess) return hip_fail(e, "launch of the batch kernel");
+  }
+  return FBG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 fbg_status fbg_batch_count(fbg_batch *b, uint64_t *d_counts, void *stream) {
   if (!b) return fail(FBG_E_INVAL, "batch is NULL");
   if (!d_counts) return fail(FBG_E_INVAL, "d_counts is NULL");
   fbg_status st = check_device(b->device);
   if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = fbg::launch_zero(d_counts, (uint64_t)b->np, b->d_head, s);
-  if (e != hipSuccess) return hip_fail(e, "launch of the zero fill");
-  fbg::BatchArgs a;
-  a.progs = b->d_progs;
-  a.items = b->d_items;
-  a.nitems = b->nitems;
-  a.max_regs = b->max_regs;
-  a.head = b->d_head;
-  a.counts = d_counts;
-  e = fbg::launch_batch(b->log2w, b->var, a, b->grid, b->block, b->lds, s);
-  return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the batch kernel");
+  return batch_launch(b, fbg::EVAL_COUNT, b->d_progs, d_counts, (hipStream_t)stream);
+}
+
+fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, const uint64_t *out_words) {
+  if (!b) return fail(FBG_E_INVAL, "batch is NULL");
+  if (!d_outs || !out_words) return fail(FBG_E_INVAL, "NULL argument");
+  fbg_status st = check_device(b->device);
+  if (st) return st;
+  std::vector<fbg::BatchProg> t = b->host_progs;
+  for (int32_t i = 0; i < b->np; i++) {
+    fbg::BatchProg &q = t[(size_t)i];
+    if (q.n > FBG_MAX_DNF_VARS) return fail(FBG_E_RANGE, "program %d: n=%d above %d for a DNF vector", i, q.n,
+                                            FBG_MAX_DNF_VARS);
+    const uint64_t need = dnf_words_of(q.n);
+    if (!d_outs[i]) return fail(FBG_E_INVAL, "d_outs[%d] is NULL", i);
+    if (out_words[i] < need)
+      return fail(FBG_E_INVAL, "out_words[%d]=%llu < %llu", i, (unsigned long long)out_words[i],
+                  (unsigned long long)need);
+    q.out32 = (uint32_t *)d_outs[i];
+    q.out_slices = 2 * need;
+  }
+  hipError_t e = hipSuccess;
+  if (!b->d_progs_dnf) e = hipMalloc((void **)&b->d_progs_dnf, t.size() * sizeof(fbg::BatchProg));
+  if (e == hipSuccess) e = hipMemcpy(b->d_progs_dnf, t.data(), t.size() * sizeof(fbg::BatchProg), hipMemcpyHostToDevice);
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "upload of the DNF output table");
+}
+
+fbg_status fbg_batch_eval_dnf(fbg_batch *b, uint64_t *d_counts, void *stream) {
+  if (!b) return fail(FBG_E_INVAL, "batch is NULL");
+  if (!d_counts) return fail(FBG_E_INVAL, "d_counts is NULL");
+  if (!b->d_progs_dnf) return fail(FBG_E_INVAL, "no DNF outputs set (fbg_batch_set_dnf_outputs)");
+  fbg_status st = check_device(b->device);
+  if (st) return st;
+  return batch_launch(b, fbg::EVAL_DNF, b->d_progs_dnf, d_counts, (hipStream_t)stream);
 }
 
 fbg_status fbg_batch_count_graph(fbg_batch *b, uint64_t *d_counts, void *stream) {
@@ -682,7 +773,9 @@ void fbg_batch_free(fbg_batch *b) {
   if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_progs) (void)hipFree(b->d_progs);
-  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_progs_dnf) (void)hipFree(b->d_progs_dnf);
+  for (auto &pl : b->plans)
+    if (pl.d_items) (void)hipFree(pl.d_items);
   if (b->d_head) (void)hipFree(b->d_head);
   delete b;
 }
@@ -790,13 +883,13 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   a.progs = (const fbg::BatchProg *)dp;
   a.items = (const fbg::BatchItem *)di;
   a.nitems = (uint32_t)nitems;
-  a.max_regs = max_regs;
+  a.max_regs = lds_regs(max_regs);
   a.head = sl.d_head;
   a.counts = d_counts;
   const int cus = cu_count(sv->device);
-  const int grid =
-      (int)std::max<int64_t>(1, std::min<int64_t>((nitems + wpb - 1) / wpb, (int64_t)cus * (32 / wpb)));
-  e = fbg::launch_batch(l, var, a, grid, 64 * wpb, lds, s);
+  const int occ = fbg::batch_blocks_per_cu(fbg::EVAL_COUNT, l, var, 64 * wpb, lds);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nitems + wpb - 1) / wpb, (int64_t)cus * occ));
+  e = fbg::launch_batch(fbg::EVAL_COUNT, l, var, a, grid, 64 * wpb, lds, s);
   if (e == hipSuccess) e = hipEventRecord(sl.done, s);
   sl.used = true;
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the server slice");

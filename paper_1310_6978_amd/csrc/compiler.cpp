@@ -835,6 +835,12 @@ SetWords encode_set(const LitSet &ls, int log2w) {
 
 }  // namespace
 
+namespace {
+uint32_t table_f(uint32_t f, uint32_t a, uint32_t b) {
+  return (f == FBG_F_AND ? (a & b) : f == FBG_F_OR ? (a | b) : (a ^ b)) & 0xFFu;
+}
+}  // namespace
+
 uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words) {
   const size_t base = words.size();
   const int W = 1 << log2w;
@@ -879,8 +885,23 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
       if (h.inv) w[0] |= FBG_INV;
       if (h.reg >= 0) w[0] |= (uint32_t)h.reg << FBG_ARG_SHIFT;
     }
-    if (h.op == FBG_OP_OPL || h.op == FBG_OP_OPR) w[0] |= h.f << FBG_F_SHIFT;
-    if (h.invout) w[0] |= FBG_INVOUT;
+    // Operations on cur: the v_bitop3 truth table over (cur = 0xF0, T or the
+    // register = 0xCC, P(i) = 0xAA) with the inversions folded in.
+    if (h.op == FBG_OP_LDL || h.op == FBG_OP_OPL) {
+      uint32_t L = (w[0] & FBG_XORSET) ? (0xCCu ^ 0xAAu) : (0xCCu | 0xAAu);  // XOR-set inversion is in mconst
+      if (w[0] & FBG_INV) L = ~L & 0xFFu;
+      w[0] &= ~(uint32_t)FBG_INV;
+      uint32_t t = h.op == FBG_OP_LDL ? L : table_f(h.f, 0xF0u, L);
+      if (h.invout) t = ~t & 0xFFu;
+      w[0] |= t << FBG_F_SHIFT;
+    } else if (h.op == FBG_OP_OPR || h.op == FBG_OP_LDR) {
+      const uint32_t R = h.inv ? 0x33u : 0xCCu;
+      uint32_t t = h.op == FBG_OP_LDR ? R : table_f(h.f, 0xF0u, R);
+      if (h.invout) t = ~t & 0xFFu;
+      w[0] = (w[0] & ~(uint32_t)FBG_INV) | (t << FBG_F_SHIFT);
+    } else if (h.invout) {
+      w[0] |= FBG_INVOUT;  // ST, ACC, NOT: cur inverted afterwards
+    }
     words.insert(words.end(), w, w + FBG_INS_WORDS);
   }
   const uint32_t nins = (uint32_t)((words.size() - base) / FBG_INS_WORDS);
@@ -910,7 +931,6 @@ uint32_t leading_clauses(const Compiled &c) {
 
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
   static const char *ops[] = {"?", "CL", "LDL", "OPL", "ST", "OPR", "ACC", "LDR", "NOT"};
-  static const char *fs[] = {"and", "or", "xor", "?"};
   const int W = 1 << log2w;
   const uint32_t *table = words.data() + (size_t)nins * FBG_INS_WORDS;
   std::string out = "; words per lane " + std::to_string(W) + "\n";
@@ -924,14 +944,17 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
       uint32_t pat = 0;
       for (int i = 0; i < W; i++)
         if (table[arg + i]) pat |= 1u << i;
+      char tt[16] = "";
+      if (op != FBG_OP_CL) snprintf(tt, sizeof tt, "tt=%02x ", (w[0] >> FBG_F_SHIFT) & 0xFFu);
       snprintf(buf, sizeof buf,
-               "%4zu %-3s %s%s set=%s%s mconst=%08x lane=%08x%08x pat=%08x sel=%08x%08x neg=%08x%08x\n",
-               pc / FBG_INS_WORDS, name, op == FBG_OP_OPL ? fs[(w[0] >> FBG_F_SHIFT) & 3u] : "",
-               (w[0] & FBG_INVOUT) ? " invout" : "", (w[0] & FBG_XORSET) ? "xor" : "or",
-               (w[0] & FBG_INV) ? " inv" : "", w[1], w[3], w[2], pat, w[5], w[4], w[7], w[6]);
+               "%4zu %-3s %sset=%s mconst=%08x lane=%08x%08x pat=%08x sel=%08x%08x neg=%08x%08x\n",
+               pc / FBG_INS_WORDS, name, tt, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], pat, w[5],
+               w[4], w[7], w[6]);
+    } else if (op == FBG_OP_OPR || op == FBG_OP_LDR) {
+      snprintf(buf, sizeof buf, "%4zu %-3s tt=%02x r%u\n", pc / FBG_INS_WORDS, name, (w[0] >> FBG_F_SHIFT) & 0xFFu,
+               arg);
     } else {
-      snprintf(buf, sizeof buf, "%4zu %-3s %s r%u%s%s\n", pc / FBG_INS_WORDS, name,
-               op == FBG_OP_OPR ? fs[(w[0] >> FBG_F_SHIFT) & 3u] : "", arg, (w[0] & FBG_INV) ? " inv" : "",
+      snprintf(buf, sizeof buf, "%4zu %-3s r%u%s%s\n", pc / FBG_INS_WORDS, name, arg, (w[0] & FBG_INV) ? " inv" : "",
                (w[0] & FBG_INVOUT) ? " invout" : "");
     }
     out += buf;
@@ -945,25 +968,23 @@ namespace {
 
 // A literal set at (lane, word index i, tile group U0), read the way the
 // kernels read it: P(i) from the pattern table.
-inline uint32_t set_value(const uint32_t *w, const uint32_t *table, uint32_t lane, uint32_t i, uint64_t U0) {
-  bool x = (w[0] & FBG_XORSET) != 0;
+// The lane value T of a literal set at (lane, tile group U0), formed the way
+// the kernels form it: every literal but the per-word ones.
+inline uint32_t set_lane_value(const uint32_t *w, uint32_t lane, uint64_t U0) {
   uint64_t lanemask = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
   uint64_t sel = (uint64_t)w[4] | ((uint64_t)w[5] << 32);
   uint64_t neg = (uint64_t)w[6] | ((uint64_t)w[7] << 32);
   uint32_t V = ((lanemask >> lane) & 1u) ? ~0u : 0u;
-  uint32_t P = table[(w[0] >> FBG_ARG_SHIFT) + i];
-  uint32_t Q;
-  if (x)
-    Q = (__builtin_popcountll(U0 & sel) & 1) ? ~0u : 0u;
-  else
-    Q = ((U0 ^ neg) & sel) ? ~0u : 0u;
-  uint32_t L = x ? (w[1] ^ V ^ P ^ Q) : (w[1] | V | P | Q);
-  if (w[0] & FBG_INV) L = ~L;
-  return L;
+  if (w[0] & FBG_XORSET) return V ^ w[1] ^ ((__builtin_popcountll(U0 & sel) & 1) ? ~0u : 0u);
+  return (V || ((U0 ^ neg) & sel)) ? ~0u : w[1];
 }
 
-inline uint32_t apply_f(uint32_t f, uint32_t a, uint32_t b) {
-  return f == FBG_F_AND ? (a & b) : f == FBG_F_OR ? (a | b) : (a ^ b);
+// v_bitop3: bit m of tt is the result for inputs (a, b, c) = bits of m.
+inline uint32_t bitop3(uint32_t tt, uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r = 0;
+  for (uint32_t m = 0; m < 8; m++)
+    if ((tt >> m) & 1u) r |= ((m & 4u) ? a : ~a) & ((m & 2u) ? b : ~b) & ((m & 1u) ? c : ~c);
+  return r;
 }
 
 }  // namespace
@@ -987,29 +1008,28 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
     for (size_t pc = 0; pc < nins; pc++) {
       const uint32_t *w = &words[pc * FBG_INS_WORDS];
       uint32_t op = w[0] & 15u;
-      uint32_t f = (w[0] >> FBG_F_SHIFT) & 3u;
+      uint32_t tt = (w[0] >> FBG_F_SHIFT) & 0xFFu;
       uint32_t arg = w[0] >> FBG_ARG_SHIFT;
       uint32_t inv = (w[0] & FBG_INV) ? ~0u : 0u;
       if (op != FBG_OP_CL) in_prefix = false;
       switch (op) {
-        case FBG_OP_CL:
+        case FBG_OP_CL: {
+          // clauses: plain OR-sets, acc &= T | P(i); for W <= 16 in the
+          // prefix the pattern entry comes from the previous clause
+          uint32_t own = arg;
           if (in_prefix && log2w <= 4) {
-            uint32_t wc[FBG_INS_WORDS];
-            for (int q = 0; q < FBG_INS_WORDS; q++) wc[q] = w[q];
-            const uint32_t own = pc == 0 ? (w[0] >> FBG_ARG_SHIFT) : chained * (uint32_t)W;
-            wc[0] = (wc[0] & 0xFFFFu) | (own << FBG_ARG_SHIFT);
-            acc &= set_value(wc, table, lane, i, U0);
+            if (pc > 0) own = chained * (uint32_t)W;
             chained = (w[0] >> FBG_F_SHIFT) & 0xFFu;
-          } else {
-            acc &= set_value(w, table, lane, i, U0);
           }
+          acc &= set_lane_value(w, lane, U0) | table[own + i];
           break;
-        case FBG_OP_LDL: cur = set_value(w, table, lane, i, U0); break;
-        case FBG_OP_OPL: cur = apply_f(f, cur, set_value(w, table, lane, i, U0)); break;
+        }
+        case FBG_OP_LDL:
+        case FBG_OP_OPL: cur = bitop3(tt, cur, set_lane_value(w, lane, U0), table[arg + i]); break;
         case FBG_OP_ST: R[arg] = cur; break;
-        case FBG_OP_OPR: cur = apply_f(f, cur, R[arg] ^ inv); break;
+        case FBG_OP_OPR:
+        case FBG_OP_LDR: cur = bitop3(tt, cur, R[arg], 0u); break;
         case FBG_OP_ACC: acc &= cur ^ inv; break;
-        case FBG_OP_LDR: cur = R[arg] ^ inv; break;
         case FBG_OP_NOT: cur = ~cur; break;
       }
       if (w[0] & FBG_INVOUT) cur = ~cur;

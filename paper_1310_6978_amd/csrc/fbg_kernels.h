@@ -7,11 +7,14 @@
 
 namespace fbg {
 
+// Registers of the general part held in VGPRs; the rest live in LDS.
+constexpr uint32_t kVgprRegs = 4;
+
 struct EvalArgs {
   const uint32_t *code;   // encoded program: instructions, then the pattern table
   uint32_t nins;          // instructions
   uint32_t ncl;           // leading clause instructions
-  uint32_t nregs;         // LDS registers per word
+  uint32_t nregs;         // registers held in LDS (beyond kVgprRegs)
   int32_t n;              // variables
   uint64_t nslices;       // 2^max(n-5, 0) valid 32-bit words
   uint64_t ntiles;        // ceil(nslices / (64 W))
@@ -32,6 +35,8 @@ struct BatchProg {
   int32_t n;
   uint64_t nslices;
   uint64_t ntiles;
+  uint32_t *out32;      // MODE_DNF: the program's DNF vector
+  uint64_t out_slices;  // MODE_DNF: 32-bit words of out32
 };
 
 struct BatchItem {
@@ -44,7 +49,7 @@ struct BatchArgs {
   const BatchProg *progs;
   const BatchItem *items;
   uint32_t nitems;
-  uint32_t max_regs;
+  uint32_t max_regs;      // LDS registers per wave (beyond kVgprRegs)
   uint32_t *head;     // queue head, zeroed before the launch
   uint64_t *counts;   // per slot; the kernel adds to it
 };
@@ -54,10 +59,15 @@ enum { EVAL_COUNT = 0, EVAL_DNF = 1, EVAL_TILECNT = 2, EVAL_ENUM = 3 };
 hipError_t launch_eval(int mode, int log2w, int var, const EvalArgs &a, int grid, int block, size_t lds,
                        hipStream_t s);
 hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hipStream_t s);
-hipError_t launch_batch(int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_batch(int mode, int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds,
+                        hipStream_t s);
+// Resident blocks per compute unit of an evaluator or batch launch.
+int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);
+int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
                        hipStream_t s);
 uint64_t scan_block_count(uint64_t n);
+// p[0..n) = 0 and, if head is not null, head[0..4) = 0 (a 16-byte area).
 hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 

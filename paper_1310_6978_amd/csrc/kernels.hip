@@ -16,8 +16,9 @@
 //                         VAR bit 0 (GEN): programs with more than clauses
 //                         VAR bit 1 (COF): the uniform-cofactor variant
 //   k_dnf_scan<MODE>      the two enumeration passes over a stored DNF vector
-//   k_batch<LOG2W, VAR>   many programs, persistent waves popping work items
-//                         (program, tile range) from a device queue
+//   k_batch<LOG2W, VAR, MODE>  many programs, persistent waves popping work
+//                         items (program, tile range) from a device queue;
+//                         counts, and with MODE_DNF the DNF vectors too
 //   k_scan_*              exclusive scan of per-tile counts
 //   k_zero_*, k_set_u64   fills (used instead of memset so that a caller may
 //                         capture the launches into a graph)
@@ -34,9 +35,6 @@ enum { MODE_COUNT = 0, MODE_DNF = 1, MODE_TILECNT = 2, MODE_ENUM = 3 };
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-__device__ __forceinline__ uint32_t fapply(uint32_t f, uint32_t a, uint32_t b) {
-  return f == FBG_F_AND ? (a & b) : (f == FBG_F_OR ? (a | b) : (a ^ b));
-}
 
 // Truth table of v_bitop3_b32(a, b, c): the function applied to the masks
 // a = 0xF0, b = 0xCC, c = 0xAA.  kTT_AND_OR(T, acc, P) = acc & (T | P).
@@ -51,6 +49,165 @@ typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 // 64-bit lane mask (a VCC-style mask, so this is one v_cndmask).
 __device__ __forceinline__ uint32_t lane_part(uint64_t lanemask) {
   return __builtin_amdgcn_inverse_ballot_w64(lanemask) ? ~0u : 0u;
+}
+
+// ---- the general part of a program (after the clause prefix)
+//
+// Every operation on cur is one v_bitop3 per word whose truth table the
+// encoder chose (w0 bits 8..15): inputs cur (0xF0), T or the register (0xCC)
+// and the word pattern P(i) (0xAA).  The cases below are every table the
+// encoder emits; a switch on a wave-uniform value costs a few scalar
+// instructions, after which each word is a single VALU instruction.
+#define FBG_LIT_TABLES(X) \
+  X(0xEE) X(0x11) X(0x66) X(0x99) X(0xE0) X(0x10) X(0x60) X(0xFE) X(0xF1) X(0xF6) \
+  X(0x1E) X(0xE1) X(0x96) X(0x1F) X(0xEF) X(0x9F) X(0x01) X(0x0E) X(0x09) X(0x69)
+#define FBG_REG_TABLES(X) \
+  X(0xC0) X(0x30) X(0xFC) X(0xF3) X(0x3C) X(0xC3) X(0x3F) X(0xCF) X(0x03) X(0x0C) X(0xCC) X(0x33)
+
+// Any truth table, bit by bit (never reached with the encoder's tables).
+__device__ __forceinline__ uint32_t bitop3_any(uint32_t a, uint32_t b, uint32_t c, uint32_t tt) {
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t m = 0; m < 8; m++) {
+    if (!((tt >> m) & 1u)) continue;
+    r |= ((m & 4u) ? a : ~a) & ((m & 2u) ? b : ~b) & ((m & 1u) ? c : ~c);
+  }
+  return r;
+}
+
+// cur = bitop3(cur, b, c) in place: the tied operand keeps cur in the same
+// registers in every case of the dispatch, so the cases merge without copies.
+#define FBG_BITOP3_INPLACE(d, b, c, tt) \
+  asm("v_bitop3_b32 %0, %0, %1, %2 bitop3:" #tt : "+v"(d) : "v"(b), "s"(c))
+#define FBG_BITOP3_INPLACE_2(d, b, tt) asm("v_bitop3_b32 %0, %0, %1, 0 bitop3:" #tt : "+v"(d) : "v"(b))
+
+template <int W>
+__device__ __forceinline__ void lit_op(uint32_t tt, uint32_t (&cur)[W], uint32_t T, const uint32_t (&P)[W]) {
+  switch (tt) {
+#define FBG_CASE(x)                                                                    \
+  case x:                                                                              \
+    _Pragma("unroll") for (int i = 0; i < W; i++) FBG_BITOP3_INPLACE(cur[i], T, P[i], x); \
+    break;
+    FBG_LIT_TABLES(FBG_CASE)
+#undef FBG_CASE
+    default:
+#pragma unroll
+      for (int i = 0; i < W; i++) cur[i] = bitop3_any(cur[i], T, P[i], tt);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void reg_op(uint32_t tt, uint32_t (&cur)[W], const uint32_t (&R)[W]) {
+  switch (tt) {
+#define FBG_CASE(x)                                                                    \
+  case x:                                                                              \
+    _Pragma("unroll") for (int i = 0; i < W; i++) FBG_BITOP3_INPLACE_2(cur[i], R[i], x); \
+    break;
+    FBG_REG_TABLES(FBG_CASE)
+#undef FBG_CASE
+    default:
+#pragma unroll
+      for (int i = 0; i < W; i++) cur[i] = bitop3_any(cur[i], R[i], 0u, tt);
+  }
+}
+
+// Registers 0..kVgprRegs-1 live in VGPRs (selected by a wave-uniform switch);
+// higher ones in LDS, W*64 words each (the launch sizes LDS for those only).
+static_assert(kVgprRegs == 4, "the register switches below name registers 0..3");
+
+template <int LOG2W>
+__device__ __forceinline__ void run_general(const code_ptr code, const code_ptr table, code_ptr w, uint32_t ncl,
+                                            uint32_t nins, uint64_t U0, uint32_t lane,
+                                            uint32_t (&acc)[1 << LOG2W], uint32_t *__restrict__ regs) {
+  constexpr int W = 1 << LOG2W;
+  uint32_t cur[W], rv[kVgprRegs][W], tmp[W];
+#pragma unroll
+  for (int i = 0; i < W; i++) cur[i] = 0u;
+#pragma unroll
+  for (uint32_t r = 0; r < kVgprRegs; r++)
+#pragma unroll
+    for (int i = 0; i < W; i++) rv[r][i] = 0u;
+  (void)code;
+  for (uint32_t pc = ncl; pc < nins; ++pc, w += FBG_INS_WORDS) {
+    const u32x8 ins = *(const __attribute__((address_space(4))) u32x8 *)w;
+    const uint32_t w0 = ins[0];
+    const uint32_t op = w0 & 15u;
+    const uint32_t tt = (w0 >> FBG_F_SHIFT) & 0xFFu;
+    if (op <= FBG_OP_OPL) {
+      const uint64_t lm = (uint64_t)ins[2] | ((uint64_t)ins[3] << 32);
+      const uint64_t sel = (uint64_t)ins[4] | ((uint64_t)ins[5] << 32);
+      const code_ptr Pp = table + (w0 >> FBG_ARG_SHIFT);
+      uint32_t P[W];
+#pragma unroll
+      for (int i = 0; i < W; i++) P[i] = Pp[i];
+      uint32_t T;
+      if (!(w0 & FBG_XORSET)) {
+        const uint64_t neg = (uint64_t)ins[6] | ((uint64_t)ins[7] << 32);
+        const uint64_t lmq = lm | (((U0 & sel) != neg) ? ~0ull : 0ull);
+        T = __builtin_amdgcn_inverse_ballot_w64(lmq) ? ~0u : ins[1];
+      } else {
+        const uint32_t S = ins[1] ^ ((__popcll(U0 & sel) & 1) ? ~0u : 0u);
+        T = lane_part(lm) ^ S;
+      }
+      if (op == FBG_OP_CL) {  // a clause outside the prefix (the compiler emits none)
+#pragma unroll
+        for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
+        continue;
+      }
+      lit_op<W>(tt, cur, T, P);
+      continue;
+    }
+    const uint32_t r = w0 >> FBG_ARG_SHIFT;
+    switch (op) {
+      case FBG_OP_ST:
+        switch (r) {
+#define FBG_ST(k) \
+  case k:         \
+    _Pragma("unroll") for (int i = 0; i < W; i++) rv[k][i] = cur[i]; \
+    break;
+          FBG_ST(0) FBG_ST(1) FBG_ST(2) FBG_ST(3)
+#undef FBG_ST
+          default: {
+            uint32_t *R = regs + (size_t)(r - kVgprRegs) * (W * 64) + lane;
+#pragma unroll
+            for (int i = 0; i < W; i++) R[i * 64] = cur[i];
+          }
+        }
+        break;
+      case FBG_OP_OPR:
+      case FBG_OP_LDR:
+        switch (r) {
+          case 0: reg_op<W>(tt, cur, rv[0]); break;
+          case 1: reg_op<W>(tt, cur, rv[1]); break;
+          case 2: reg_op<W>(tt, cur, rv[2]); break;
+          case 3: reg_op<W>(tt, cur, rv[3]); break;
+          default: {
+            const uint32_t *R = regs + (size_t)(r - kVgprRegs) * (W * 64) + lane;
+#pragma unroll
+            for (int i = 0; i < W; i++) tmp[i] = R[i * 64];
+            reg_op<W>(tt, cur, tmp);
+          }
+        }
+        break;
+      case FBG_OP_ACC:
+        if (w0 & FBG_INV) {
+#pragma unroll
+          for (int i = 0; i < W; i++) acc[i] &= ~cur[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < W; i++) acc[i] &= cur[i];
+        }
+        break;
+      default:  // FBG_OP_NOT
+#pragma unroll
+        for (int i = 0; i < W; i++) cur[i] = ~cur[i];
+        break;
+    }
+    if (w0 & FBG_INVOUT) {  // ST / ACC / NOT only: the encoder folds it into the table elsewhere
+#pragma unroll
+      for (int i = 0; i < W; i++) cur[i] = ~cur[i];
+    }
+  }
 }
 
 // Interpret one program over the W words of this lane in tile group U0.
@@ -152,73 +309,7 @@ __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g,
   }
   }
   if (!GEN) return;
-
-  // ---- general structure through cur and the LDS registers
-  uint32_t cur[W];
-#pragma unroll
-  for (int i = 0; i < W; i++) cur[i] = 0u;
-  for (uint32_t pc = ncl; pc < nins; ++pc, w += FBG_INS_WORDS) {
-    const uint32_t w0 = w[0];
-    const uint32_t op = w0 & 15u;
-    const uint32_t invm = (w0 & FBG_INV) ? ~0u : 0u;
-    if (op <= FBG_OP_OPL) {
-      // literal set L = mconst OP V(lane) OP P(i) OP Q(U0), then cur = f(cur, L)
-      const uint64_t lm = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
-      const uint64_t sel = (uint64_t)w[4] | ((uint64_t)w[5] << 32);
-      const bool isx = (w0 & FBG_XORSET) != 0;
-      uint32_t S;
-      if (!isx) {
-        const uint64_t neg = (uint64_t)w[6] | ((uint64_t)w[7] << 32);
-        S = ((U0 & sel) != neg) ? ~0u : w[1];
-      } else {
-        S = w[1] ^ ((__popcll(U0 & sel) & 1) ? ~0u : 0u);
-      }
-      const uint32_t V = lane_part(lm);
-      const code_ptr P = table + (w0 >> FBG_ARG_SHIFT);
-      if (op == FBG_OP_CL) {  // a clause outside the prefix (the compiler emits none)
-#pragma unroll
-        for (int i = 0; i < W; i++) acc[i] &= V | (S | P[i]);
-        continue;
-      }
-      const uint32_t f = (op == FBG_OP_LDL) ? 3u : ((w0 >> FBG_F_SHIFT) & 3u);
-#pragma unroll
-      for (int i = 0; i < W; i++) {
-        const uint32_t L = (isx ? (V ^ (S ^ P[i])) : (V | (S | P[i]))) ^ invm;
-        cur[i] = (f == 3u) ? L : fapply(f, cur[i], L);
-      }
-    } else {
-      const uint32_t r = w0 >> FBG_ARG_SHIFT;
-      uint32_t *R = regs + (size_t)r * (W * 64) + lane;
-      switch (op) {
-        case FBG_OP_ST:
-#pragma unroll
-          for (int i = 0; i < W; i++) R[i * 64] = cur[i];
-          break;
-        case FBG_OP_OPR: {
-          const uint32_t f = (w0 >> FBG_F_SHIFT) & 3u;
-#pragma unroll
-          for (int i = 0; i < W; i++) cur[i] = fapply(f, cur[i], R[i * 64] ^ invm);
-          break;
-        }
-        case FBG_OP_ACC:
-#pragma unroll
-          for (int i = 0; i < W; i++) acc[i] &= cur[i] ^ invm;
-          break;
-        case FBG_OP_LDR:
-#pragma unroll
-          for (int i = 0; i < W; i++) cur[i] = R[i * 64] ^ invm;
-          break;
-        default:  // FBG_OP_NOT
-#pragma unroll
-          for (int i = 0; i < W; i++) cur[i] = ~cur[i];
-          break;
-      }
-    }
-    if (w0 & FBG_INVOUT) {
-#pragma unroll
-      for (int i = 0; i < W; i++) cur[i] = ~cur[i];
-    }
-  }
+  run_general<LOG2W>(code, table, w, ncl, nins, U0, lane, acc, regs);
 }
 
 // Zero the words of this lane that lie beyond the valuation space.
@@ -296,6 +387,23 @@ __device__ __forceinline__ void tile_compact(const uint32_t (&acc)[1 << LOG2W], 
   }
 }
 
+// Store the W words of this lane; the stores of a whole tile are issued
+// unconditionally (streaming: the vector is not read back by this kernel).
+template <int LOG2W>
+__device__ __forceinline__ void store_tile(const uint32_t (&acc)[1 << LOG2W], uint64_t U0, uint32_t lane,
+                                           uint32_t *out32, uint64_t out_slices) {
+  constexpr int W = 1 << LOG2W;
+  uint32_t *dst = out32 + U0 * 64 + lane;
+  if ((U0 + W) * 64 <= out_slices) {  // wave-uniform
+#pragma unroll
+    for (int i = 0; i < W; i++) __builtin_nontemporal_store(acc[i], dst + i * 64);
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; i++)
+      if ((U0 + i) * 64 + lane < out_slices) dst[i * 64] = acc[i];
+  }
+}
+
 template <int LOG2W, int MODE, int VAR>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
   constexpr int W = 1 << LOG2W;
@@ -321,11 +429,7 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
       for (int i = 0; i < W; i++) c += __popc(acc[i]);
       total += c;
     } else if (MODE == MODE_DNF) {
-#pragma unroll
-      for (int i = 0; i < W; i++) {
-        const uint64_t s = (U0 + i) * 64 + lane;
-        if (s < a.out_slices) a.out32[s] = acc[i];
-      }
+      store_tile<LOG2W>(acc, U0, lane, a.out32, a.out_slices);
     } else if (MODE == MODE_TILECNT) {
       tile_count_out<LOG2W>(acc, lane, a.tile_counts + t);
     } else {
@@ -354,10 +458,16 @@ __global__ __launch_bounds__(256) void k_dnf_scan(EvalArgs a) {
       if (a.tile_counts[t] == 0u) continue;
     }
     uint32_t acc[W];
+    const uint32_t *src = a.out32 + U0 * 64 + lane;
+    if ((U0 + W) * 64 <= a.nslices) {  // wave-uniform: a whole tile, every load issued at once
 #pragma unroll
-    for (int i = 0; i < W; i++) {
-      const uint64_t s = (U0 + i) * 64 + lane;
-      acc[i] = s < a.nslices ? a.out32[s] : 0u;
+      for (int i = 0; i < W; i++) acc[i] = __builtin_nontemporal_load(src + i * 64);
+    } else {
+#pragma unroll
+      for (int i = 0; i < W; i++) {
+        const uint64_t s = (U0 + i) * 64 + lane;
+        acc[i] = s < a.nslices ? src[i * 64] : 0u;
+      }
     }
     if (MODE == MODE_TILECNT)
       tile_count_out<LOG2W>(acc, lane, a.tile_counts + t);
@@ -368,33 +478,42 @@ __global__ __launch_bounds__(256) void k_dnf_scan(EvalArgs a) {
 
 // ---------------------------------------------------------------- batches
 
-template <int LOG2W, int VAR>
+// MODE_COUNT adds each program's model count into its slot; MODE_DNF also
+// writes the program's DNF vector (BatchProg.out32).  The item and program
+// tables are read-only during the launch: scalar loads, so tile indices and
+// code pointers stay wave-uniform.
+template <int LOG2W, int VAR, int MODE>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
   constexpr int W = 1 << LOG2W;
   extern __shared__ uint32_t lds[];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = uni(threadIdx.x) >> 6;
   uint32_t *regs = lds + (size_t)wib * a.max_regs * (W * 64);
+  typedef const __attribute__((address_space(4))) BatchItem *item_ptr;
+  typedef const __attribute__((address_space(4))) BatchProg *prog_ptr;
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = atomicAdd(a.head, 1u);
     item = uni(__shfl(item, 0, 64));
     if (item >= a.nitems) break;  // every wave leaves once the queue is drained
-    const BatchItem it = a.items[item];
-    const BatchProg p = a.progs[it.prog];
+    const item_ptr it = (item_ptr)a.items + item;
+    const uint64_t t0 = it->t0, t1 = it->t1;
+    const uint32_t slot = it->slot;
+    const prog_ptr p = (prog_ptr)a.progs + it->prog;
     uint64_t total = 0;
-    for (uint64_t t = it.t0; t < it.t1; ++t) {
+    for (uint64_t t = t0; t < t1; ++t) {
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
-      run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(p.code, p.nins, p.ncl, U0, lane, acc, regs);
-      mask_tail<LOG2W>(acc, U0, lane, p.nslices, p.n);
+      run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(p->code, p->nins, p->ncl, U0, lane, acc, regs);
+      mask_tail<LOG2W>(acc, U0, lane, p->nslices, p->n);
+      if (MODE == MODE_DNF) store_tile<LOG2W>(acc, U0, lane, p->out32, p->out_slices);
       uint32_t c = 0;
 #pragma unroll
       for (int i = 0; i < W; i++) c += __popc(acc[i]);
       total += c;
     }
     const uint64_t s = wave_sum_u64(total);
-    if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + it.slot), (unsigned long long)s);
+    if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + slot), (unsigned long long)s);
   }
 }
 
@@ -465,10 +584,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *in,
 
 // ------------------------------------------------------------------ fills
 
+// p[0..n) = 0 and, when head is given, the four queue heads head[0..4).
 __global__ void k_zero_u64(uint64_t *p, uint64_t n, uint32_t *head) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
-  if (head && i == 0) *head = 0;
+  if (head && i < 4) head[i] = 0;
 }
 
 __global__ void k_set_u64(uint64_t *p, uint64_t v) {
@@ -507,18 +627,30 @@ hipError_t launch_eval_mode(int log2w, int var, const EvalArgs &a, int grid, int
   return hipErrorInvalidValue;
 }
 
-template <int VAR>
+template <int VAR, int MODE>
 hipError_t launch_batch_w(int log2w, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s) {
   switch (log2w) {
-    case 0: hipLaunchKernelGGL((dev::k_batch<0, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 1: hipLaunchKernelGGL((dev::k_batch<1, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((dev::k_batch<2, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((dev::k_batch<3, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((dev::k_batch<4, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((dev::k_batch<5, VAR>), dim3(grid), dim3(block), lds, s, a); break;
+    case 0: hipLaunchKernelGGL((dev::k_batch<0, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
+    case 1: hipLaunchKernelGGL((dev::k_batch<1, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((dev::k_batch<2, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((dev::k_batch<3, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((dev::k_batch<4, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
+    case 5: hipLaunchKernelGGL((dev::k_batch<5, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_batch_mode(int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds,
+                             hipStream_t s) {
+  switch (var) {
+    case 0: return launch_batch_w<0, MODE>(log2w, a, grid, block, lds, s);
+    case 1: return launch_batch_w<1, MODE>(log2w, a, grid, block, lds, s);
+    case 2: return launch_batch_w<2, MODE>(log2w, a, grid, block, lds, s);
+    case 3: return launch_batch_w<3, MODE>(log2w, a, grid, block, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -544,14 +676,79 @@ hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hip
   return hipGetLastError();
 }
 
-hipError_t launch_batch(int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s) {
-  switch (var) {
-    case 0: return launch_batch_w<0>(log2w, a, grid, block, lds, s);
-    case 1: return launch_batch_w<1>(log2w, a, grid, block, lds, s);
-    case 2: return launch_batch_w<2>(log2w, a, grid, block, lds, s);
-    case 3: return launch_batch_w<3>(log2w, a, grid, block, lds, s);
-  }
+hipError_t launch_batch(int mode, int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds,
+                        hipStream_t s) {
+  if (mode == dev::MODE_COUNT) return launch_batch_mode<dev::MODE_COUNT>(log2w, var, a, grid, block, lds, s);
+  if (mode == dev::MODE_DNF) return launch_batch_mode<dev::MODE_DNF>(log2w, var, a, grid, block, lds, s);
   return hipErrorInvalidValue;
+}
+
+namespace {
+
+int blocks_per_cu(const void *kernel, int block, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, lds) != hipSuccess || nb <= 0) nb = 1;
+  return nb;
+}
+
+template <int MODE, int VAR>
+int eval_occ_w(int log2w, int block, size_t lds) {
+  switch (log2w) {
+    case 0: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<0, MODE, VAR>), block, lds);
+    case 1: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<1, MODE, VAR>), block, lds);
+    case 2: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<2, MODE, VAR>), block, lds);
+    case 3: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<3, MODE, VAR>), block, lds);
+    case 4: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<4, MODE, VAR>), block, lds);
+    default: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<5, MODE, VAR>), block, lds);
+  }
+}
+
+template <int MODE>
+int eval_occ_mode(int log2w, int var, int block, size_t lds) {
+  switch (var) {
+    case 0: return eval_occ_w<MODE, 0>(log2w, block, lds);
+    case 1: return eval_occ_w<MODE, 1>(log2w, block, lds);
+    case 2: return eval_occ_w<MODE, 2>(log2w, block, lds);
+    default: return eval_occ_w<MODE, 3>(log2w, block, lds);
+  }
+}
+
+template <int VAR, int MODE>
+int batch_occ_w(int log2w, int block, size_t lds) {
+  switch (log2w) {
+    case 0: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<0, VAR, MODE>), block, lds);
+    case 1: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<1, VAR, MODE>), block, lds);
+    case 2: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<2, VAR, MODE>), block, lds);
+    case 3: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<3, VAR, MODE>), block, lds);
+    case 4: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<4, VAR, MODE>), block, lds);
+    default: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<5, VAR, MODE>), block, lds);
+  }
+}
+
+template <int MODE>
+int batch_occ_mode(int log2w, int var, int block, size_t lds) {
+  switch (var) {
+    case 0: return batch_occ_w<0, MODE>(log2w, block, lds);
+    case 1: return batch_occ_w<1, MODE>(log2w, block, lds);
+    case 2: return batch_occ_w<2, MODE>(log2w, block, lds);
+    default: return batch_occ_w<3, MODE>(log2w, block, lds);
+  }
+}
+
+}  // namespace
+
+int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
+  switch (mode) {
+    case dev::MODE_COUNT: return eval_occ_mode<dev::MODE_COUNT>(log2w, var, block, lds);
+    case dev::MODE_DNF: return eval_occ_mode<dev::MODE_DNF>(log2w, var, block, lds);
+    case dev::MODE_TILECNT: return eval_occ_mode<dev::MODE_TILECNT>(log2w, var, block, lds);
+    default: return eval_occ_mode<dev::MODE_ENUM>(log2w, var, block, lds);
+  }
+}
+
+int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
+  if (mode == dev::MODE_DNF) return batch_occ_mode<dev::MODE_DNF>(log2w, var, block, lds);
+  return batch_occ_mode<dev::MODE_COUNT>(log2w, var, block, lds);
 }
 
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,

@@ -80,6 +80,8 @@ def _load():
         "fbg_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(Tune), ctypes.POINTER(vp)]),
         "fbg_batch_count": (i32, [vp, vp, vp]),
         "fbg_batch_count_graph": (i32, [vp, vp, vp]),
+        "fbg_batch_set_dnf_outputs": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)]),
+        "fbg_batch_eval_dnf": (i32, [vp, vp, vp]),
         "fbg_batch_free": (None, [vp]),
         "fbg_count_batch": (i32, [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(Tune), vp]),
         "fbg_enumerate_dnf": (i32, [vp, i32, vp, u64, vp, vp]),
@@ -106,7 +108,8 @@ lib = _load()
 EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_program_free", "fbg_program_get_info", "fbg_program_set_tuning",
             "fbg_eval_dnf", "fbg_eval_dnf_tuned",
             "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_dnf", "fbg_batch_create",
-            "fbg_batch_count", "fbg_batch_count_graph", "fbg_batch_free", "fbg_count_batch", "fbg_program_tiles", "fbg_server_create",
+            "fbg_batch_count", "fbg_batch_count_graph", "fbg_batch_set_dnf_outputs", "fbg_batch_eval_dnf",
+            "fbg_batch_free", "fbg_count_batch", "fbg_program_tiles", "fbg_server_create",
             "fbg_server_launch", "fbg_server_free", "fbg_program_emulate", "fbg_program_disasm",
             "fbg_last_error", "fbg_last_error_offset", "fbg_version")
 
@@ -329,6 +332,23 @@ class Batch:
         f = lib.fbg_batch_count_graph if graph else lib.fbg_batch_count
         _check(f(self._h, _ptr(out), _stream(stream)))
         return out
+
+    def set_dnf_outputs(self, outs):
+        """outs: one int64 device tensor per program (at least its dnf_words)."""
+        if len(outs) != len(self._progs):
+            raise ValueError("need %d output tensors" % len(self._progs))
+        self._outs = list(outs)  # the buffers must outlive the launches
+        ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        sizes = (ctypes.c_uint64 * len(outs))(*[o.numel() for o in outs])
+        _check(lib.fbg_batch_set_dnf_outputs(self._h, ptrs, sizes))
+
+    def eval_dnf(self, counts=None, stream=None):
+        """Every program's DNF vector into its output tensor and its count
+        into counts, in one launch (fbg_batch_eval_dnf)."""
+        if counts is None:
+            counts = _device_u64(len(self._progs))
+        _check(lib.fbg_batch_eval_dnf(self._h, _ptr(counts), _stream(stream)))
+        return counts
 
     def free(self):
         if getattr(self, "_h", None) is not None:

@@ -45,3 +45,18 @@ def random_cnf(rng, n, m, width=(1, 5)):
             lits.append(("~x%d" % k) if rng.random() < 0.5 else ("x%d" % k))
         lines.append(" | ".join(lits))
     return "\n".join(lines) + "\n"
+
+
+def many_registers(rng, n, k):
+    """k shared subterms that are all live at once: each is used once in an
+    OR over all of them and again in an XOR over all of them, so the
+    compiled program needs about k registers."""
+    lines = []
+    for i in range(k):
+        a, b, c, d = rng.sample(range(n), 4)
+        ops = rng.choice([("&", "^", "|"), ("|", "&", "^"), ("^", "|", "&")])
+        lines.append("t%d = (x%d %s x%d) %s (x%d %s ~x%d)" % (i, a, ops[0], b, ops[1], c, ops[2], d))
+    names = ["t%d" % i for i in range(k)]
+    rng.shuffle(names)
+    lines.append("(%s) | ~(%s)" % (" | ".join(names), " ^ ".join(reversed(names))))
+    return "\n".join(lines) + "\n"

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import workloads
 from paper_1310_6978_amd import fbg
-from tests.formula_gen import random_cnf, random_program
+from tests.formula_gen import many_registers, random_cnf, random_program
 
 WPL = [1, 2, 4, 8, 16, 32]
 
@@ -205,3 +205,12 @@ def test_tile_only_clauses_lead_the_prefix():
         k = kinds.index(False) if False in kinds else len(kinds)
         assert k > 0 and not any(kinds[k:]), w
     check("(x0|x1) & (x22|~x23) & (x2|x12) & ~x21 & (x18|x20)", 24, wpl=[1, 32])
+
+
+@pytest.mark.parametrize("k", [3, 5, 9, 17])
+def test_registers_beyond_the_vgpr_set(k):
+    # registers 0..3 live in VGPRs, the rest in LDS: programs on both sides
+    rng = random.Random(4400 + k)
+    text = many_registers(rng, 14, k)
+    p = check(text, 14, wpl=[1, 4, 8])
+    assert p.info["n_regs"] >= min(k, 5) - 1

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import workloads
-from tests.formula_gen import random_cnf, random_program
+from tests.formula_gen import many_registers, random_cnf, random_program
 
 pytestmark = pytest.mark.gpu
 
@@ -343,3 +343,57 @@ def test_autotuner_choice_is_exact(F, tmp_path):
     assert w in autotune.CANDIDATES and p.info["words_per_lane"] == w
     assert gpu_count(F, p) == oracle.count(text, n)
     assert t.table[autotune.key_of(p)]["ms"]
+
+
+def test_batch_eval_dnf_writes_every_vector(F):
+    import torch
+    rng = random.Random(77)
+    texts = [("x0", 1), ("~x2 | x1", 3), ("0", 7)]
+    texts += [workloads.random_3cnf(rng.choice([12, 17, 21, 23]), 50, s) for s in range(5)]
+    texts += [workloads.random_dag(rng.choice([14, 19]), rng.randrange(50, 400), s) for s in range(4)]
+    texts.append(workloads.triangle_free(6))
+    progs = [F.Program(t, n) for t, n in texts]
+    outs = [torch.full((F.dnf_words(n) + 3,), -1, dtype=torch.int64, device="cuda") for _, n in texts]
+    for wpl, cof in ((0, False), (1, False), (16, True), (32, False)):
+        b = F.Batch(progs, words_per_lane=wpl, cofactor=cof)
+        b.set_dnf_outputs(outs)
+        for rep in range(2):
+            for o in outs:
+                o.fill_(-1)
+            counts = host(b.eval_dnf())
+            for (t, n), o, c in zip(texts, outs, counts):
+                want = oracle.dnf(t, n)
+                got = host(o)
+                assert np.array_equal(got[:len(want)], want), (wpl, n, t[:60])
+                assert np.all(got[len(want):] == np.uint64(2**64 - 1))   # nothing past the vector
+                assert int(c) == int(np.unpackbits(want.view(np.uint8)).sum())
+        b.free()
+
+
+def test_batch_eval_dnf_argument_errors(F):
+    import torch
+    p = F.Program("x3 | x9", 12)
+    b = F.Batch([p])
+    with pytest.raises(F.FbgError) as ei:
+        b.eval_dnf()                               # no outputs set
+    assert ei.value.status == F.FBG_E_INVAL
+    with pytest.raises(F.FbgError) as ei:
+        b.set_dnf_outputs([torch.empty(10, dtype=torch.int64, device="cuda")])
+    assert ei.value.status == F.FBG_E_INVAL
+    with pytest.raises(ValueError):
+        b.set_dnf_outputs([])
+    b.free()
+
+
+@pytest.mark.parametrize("k", [3, 5, 9, 17])
+def test_registers_beyond_the_vgpr_set(F, k):
+    rng = random.Random(4400 + k)
+    for n in (12, 19):
+        text = many_registers(rng, n, k)
+        p = full_check(F, text, n, wpls=[1, 2, 4, 8, 16])
+        assert p.info["n_regs"] >= min(k, 5) - 1
+        # and inside a batch next to clause-only programs (two plans)
+        cnf = workloads.random_3cnf(n, 40, k)
+        progs = [p, F.Program(*cnf)]
+        want = [oracle.count(text, n), oracle.count(*cnf)]
+        assert host(F.count_batch(progs)).tolist() == want
