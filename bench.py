@@ -26,6 +26,10 @@ Workload c4: the serving loop (Poisson arrivals, continuous batching),
 reporting p50/p99 latency beside valuations/s.
 Workload posets: labeled partial orders through the c-partition counting
 procedure (bounded posets on --posets-n elements).
+Workload theories: one count of each propositional theory of the paper's
+examples, at every tiling, with and without the uniform-cofactor variant.
+Workload unlabeled: non-isomorphic partial orders (7 elements) and graphs (9
+vertices) by the Frobenius-Burnside lemma.
 Workload copy: a 1 GiB device copy, the calibration kernel for the HBM byte
 counters.
 """
@@ -49,10 +53,9 @@ METRIC = "valuations/sec and % VALU bitwise peak (batched vs plain, bit-exact co
 # HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
 # the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
-# half the bytes copied, WRITE_SIZE all of them): 2 x 2511.5 KiB fetched and
-# 8389827.2 KiB written by k_batch<5, 0, 1> (16 x 2^32-bit DNF vectors).
-# Reset to None whenever that kernel changes, until measured again.
-C1_TRAFFIC = (2 * 2511.5 + 8389827.2) * 1024
+# half the bytes copied, WRITE_SIZE all of them).  None whenever that kernel
+# has changed since the counters were taken.
+C1_TRAFFIC = None
 
 
 class ProgramCache:
@@ -279,14 +282,19 @@ def bench_c4(args, torch, fbg):
     import oracle
     from paper_1310_6978_amd.serve import ServeLoop
     from workloads.serving import request_stream
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     loop = ServeLoop(words_per_lane=16, slice_words=args.slice_words, max_active=256)
     warm = request_stream(50, 0.0, seed=99)
-    loop.run(warm, realtime=False)
-    sat = loop.run(request_stream(args.sat_requests, 0.0, seed=1), realtime=False)
+    loop.run(warm, realtime=False, log=log)
+    log("c4: saturation run, %d requests at once" % args.sat_requests)
+    sat = loop.run(request_stream(args.sat_requests, 0.0, seed=1), realtime=False, log=log)
     rate = sat["requests_per_s"]
     qps = args.load * rate
+    log("c4: saturation %.1f req/s; timed run of %d requests at %.1f req/s" % (rate, args.requests, qps))
     reqs = request_stream(args.requests, qps, seed=0)
-    res = loop.run(reqs, realtime=True)
+    res = loop.run(reqs, realtime=True, log=log)
     loop.close()
     closed = {"equivalence_k9": 21147, "permutations_k5": 120, "triangle_free_k8": 4682270}
     ok = True
@@ -358,6 +366,80 @@ def bench_posets(args, torch, fbg):
             "batched_count_ms_full_evaluation": times[False], "first_run_wall_s_with_compile": wall_first}
 
 
+def bench_theories(args, torch, fbg):
+    """The propositional theories of the paper's examples: one count per
+    theory at every tiling, full evaluation and uniform cofactor, against
+    their closed-form counts."""
+    import workloads
+    cases = [("equivalence relations k=9 (Bell 9)", workloads.equivalence_relations(9), 21147),
+             ("triangle-free graphs k=8", workloads.triangle_free(8), 4682270),
+             ("5x5 permutation matrices", workloads.permutation_matrices(5), 120),
+             ("equivalence relations k=6", workloads.equivalence_relations(6), 203)]
+    stream = torch.cuda.current_stream()
+    out = torch.empty(1, dtype=torch.int64, device="cuda")
+    rows, ok, vals, best_total = [], True, 0.0, 0.0
+    for name, (text, n), want in cases:
+        p = fbg.Program(text, n)
+        best = None
+        for w in (8, 16, 32):
+            for cof in (False, True):
+                fbg.count(p, out=out, stream=stream, words_per_lane=w, cofactor=cof)
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(args.steps):
+                    fbg.count(p, out=out, stream=stream, words_per_lane=w, cofactor=cof)
+                b.record(stream)
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / args.steps
+                got = int(out.cpu().numpy().view("uint64")[0])
+                ok = ok and got == want
+                rows.append({"theory": name, "n": n, "words_per_lane": w, "cofactor": cof, "ms": ms,
+                             "alg_frac": p.info["l2in"] * 2.0 ** n / (ms / 1e3) / VALU_BITWISE_PEAK, "count": got})
+                if not cof and (best is None or ms < best):
+                    best = ms
+        vals += 2.0 ** n
+        best_total += best
+    return {"metric": "valuations/s of one full-evaluation count per theory (best tiling)",
+            "value": vals / (best_total / 1e3), "unit": "valuations/s", "ms_per_step": best_total, "dtype": "u32",
+            "config": {"workload": "propositional theories: equivalence k=9 and k=6, triangle-free k=8, "
+                                   "5x5 permutations; one count each"},
+            "counts_match_closed_forms": ok, "runs": rows}
+
+
+def bench_unlabeled(args, torch, fbg):
+    """Non-isomorphic models by the Frobenius-Burnside lemma: one batched
+    count of the fixed-point theories of every cycle type."""
+    from paper_1310_6978_amd import frontend, unlabeled
+    posets = ("S = range({n})\nS2 = perm(S, 2)\nS3 = perm(S, 3)\n"
+              "anti = A[i,j:S2] (~p(i,j) | ~p(j,i))\n"
+              "trans = A[i,j,k:S3] (~(p(i,j) & p(j,k)) | p(i,k))\n"
+              "assumptions = {{p(i,i): 1 for i in S}}\n")
+    graphs = ("S = range({n})\nS2 = perm(S, 2)\nsym = A[i,j:S2] (~e(i,j) | e(j,i))\n"
+              "assumptions = {{e(i,i): 0 for i in S}}\n")
+    rows, total_ms = [], 0.0
+    for name, script, n in (("partial orders", posets, 7), ("graphs", graphs, 9)):
+        tr = frontend.translate(script.format(n=n))
+        t0 = time.perf_counter()
+        res = unlabeled.count_translation(tr, range(n), cofactor=True)
+        torch.cuda.synchronize()
+        first = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = unlabeled.count_translation(tr, range(n), cofactor=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        total_ms += ms
+        rows.append({"structures": name, "n": n, "letters": tr.n, "cycle_types": len(res.terms),
+                     "unlabeled": res.unlabeled, "labeled": res.labeled, "ms_with_compile": ms,
+                     "first_ms": first})
+    return {"metric": "non-isomorphic models counted per second (Frobenius-Burnside, one batched count)",
+            "value": len(rows) / (total_ms / 1e3), "unit": "theories/s", "ms_per_step": total_ms, "dtype": "u32",
+            "config": {"workload": "unlabeled partial orders on 7 elements and graphs on 9 vertices"},
+            "runs": rows}
+
+
 def bench_copy(args, torch):
     """A plain device-to-device copy of 1 GiB: the calibration kernel for the
     FETCH_SIZE / WRITE_SIZE counters (it must read and write 1 GiB)."""
@@ -382,7 +464,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "posets", "copy"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "posets", "theories", "unlabeled", "copy"])
     ap.add_argument("--posets-n", type=int, default=11, help="posets: bounded posets on n elements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=20000, help="c4: requests in the timed run")
@@ -409,6 +491,10 @@ def main():
         res = bench_c4(args, torch, fbg)
     elif args.workload == "posets":
         res = bench_posets(args, torch, fbg)
+    elif args.workload == "theories":
+        res = bench_theories(args, torch, fbg)
+    elif args.workload == "unlabeled":
+        res = bench_unlabeled(args, torch, fbg)
     else:
         res = bench_copy(args, torch)
     out = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,

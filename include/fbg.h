@@ -131,6 +131,31 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
 fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *assume, uint32_t flags,
                               fbg_program **out);
 
+/* Entries of the substitution of fbg_compile_subst besides variable indices. */
+#define FBG_SUBST_ZERO (-1)
+#define FBG_SUBST_ONE (-2)
+
+/*
+ * fbg_compile_subst -- fbg_compile after a substitution of the variables:
+ * letters replaced by constants (killing, Section 3.3) or identified with
+ * one another.  Identifying the letters of each orbit of a permutation of the
+ * domain gives the theory of the models that the permutation fixes, which
+ * the Frobenius-Burnside counting lemma of Section 3.2 sums over.
+ *   src     formula text over x0..x{n_vars-1}.
+ *   n_vars  0 <= n_vars <= FBG_MAX_TEXT_VARS.
+ *   subst   host array of n_vars entries (read during the call):
+ *           FBG_SUBST_ZERO / FBG_SUBST_ONE put the constant in place of xk,
+ *           j in [0, n_free) puts the program's variable j (several letters
+ *           may map to one j).  May be NULL only when n_vars = 0.
+ *   n_free  the program's variables, 0 <= n_free <= FBG_MAX_VARS; a j that
+ *           no letter maps to still indexes valuations (and doubles counts).
+ *   flags   0 (reserved).
+ * FBG_E_INVAL for an entry outside [-2, n_free); otherwise as fbg_compile.
+ * Synchronous.
+ */
+fbg_status fbg_compile_subst(const char *src, int32_t n_vars, const int32_t *subst, int32_t n_free, uint32_t flags,
+                             fbg_program **out);
+
 /* Release a program and its device copy.  NULL is a no-op.  The caller must
    make sure no launch that uses it is still pending. */
 void fbg_program_free(fbg_program *p);

@@ -138,3 +138,21 @@ def bitpar_dnf(src, n, threads=0):
     out = np.zeros(dnf_words(n), dtype=np.uint64)
     _check(_load().orc_bitpar_dnf(_b(src), n, threads, _u64p(out), out.size))
     return out
+
+
+def orbits(src, n, perms, threads=0):
+    """(number of orbits of the models under the permutations of the
+    letters in ``perms`` -- a whole group, one row per element; number of
+    models).  With the group of all relabelings of a domain this is the
+    number of non-isomorphic models (Section 3.2, kappa)."""
+    perms = np.ascontiguousarray(np.asarray(perms, dtype=np.int32))
+    if perms.ndim != 2 or perms.shape[1] != n:
+        raise OracleError("perms must have shape (group size, n)")
+    lib = _load()
+    lib.orc_orbits.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                               ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+    lib.orc_orbits.restype = ctypes.c_int
+    o, t = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(lib.orc_orbits(_b(src), n, perms.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), perms.shape[0],
+                          threads, ctypes.byref(o), ctypes.byref(t)))
+    return o.value, t.value

@@ -694,3 +694,63 @@ int orc_bitpar_dnf(const char *src, int n, int threads, uint64_t *out, uint64_t 
   free_formula(&f);
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Unlabeled models (Section 3.2: kappa_{T,n} is the number of non-isomorphic
+ * models of size n).  Two labeled models are isomorphic when a permutation of
+ * the domain maps one onto the other; a permutation acts on valuations by
+ * moving the value of each letter to the letter it maps that letter to.
+ * perms holds the action of every permutation of the group on the n letters
+ * (perms[p*n + k] = image of letter k); the orbits are counted as the number
+ * of distinct smallest images, computed model by model.
+ * ---------------------------------------------------------------------- */
+
+static int cmp_u64(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? -1 : (x > y);
+}
+
+int orc_orbits(const char *src, int n, const int32_t *perms, int nperm, int threads, uint64_t *out_orbits,
+               uint64_t *out_models) {
+  uint64_t total = 0;
+  if (n < 0 || n > 40 || nperm <= 0) {
+    snprintf(g_err, sizeof g_err, "orbits: n=%d nperm=%d out of range", n, nperm);
+    return -1;
+  }
+  for (int p = 0; p < nperm; p++)
+    for (int k = 0; k < n; k++)
+      if (perms[(size_t)p * n + k] < 0 || perms[(size_t)p * n + k] >= n) {
+        snprintf(g_err, sizeof g_err, "orbits: perms[%d][%d] out of range", p, k);
+        return -1;
+      }
+  if (orc_count(src, n, threads, &total)) return -1;
+  uint64_t *m = (uint64_t *)malloc(sizeof(uint64_t) * (total ? total : 1));
+  if (!m) {
+    snprintf(g_err, sizeof g_err, "orbits: out of memory");
+    return -1;
+  }
+  uint64_t got = 0;
+  if (orc_models(src, n, threads, m, total, &got)) {
+    free(m);
+    return -1;
+  }
+  for (uint64_t i = 0; i < total; i++) {
+    uint64_t best = UINT64_MAX;
+    for (int p = 0; p < nperm; p++) {
+      const int32_t *pi = perms + (size_t)p * n;
+      uint64_t img = 0;
+      for (int k = 0; k < n; k++)
+        if ((m[i] >> k) & 1u) img |= 1ull << pi[k];
+      if (img < best) best = img;
+    }
+    m[i] = best;
+  }
+  qsort(m, total, sizeof(uint64_t), cmp_u64);
+  uint64_t orbits = 0;
+  for (uint64_t i = 0; i < total; i++)
+    if (i == 0 || m[i] != m[i - 1]) orbits++;
+  free(m);
+  *out_orbits = orbits;
+  if (out_models) *out_models = total;
+  return 0;
+}

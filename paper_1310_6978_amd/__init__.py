@@ -12,6 +12,7 @@ from .fbg import (  # noqa: F401
     as_u64,
     compile,
     compile_assume,
+    compile_subst,
     count,
     count_batch,
     dnf_words,

@@ -332,12 +332,13 @@ int64_t fbg_last_error_offset(void) { return g_err_off; }
 
 namespace {
 
-fbg_status compile_common(const char *src, int32_t n_vars, const int8_t *assume, fbg_program **out) {
+fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst, int32_t n_free,
+                          fbg_program **out) {
   fbg_program *p = new (std::nothrow) fbg_program();
   if (!p) return fail(FBG_E_NOMEM, "out of host memory");
   std::string msg;
   int64_t off = -1;
-  int st = fbg::compile_formula(src, n_vars, p->c, msg, off, assume);
+  int st = fbg::compile_formula(src, n_vars, p->c, msg, off, subst, n_free);
   if (st != FBG_OK) {
     delete p;
     g_err = msg;
@@ -395,7 +396,7 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
   if (!src) return fail(FBG_E_INVAL, "src is NULL");
   if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
   if (n_vars < 0 || n_vars > FBG_MAX_VARS) return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_VARS);
-  return compile_common(src, n_vars, nullptr, out);
+  return compile_common(src, n_vars, nullptr, 0, out);
 }
 
 fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *assume, uint32_t flags,
@@ -407,14 +408,32 @@ fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *ass
   if (n_vars < 0 || n_vars > FBG_MAX_TEXT_VARS)
     return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_TEXT_VARS);
   if (n_vars > 0 && !assume) return fail(FBG_E_INVAL, "assume is NULL");
+  std::vector<int32_t> subst((size_t)n_vars);
   int32_t nfree = 0;
   for (int32_t k = 0; k < n_vars; k++) {
     if (assume[k] < -1 || assume[k] > 1)
       return fail(FBG_E_INVAL, "assume[%d] = %d (must be -1, 0 or 1)", k, (int)assume[k]);
-    nfree += assume[k] < 0;
+    subst[(size_t)k] = assume[k] < 0 ? nfree++ : (assume[k] ? FBG_SUBST_ONE : FBG_SUBST_ZERO);
   }
   if (nfree > FBG_MAX_VARS) return fail(FBG_E_RANGE, "%d free variables (max %d)", nfree, FBG_MAX_VARS);
-  return compile_common(src, n_vars, assume, out);
+  return compile_common(src, n_vars, subst.data(), nfree, out);
+}
+
+fbg_status fbg_compile_subst(const char *src, int32_t n_vars, const int32_t *subst, int32_t n_free, uint32_t flags,
+                             fbg_program **out) {
+  if (!out) return fail(FBG_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!src) return fail(FBG_E_INVAL, "src is NULL");
+  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
+  if (n_vars < 0 || n_vars > FBG_MAX_TEXT_VARS)
+    return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_TEXT_VARS);
+  if (n_free < 0 || n_free > FBG_MAX_VARS) return fail(FBG_E_RANGE, "n_free=%d out of range [0,%d]", n_free,
+                                                       FBG_MAX_VARS);
+  if (n_vars > 0 && !subst) return fail(FBG_E_INVAL, "subst is NULL");
+  for (int32_t k = 0; k < n_vars; k++)
+    if (subst[k] < FBG_SUBST_ONE || subst[k] >= n_free)
+      return fail(FBG_E_INVAL, "subst[%d] = %d (must be -1, -2 or in [0, %d))", k, subst[k], n_free);
+  return compile_common(src, n_vars, subst, n_free, out);
 }
 
 void fbg_program_free(fbg_program *p) {

@@ -115,11 +115,11 @@ struct Parser {
   int64_t off = -1;
   int status = FBG_OK;
 
-  // Killed variables (Section 3.3): assume[k] = 0 or 1 replaces xk by that
-  // constant, which the graph folds away (the Reduction of Section 4.1);
-  // free variables take the index renum[k].  Both null: every xk is free.
-  const int8_t *assume = nullptr;
-  const int32_t *renum = nullptr;
+  // Substitution (Section 3.3, killing variables): subst[k] = -1 or -2
+  // replaces xk by the constant 0 or 1, which the graph folds away (the
+  // Reduction of Section 4.1); subst[k] = j >= 0 makes xk the program's
+  // variable j (several letters may share one).  Null: every xk is itself.
+  const int32_t *subst = nullptr;
 
   Parser(const char *s, int nv, Graph &gr) : src(s), n(nv), g(gr) {}
 
@@ -213,10 +213,12 @@ struct Parser {
       case Tok::VAR:
         if (t.val >= n) return fail(FBG_E_RANGE, t.pos, "variable x" + std::to_string(t.val) + " >= n");
         p++;
-        if (assume && assume[t.val] >= 0)
-          e = assume[t.val] ? kTrue : kFalse;
+        if (!subst)
+          e = g.var((int)t.val);
+        else if (subst[t.val] < 0)
+          e = subst[t.val] == -2 ? kTrue : kFalse;
         else
-          e = g.var(renum ? renum[t.val] : (int)t.val);
+          e = g.var(subst[t.val]);
         return true;
       case Tok::NAME: {
         auto it = names.find(t.name);
@@ -702,8 +704,7 @@ struct CompileJob {
   const char *src;
   int n;        // variables of the text
   int n_free;   // variables of the program
-  const int8_t *assume = nullptr;
-  const int32_t *renum = nullptr;
+  const int32_t *subst = nullptr;
   Compiled *out;
   std::string msg;
   int64_t off = -1;
@@ -714,8 +715,7 @@ void *compile_thread(void *arg) {
   CompileJob *job = (CompileJob *)arg;
   Graph g;
   Parser ps(job->src, job->n, g);
-  ps.assume = job->assume;
-  ps.renum = job->renum;
+  ps.subst = job->subst;
   Edge root;
   if (!ps.program(root)) {
     job->status = ps.status;
@@ -747,21 +747,13 @@ void *compile_thread(void *arg) {
 }  // namespace
 
 int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset,
-                    const int8_t *assume) {
+                    const int32_t *subst, int n_free) {
   CompileJob job;
   job.src = src;
   job.n = n;
-  job.n_free = n;
+  job.n_free = subst ? n_free : n;
   job.out = &out;
-  std::vector<int32_t> renum;
-  if (assume) {
-    renum.resize((size_t)n);
-    int f = 0;
-    for (int k = 0; k < n; k++) renum[(size_t)k] = assume[k] < 0 ? f++ : -1;
-    job.n_free = f;
-    job.assume = assume;
-    job.renum = renum.data();
-  }
+  job.subst = subst;
   // Deeply nested text recurses in the parser and code generator; give the
   // work a large stack of its own.
   pthread_attr_t attr;

@@ -46,10 +46,10 @@ struct Compiled {
 };
 
 // Parse and compile.  Returns 0, or an fbg_status with msg / offset set.
-// assume (n entries or null): 0/1 kills the variable, -1 keeps it free; free
-// variables are renumbered in increasing order and out.n is their number.
+// subst (n entries or null): -1 / -2 replace the variable by 0 / 1, j >= 0 by
+// the program's variable j < n_free; out.n is n_free (n without subst).
 int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset,
-                    const int8_t *assume = nullptr);
+                    const int32_t *subst = nullptr, int n_free = 0);
 
 // Encode for words-per-lane 2^log2w (W <= 16).  Appends FBG_INS_WORDS words
 // per instruction, then the pattern table; returns the instruction count.

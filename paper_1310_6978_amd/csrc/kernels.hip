@@ -404,8 +404,17 @@ __device__ __forceinline__ void store_tile(const uint32_t (&acc)[1 << LOG2W], ui
   }
 }
 
+// Waves per SIMD each evaluator instance is compiled for (its VGPR budget),
+// as many as fit without spilling: the plain clause loop fits 8 (<= 64
+// VGPRs); the uniform-cofactor loop 6 at W = 16 and 4 at W = 32; the general
+// interpreter 6 at W <= 8 and is left unconstrained above.
+constexpr int min_waves(int log2w, int var) {
+  return (var & 1) ? (log2w <= 3 ? 6 : (log2w == 4 ? 2 : 1))
+                   : ((var & 2) ? (log2w == 5 ? 4 : (log2w == 4 ? 6 : 8)) : 8);
+}
+
 template <int LOG2W, int MODE, int VAR>
-__global__ __launch_bounds__(256) void k_eval(EvalArgs a) {
+__global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a) {
   constexpr int W = 1 << LOG2W;
   extern __shared__ uint32_t lds[];
   const uint32_t lane = threadIdx.x & 63u;
@@ -483,7 +492,7 @@ __global__ __launch_bounds__(256) void k_dnf_scan(EvalArgs a) {
 // tables are read-only during the launch: scalar loads, so tile indices and
 // code pointers stay wave-uniform.
 template <int LOG2W, int VAR, int MODE>
-__global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
+__global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs a) {
   constexpr int W = 1 << LOG2W;
   extern __shared__ uint32_t lds[];
   const uint32_t lane = threadIdx.x & 63u;

@@ -69,6 +69,8 @@ def _load():
     sigs = {
         "fbg_compile": (i32, [ctypes.c_char_p, i32, u32, ctypes.POINTER(vp)]),
         "fbg_compile_assume": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_int8), u32, ctypes.POINTER(vp)]),
+        "fbg_compile_subst": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_int32), i32, u32,
+                                    ctypes.POINTER(vp)]),
         "fbg_program_free": (None, [vp]),
         "fbg_program_get_info": (i32, [vp, ctypes.POINTER(ProgramInfo)]),
         "fbg_program_set_tuning": (i32, [vp, ctypes.POINTER(Tune)]),
@@ -105,7 +107,7 @@ def _load():
 lib = _load()
 
 # every symbol include/fbg.h declares
-EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_program_free", "fbg_program_get_info", "fbg_program_set_tuning",
+EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_compile_subst", "fbg_program_free", "fbg_program_get_info", "fbg_program_set_tuning",
             "fbg_eval_dnf", "fbg_eval_dnf_tuned",
             "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_dnf", "fbg_batch_create",
             "fbg_batch_count", "fbg_batch_count_graph", "fbg_batch_set_dnf_outputs", "fbg_batch_eval_dnf",
@@ -153,11 +155,17 @@ def dnf_words(n):
 class Program:
     """A compiled formula, resident on the device it was compiled on."""
 
-    def __init__(self, src, n, flags=0, assume=None):
+    def __init__(self, src, n, flags=0, assume=None, subst=None, n_free=0):
         h = ctypes.c_void_p()
         if isinstance(src, str):
             src = src.encode()
-        if assume is None:
+        if subst is not None:
+            a = np.ascontiguousarray(subst, dtype=np.int32)
+            if a.shape != (int(n),):
+                raise ValueError("subst needs %d entries, got shape %s" % (int(n), a.shape))
+            _check(lib.fbg_compile_subst(src, int(n), a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         int(n_free), int(flags), ctypes.byref(h)))
+        elif assume is None:
             _check(lib.fbg_compile(src, int(n), int(flags), ctypes.byref(h)))
         else:
             a = np.ascontiguousarray(assume, dtype=np.int8)
@@ -221,6 +229,12 @@ def compile_assume(src, n, assume, flags=0):
     """fbg_compile_assume: assume[k] in {-1, 0, 1} (-1 free); the program's
     variables are the free ones, renumbered in increasing order."""
     return Program(src, n, flags, assume=assume)
+
+
+def compile_subst(src, n, subst, n_free, flags=0):
+    """fbg_compile_subst: subst[k] = -1 / -2 (constant 0 / 1) or the
+    program variable j < n_free that xk becomes."""
+    return Program(src, n, flags, subst=subst, n_free=n_free)
 
 
 def eval_dnf(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0, cofactor=False):

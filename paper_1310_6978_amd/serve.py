@@ -99,7 +99,7 @@ class ServeLoop:
     slice (a clause applied to one 32-bit word is one unit)."""
 
     def __init__(self, words_per_lane=16, slice_words=4e10, arena_bytes=4 << 30, max_active=256,
-                 max_items=4096, nstreams=2, cache_capacity=64):
+                 max_items=16384, nstreams=2, cache_capacity=64):
         import torch
         self.torch = torch
         self.W = int(words_per_lane)
@@ -130,6 +130,7 @@ class ServeLoop:
         peak = 0                          # most requests admitted at once
         t0 = time.perf_counter()
         k = 0
+        last_log = 0.0
 
         def now():
             return time.perf_counter() - t0
@@ -160,6 +161,9 @@ class ServeLoop:
                 share = self.slice_words / len(active)
                 words_per_tile = 64 * self.W
                 still = []
+                # each request's share is cut into several work items so that
+                # a slice keeps many waves busy, not one wave per request
+                per_req = max(1, self.max_items // len(active))
                 for r in active:
                     if len(items) >= self.max_items or len(progs) >= self.max_active:
                         still.append(r)
@@ -169,7 +173,10 @@ class ServeLoop:
                     if id(r.prog) not in local:
                         local[id(r.prog)] = len(progs)
                         progs.append(r.prog)
-                    items.append((local[id(r.prog)], r.slot, r.next_tile, t1))
+                    room = max(1, min(per_req, self.max_items - len(items)))
+                    step = max(1, -(-(t1 - r.next_tile) // room))
+                    for a in range(r.next_tile, t1, step):
+                        items.append((local[id(r.prog)], r.slot, a, min(t1, a + step)))
                     r.next_tile = t1
                     (issued if t1 >= r.ntiles else still).append(r)
                     r.deps.append(k)
@@ -204,6 +211,10 @@ class ServeLoop:
                     r.prog = None
                     done.append(r)
                 issued = [r for r in issued if r.count is None]
+            if log is not None and now() - last_log >= 10.0:
+                last_log = now()
+                log("serve: %.1f s, %d of %d requests done, %d slices, %d waiting, %d active"
+                    % (last_log, len(done), len(reqs), k, len(waiting), len(active) + len(issued)))
             if not launched and not ready:
                 if inflight and (not pending or pending[0].arrival > now()):
                     inflight[0][2].synchronize()
