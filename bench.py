@@ -8,11 +8,13 @@ space each.  One step is the whole hot path over that batch, with the
 programs resident on the device:
 
   * compile       residency lookup of the 16 compiled programs
-  * count         one persistent batched launch over all 16 programs
-                  (generator synthesis, evaluation, popcount reduction)
-  * DNF           the 2^32-bit DNF vector of every instance (512 MiB each)
-  * enumerate     ascending model indices of every instance, read off its
-                  stored DNF vector
+  * evaluate      one persistent batched launch over all 16 programs:
+                  generator synthesis, evaluation, the 2^32-bit DNF vector of
+                  every instance (512 MiB each), its model count and the
+                  model count of every tile
+  * enumerate     one batched enumeration: a scan over the tile counts of all
+                  instances and one compaction launch that reads the DNF
+                  vectors only in tiles holding models
 
 value = 16 * 2^32 valuations per step / step time.  The JSON line also
 carries the roofline of the dominant kernel (the evaluator: integer VALU
@@ -28,7 +30,7 @@ Workload posets: labeled partial orders through the c-partition counting
 procedure (bounded posets on --posets-n elements).
 Workload theories: one count of each propositional theory of the paper's
 examples, at every tiling, with and without the uniform-cofactor variant.
-Workload unlabeled: non-isomorphic partial orders (7 elements) and graphs (9
+Workload unlabeled: non-isomorphic partial orders (7 elements) and graphs (7
 vertices) by the Frobenius-Burnside lemma.
 Workload copy: a 1 GiB device copy, the calibration kernel for the HBM byte
 counters.
@@ -103,13 +105,14 @@ def cpu_baseline(text, n, target_s=15.0):
                       % (size2, dt, c)}
 
 
-def golden_counts():
+def golden_c1():
+    """Oracle counts and model lists of the 16 instances (tests/golden)."""
     path = os.path.join(ROOT, "tests", "golden", "c1_3cnf_n32.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         g = json.load(f)
-    return {int(s): r["count"] for s, r in g["seeds"].items()}
+    return {int(s): r for s, r in g["seeds"].items()}
 
 
 def bench_c1(args, torch, fbg):
@@ -127,7 +130,7 @@ def bench_c1(args, torch, fbg):
     batch.set_dnf_outputs(dnfs)
     cap = 4096
     idx = [torch.empty(cap, dtype=torch.int64, device="cuda") for _ in progs]
-    tots = [torch.empty(1, dtype=torch.int64, device="cuda") for _ in progs]
+    batch.set_enum_outputs(idx)
     stream = torch.cuda.current_stream()
     ev = []
 
@@ -142,8 +145,7 @@ def bench_c1(args, torch, fbg):
         if record:
             b.record(stream)
             ev.append((a, b))
-        for d, ii, tt in zip(dnfs, idx, tots):
-            fbg.enumerate_dnf(d, n, cap, out=ii, total=tt, stream=stream)  # models, from the DNF
+        batch.enumerate(stream=stream)                               # models of all, from the DNF vectors
 
     for _ in range(args.warmup):
         step(False)
@@ -156,11 +158,12 @@ def bench_c1(args, torch, fbg):
     ms_step = (t1 - t0) * 1e3 / args.steps
 
     got = counts.cpu().numpy().view("uint64").tolist()
-    totals = [int(t.cpu().numpy().view("uint64")[0]) for t in tots]
-    gold = golden_counts()
+    lists = [ii.cpu().numpy().view("uint64")[:min(c, cap)].tolist() for ii, c in zip(idx, got)]
+    gold = golden_c1()
     exact = None
     if gold is not None and all(s in gold for s in seeds):
-        exact = all(got[i] == gold[s] == totals[i] for i, s in enumerate(seeds))
+        exact = all(got[i] == gold[s]["count"] and lists[i] == gold[s]["models"][:cap]
+                    for i, s in enumerate(seeds))
     k_ms = sum(ev_ms(a, b) for a, b in ev) / len(ev)
 
     # counting alone: one batched launch vs 16 plain launches, and the
@@ -202,8 +205,9 @@ def bench_c1(args, torch, fbg):
         "ms_per_step": ms_step,
         "dtype": "u32",
         "config": {"workload": "random 3-CNF model counting, n=32, m=136 (ratio 4.25), seeds 0-15; per step: "
-                               "one batched launch writing the 2^32-bit DNF vector and the count of every "
-                               "instance, then every instance's models enumerated from its DNF vector",
+                               "one batched launch writing the 2^32-bit DNF vector, the count and the per-tile "
+                               "model counts of every instance, then one batched enumeration of all "
+                               "models from the DNF vectors",
                    "n": n, "clauses": 136, "instances": len(progs),
                    "words_per_lane": progs[0].info["words_per_lane"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_BITWISE_PEAK / 1e12,
@@ -419,7 +423,7 @@ def bench_unlabeled(args, torch, fbg):
     graphs = ("S = range({n})\nS2 = perm(S, 2)\nsym = A[i,j:S2] (~e(i,j) | e(j,i))\n"
               "assumptions = {{e(i,i): 0 for i in S}}\n")
     rows, total_ms = [], 0.0
-    for name, script, n in (("partial orders", posets, 7), ("graphs", graphs, 9)):
+    for name, script, n in (("partial orders", posets, 7), ("graphs", graphs, 7)):
         tr = frontend.translate(script.format(n=n))
         t0 = time.perf_counter()
         res = unlabeled.count_translation(tr, range(n), cofactor=True)
@@ -436,7 +440,7 @@ def bench_unlabeled(args, torch, fbg):
                      "first_ms": first})
     return {"metric": "non-isomorphic models counted per second (Frobenius-Burnside, one batched count)",
             "value": len(rows) / (total_ms / 1e3), "unit": "theories/s", "ms_per_step": total_ms, "dtype": "u32",
-            "config": {"workload": "unlabeled partial orders on 7 elements and graphs on 9 vertices"},
+            "config": {"workload": "unlabeled partial orders on 7 elements and graphs on 7 vertices"},
             "runs": rows}
 
 

@@ -247,6 +247,27 @@ fbg_status fbg_batch_count_graph(fbg_batch *b, uint64_t *d_counts, void *stream)
  */
 fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, const uint64_t *out_words);
 fbg_status fbg_batch_eval_dnf(fbg_batch *b, uint64_t *d_counts, void *stream);
+
+/*
+ * fbg_batch_set_enum_outputs -- where fbg_batch_enumerate writes the models
+ * of every program (Section 3.2: the models are the set bits of the DNF
+ * vector, read here in ascending order).  Call after
+ * fbg_batch_set_dnf_outputs; from then on fbg_batch_eval_dnf also records
+ * the number of models of every tile.
+ *   d_idx     host array of np device pointers (caller-owned), program i
+ *             receives at most capacity[i] uint64 indices; NULL allowed
+ *             when capacity[i] = 0.
+ *   capacity  host array of np capacities.
+ * Synchronous (allocates the tile-count and offset buffers once and uploads
+ * a table); must not run while a launch of this batch is pending.
+ * fbg_batch_enumerate -- after fbg_batch_eval_dnf on the same stream: the
+ *   first min(count_i, capacity_i) models of every program i, ascending,
+ *   into d_idx[i] (count_i is d_counts[i] of that call).  One scan over the
+ *   tile counts of all programs, then one compaction launch per plan that
+ *   reads only the tiles holding models.  Allocates nothing.
+ */
+fbg_status fbg_batch_set_enum_outputs(fbg_batch *b, uint64_t *const *d_idx, const uint64_t *capacity);
+fbg_status fbg_batch_enumerate(fbg_batch *b, void *stream);
 fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d_counts, const fbg_tune *tune,
                            void *stream);
 
@@ -279,6 +300,8 @@ fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_
  *   FBG_TUNE_COFACTOR.
  * fbg_server_launch -- upload the program table and the items (asynchronous,
  *   from pinned memory) and launch one persistent batched kernel on `stream`.
+ *   Long items are cut into pieces (at most max_items pieces in all) so that
+ *   a few large requests still occupy every compute unit.
  *   Items are validated on the host (FBG_E_INVAL on a bad index or range).
  *   A staging buffer is reused only after its previous launch has finished.
  *   Not thread-safe: one server object per host thread.

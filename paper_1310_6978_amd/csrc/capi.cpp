@@ -170,6 +170,15 @@ struct fbg_batch {
   fbg::BatchProg *d_progs = nullptr;
   fbg::BatchProg *d_progs_dnf = nullptr;  // with DNF outputs (fbg_batch_set_dnf_outputs)
   std::vector<fbg::BatchProg> host_progs;
+  std::vector<fbg::BatchProg> host_dnf;   // host copy of d_progs_dnf
+  // batched enumeration (fbg_batch_set_enum_outputs): per-tile counts written
+  // by fbg_batch_eval_dnf, their scan, and the per-program output table
+  std::vector<int> plan_of;               // plan index of every program
+  uint64_t total_tiles = 0;
+  uint32_t *d_tile_counts = nullptr;
+  uint64_t *d_offsets = nullptr;
+  uint64_t *d_scan_blk = nullptr;
+  fbg::EnumProg *d_enum = nullptr;
   uint32_t *d_head = nullptr;             // one queue head per plan
   // captured graph of (zero fill, persistent kernels) for one counts pointer
   hipGraph_t graph = nullptr;
@@ -585,11 +594,18 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   b->device = dev;
   b->np = np;
   b->host_progs.resize((size_t)np);
+  b->plan_of.assign((size_t)np, 0);
   std::vector<std::vector<fbg::BatchItem>> plan_items;
-  for (int group = 0; group < 2; group++) {  // 0: clause-only programs, 1: general programs
+  // 0: clause-only programs; 1: general programs whose registers all fit in
+  // VGPRs; 2: general programs with LDS registers (their LDS per wave would
+  // otherwise limit the occupancy of every program in the plan)
+  auto group_of = [](const fbg_program *q) {
+    return !q->general() ? 0 : (lds_regs((uint32_t)q->c.nregs) == 0 ? 1 : 2);
+  };
+  for (int group = 0; group < 3; group++) {
     std::vector<int32_t> members;
     for (int32_t i = 0; i < np; i++)
-      if (ps[i]->general() == (group == 1)) members.push_back(i);
+      if (group_of(ps[i]) == group) members.push_back(i);
     if (members.empty()) continue;
     // words per lane: the tuning, else the choice for the largest program
     int l = fixed_l;
@@ -611,6 +627,9 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       var |= ps[i]->variant(tune);
     }
     while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
+    // LDS registers: keep a block of 4 waves within 32 KiB (5 blocks per CU)
+    if (fixed_l < 0)
+      while (l > 0 && lds_per_wave(max_regs, l) * kWavesPerBlock > kMaxLdsPerBlock / 2) l--;
     int wpb;
     size_t lds;
     if ((st = block_shape(max_regs, l, wpb, lds))) {
@@ -622,6 +641,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       fbg::BatchProg &q = b->host_progs[(size_t)i];
       q = batch_prog(ps[i], l);
       total_cost += (double)q.ntiles * (q.nins + 4);
+      b->plan_of[(size_t)i] = (int)b->plans.size();
     }
     // about four items per wave; never split below one tile
     const double target = std::max(1.0, total_cost / (double)(waves * 4));
@@ -740,11 +760,81 @@ fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, cons
                   (unsigned long long)need);
     q.out32 = (uint32_t *)d_outs[i];
     q.out_slices = 2 * need;
+    if (!b->host_dnf.empty()) q.tile_counts = b->host_dnf[(size_t)i].tile_counts;
   }
   hipError_t e = hipSuccess;
   if (!b->d_progs_dnf) e = hipMalloc((void **)&b->d_progs_dnf, t.size() * sizeof(fbg::BatchProg));
   if (e == hipSuccess) e = hipMemcpy(b->d_progs_dnf, t.data(), t.size() * sizeof(fbg::BatchProg), hipMemcpyHostToDevice);
-  return e == hipSuccess ? FBG_OK : hip_fail(e, "upload of the DNF output table");
+  if (e != hipSuccess) return hip_fail(e, "upload of the DNF output table");
+  b->host_dnf = t;
+  return FBG_OK;
+}
+
+fbg_status fbg_batch_set_enum_outputs(fbg_batch *b, uint64_t *const *d_idx, const uint64_t *capacity) {
+  if (!b) return fail(FBG_E_INVAL, "batch is NULL");
+  if (!d_idx || !capacity) return fail(FBG_E_INVAL, "NULL argument");
+  if (b->host_dnf.empty()) return fail(FBG_E_INVAL, "set the DNF outputs first (fbg_batch_set_dnf_outputs)");
+  fbg_status st = check_device(b->device);
+  if (st) return st;
+  for (int32_t i = 0; i < b->np; i++)
+    if (capacity[i] > 0 && !d_idx[i]) return fail(FBG_E_INVAL, "d_idx[%d] is NULL with capacity %llu", i,
+                                                  (unsigned long long)capacity[i]);
+  hipError_t e = hipSuccess;
+  if (!b->d_tile_counts) {
+    uint64_t total = 0;
+    for (const auto &q : b->host_progs) total += q.ntiles;
+    b->total_tiles = total;
+    const uint64_t nb = fbg::scan_block_count(total);
+    e = hipMalloc((void **)&b->d_tile_counts, std::max<uint64_t>(total, 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_offsets, std::max<uint64_t>(total, 1) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_scan_blk, (nb + 2) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_enum, (size_t)b->np * sizeof(fbg::EnumProg));
+    if (e != hipSuccess) return fail(FBG_E_NOMEM, "enumeration buffers: %s", hipGetErrorString(e));
+  }
+  std::vector<fbg::EnumProg> ep((size_t)b->np);
+  uint64_t tile0 = 0;
+  for (int32_t i = 0; i < b->np; i++) {
+    fbg::BatchProg &q = b->host_dnf[(size_t)i];
+    q.tile_counts = b->d_tile_counts + tile0;
+    fbg::EnumProg &x = ep[(size_t)i];
+    memset(&x, 0, sizeof x);
+    x.dnf = q.out32;
+    x.nslices = q.nslices;
+    x.tile0 = tile0;
+    x.out = d_idx[i];
+    x.capacity = capacity[i];
+    x.log2w = (uint32_t)b->plans[(size_t)b->plan_of[(size_t)i]].log2w;
+    tile0 += q.ntiles;
+  }
+  e = hipMemcpy(b->d_enum, ep.data(), ep.size() * sizeof(fbg::EnumProg), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_progs_dnf, b->host_dnf.data(), b->host_dnf.size() * sizeof(fbg::BatchProg),
+                  hipMemcpyHostToDevice);
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "upload of the enumeration tables");
+}
+
+fbg_status fbg_batch_enumerate(fbg_batch *b, void *stream) {
+  if (!b) return fail(FBG_E_INVAL, "batch is NULL");
+  if (!b->d_enum) return fail(FBG_E_INVAL, "no enumeration outputs set (fbg_batch_set_enum_outputs)");
+  fbg_status st = check_device(b->device);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t nb = fbg::scan_block_count(b->total_tiles);
+  hipError_t e = fbg::launch_scan(b->d_tile_counts, b->total_tiles, b->d_offsets, b->d_scan_blk,
+                                  b->d_scan_blk + nb + 1, s);
+  if (e != hipSuccess) return hip_fail(e, "launch of the tile-count scan");
+  fbg::BatchEnumArgs a;
+  a.progs = b->d_enum;
+  a.np = (uint32_t)b->np;
+  a.total_tiles = b->total_tiles;
+  a.tile_counts = b->d_tile_counts;
+  a.offsets = b->d_offsets;
+  const int grid = cu_count(b->device) * 8;
+  for (const auto &pl : b->plans) {
+    e = fbg::launch_batch_compact(pl.log2w, a, grid, 256, s);
+    if (e != hipSuccess) return hip_fail(e, "launch of the compaction kernel");
+  }
+  return FBG_OK;
 }
 
 fbg_status fbg_batch_eval_dnf(fbg_batch *b, uint64_t *d_counts, void *stream) {
@@ -793,6 +883,10 @@ void fbg_batch_free(fbg_batch *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_progs) (void)hipFree(b->d_progs);
   if (b->d_progs_dnf) (void)hipFree(b->d_progs_dnf);
+  if (b->d_tile_counts) (void)hipFree(b->d_tile_counts);
+  if (b->d_offsets) (void)hipFree(b->d_offsets);
+  if (b->d_scan_blk) (void)hipFree(b->d_scan_blk);
+  if (b->d_enum) (void)hipFree(b->d_enum);
   for (auto &pl : b->plans)
     if (pl.d_items) (void)hipFree(pl.d_items);
   if (b->d_head) (void)hipFree(b->d_head);
@@ -878,6 +972,8 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   int wpb;
   size_t lds;
   if ((st = block_shape(max_regs, l, wpb, lds))) return st;
+  const int cus = cu_count(sv->device);
+  const int occ = fbg::batch_blocks_per_cu(fbg::EVAL_COUNT, l, var, 64 * wpb, lds);
   fbg_server::Slot &sl = sv->slots[(size_t)sv->next];
   sv->next = (sv->next + 1) % sv->nbuf;
   hipError_t e;
@@ -885,29 +981,40 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   fbg::BatchProg *hp = (fbg::BatchProg *)sl.h;
   fbg::BatchItem *hi = (fbg::BatchItem *)(sl.h + (size_t)sv->max_programs * sizeof(fbg::BatchProg));
   for (int32_t i = 0; i < np; i++) hp[i] = batch_prog(ps[i], l);
+  // Cut the items into pieces of at most `piece` tiles so that every resident
+  // wave gets about four, within the staging capacity: the pieces number at
+  // most (total tiles / piece) + nitems <= max_items.
+  uint64_t total = 0;
+  for (int32_t k = 0; k < nitems; k++) total += items[k].tile_end - items[k].tile_begin;
+  const uint64_t room = (uint64_t)(sv->max_items - nitems);
+  const uint64_t want = std::min<uint64_t>(room, (uint64_t)cus * occ * wpb * 4);
+  const uint64_t piece = want > 0 ? std::max<uint64_t>(1, (total + want - 1) / want) : ~0ull;
+  int32_t npieces = 0;
   for (int32_t k = 0; k < nitems; k++) {
-    hi[k].prog = (uint32_t)items[k].prog;
-    hi[k].slot = (uint32_t)items[k].slot;
-    hi[k].t0 = items[k].tile_begin;
-    hi[k].t1 = items[k].tile_end;
+    for (uint64_t t = items[k].tile_begin; t < items[k].tile_end; t += std::min(piece, items[k].tile_end - t)) {
+      fbg::BatchItem &q = hi[npieces++];
+      q.prog = (uint32_t)items[k].prog;
+      q.slot = (uint32_t)items[k].slot;
+      q.t0 = t;
+      q.t1 = t + std::min(piece, items[k].tile_end - t);
+    }
   }
   hipStream_t s = (hipStream_t)stream;
   char *dp = sl.d;
   char *di = sl.d + (size_t)sv->max_programs * sizeof(fbg::BatchProg);
   e = hipMemcpyAsync(dp, hp, (size_t)np * sizeof(fbg::BatchProg), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(di, hi, (size_t)nitems * sizeof(fbg::BatchItem), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && npieces > 0)
+    e = hipMemcpyAsync(di, hi, (size_t)npieces * sizeof(fbg::BatchItem), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = fbg::launch_zero(nullptr, 0, sl.d_head, s);
   if (e != hipSuccess) return hip_fail(e, "server upload");
   fbg::BatchArgs a;
   a.progs = (const fbg::BatchProg *)dp;
   a.items = (const fbg::BatchItem *)di;
-  a.nitems = (uint32_t)nitems;
+  a.nitems = (uint32_t)npieces;
   a.max_regs = lds_regs(max_regs);
   a.head = sl.d_head;
   a.counts = d_counts;
-  const int cus = cu_count(sv->device);
-  const int occ = fbg::batch_blocks_per_cu(fbg::EVAL_COUNT, l, var, 64 * wpb, lds);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nitems + wpb - 1) / wpb, (int64_t)cus * occ));
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((npieces + wpb - 1) / wpb, (int64_t)cus * occ));
   e = fbg::launch_batch(fbg::EVAL_COUNT, l, var, a, grid, 64 * wpb, lds, s);
   if (e == hipSuccess) e = hipEventRecord(sl.done, s);
   sl.used = true;

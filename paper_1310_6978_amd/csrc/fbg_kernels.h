@@ -37,6 +37,26 @@ struct BatchProg {
   uint64_t ntiles;
   uint32_t *out32;      // MODE_DNF: the program's DNF vector
   uint64_t out_slices;  // MODE_DNF: 32-bit words of out32
+  uint32_t *tile_counts;  // MODE_DNF: per-tile model counts (or null)
+};
+
+// One program of a batched enumeration over stored DNF vectors.
+struct EnumProg {
+  const uint32_t *dnf;  // the DNF vector as 32-bit words
+  uint64_t nslices;     // valid 32-bit words
+  uint64_t tile0;       // first global tile of the program
+  uint64_t *out;        // model indices (capacity entries)
+  uint64_t capacity;
+  uint32_t log2w;       // tiling of the program's plan
+  uint32_t pad;
+};
+
+struct BatchEnumArgs {
+  const EnumProg *progs;
+  uint32_t np;
+  uint64_t total_tiles;
+  const uint32_t *tile_counts;  // all programs, concatenated
+  const uint64_t *offsets;      // exclusive scan of tile_counts
 };
 
 struct BatchItem {
@@ -64,6 +84,7 @@ hipError_t launch_batch(int mode, int log2w, int var, const BatchArgs &a, int gr
 // Resident blocks per compute unit of an evaluator or batch launch.
 int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);
 int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);
+hipError_t launch_batch_compact(int log2w, const BatchEnumArgs &a, int grid, int block, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
                        hipStream_t s);
 uint64_t scan_block_count(uint64_t n);

@@ -520,9 +520,57 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
 #pragma unroll
       for (int i = 0; i < W; i++) c += __popc(acc[i]);
       total += c;
+      if (MODE == MODE_DNF && p->tile_counts) {  // for a later batched enumeration
+        const uint32_t tc = wave_sum_u32(c);
+        if (lane == 0) p->tile_counts[t] = tc;
+      }
     }
     const uint64_t s = wave_sum_u64(total);
     if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + slot), (unsigned long long)s);
+  }
+}
+
+// Batched enumeration from the stored DNF vectors: every wave strides over
+// the global tile list of all programs (tile counts and their exclusive scan
+// concatenated in program order), skips programs of the other plan and tiles
+// without models, and compacts the models of a tile into its program's list.
+template <int LOG2W>
+__global__ __launch_bounds__(256) void k_batch_compact(BatchEnumArgs a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = uni(threadIdx.x) >> 6;
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  typedef const __attribute__((address_space(4))) EnumProg *enum_ptr;
+  // 64 tile counts per wave and step, one per lane; the wave then visits
+  // the tiles with models one by one
+  for (uint64_t base = wave * 64; base < a.total_tiles; base += nwaves * 64) {
+    const uint64_t mine = base + lane;
+    const bool has = mine < a.total_tiles && a.tile_counts[mine] != 0u;
+    uint64_t todo = __ballot(has);
+    while (todo) {
+    const uint64_t g = base + (uint64_t)__builtin_ctzll(todo);
+    todo &= todo - 1;
+    // the program owning global tile g: tile0 ascends with the program index
+    uint32_t lo = 0, hi = a.np;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (((enum_ptr)a.progs)[mid].tile0 <= g) lo = mid; else hi = mid;
+    }
+    const enum_ptr p = (enum_ptr)a.progs + lo;
+    if (p->log2w != (uint32_t)LOG2W || p->capacity == 0) continue;
+    const uint64_t t = g - p->tile0;
+    const uint64_t U0 = t << LOG2W;
+    constexpr int W = 1 << LOG2W;
+    uint32_t acc[W];
+    const uint32_t *src = p->dnf + U0 * 64 + lane;
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+      const uint64_t sidx = (U0 + i) * 64 + lane;
+      acc[i] = sidx < p->nslices ? src[i * 64] : 0u;
+    }
+    const uint64_t first = a.offsets[g] - a.offsets[p->tile0];
+    tile_compact<LOG2W>(acc, U0, lane, first, p->out, p->capacity);
+    }
   }
 }
 
@@ -758,6 +806,19 @@ int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
 int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
   if (mode == dev::MODE_DNF) return batch_occ_mode<dev::MODE_DNF>(log2w, var, block, lds);
   return batch_occ_mode<dev::MODE_COUNT>(log2w, var, block, lds);
+}
+
+hipError_t launch_batch_compact(int log2w, const BatchEnumArgs &a, int grid, int block, hipStream_t s) {
+  switch (log2w) {
+    case 0: hipLaunchKernelGGL((dev::k_batch_compact<0>), dim3(grid), dim3(block), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((dev::k_batch_compact<1>), dim3(grid), dim3(block), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((dev::k_batch_compact<2>), dim3(grid), dim3(block), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((dev::k_batch_compact<3>), dim3(grid), dim3(block), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((dev::k_batch_compact<4>), dim3(grid), dim3(block), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((dev::k_batch_compact<5>), dim3(grid), dim3(block), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,

@@ -84,6 +84,8 @@ def _load():
         "fbg_batch_count_graph": (i32, [vp, vp, vp]),
         "fbg_batch_set_dnf_outputs": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)]),
         "fbg_batch_eval_dnf": (i32, [vp, vp, vp]),
+        "fbg_batch_set_enum_outputs": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64)]),
+        "fbg_batch_enumerate": (i32, [vp, vp]),
         "fbg_batch_free": (None, [vp]),
         "fbg_count_batch": (i32, [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(Tune), vp]),
         "fbg_enumerate_dnf": (i32, [vp, i32, vp, u64, vp, vp]),
@@ -111,6 +113,7 @@ EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_compile_subst", "fbg_progr
             "fbg_eval_dnf", "fbg_eval_dnf_tuned",
             "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_dnf", "fbg_batch_create",
             "fbg_batch_count", "fbg_batch_count_graph", "fbg_batch_set_dnf_outputs", "fbg_batch_eval_dnf",
+            "fbg_batch_set_enum_outputs", "fbg_batch_enumerate",
             "fbg_batch_free", "fbg_count_batch", "fbg_program_tiles", "fbg_server_create",
             "fbg_server_launch", "fbg_server_free", "fbg_program_emulate", "fbg_program_disasm",
             "fbg_last_error", "fbg_last_error_offset", "fbg_version")
@@ -355,6 +358,21 @@ class Batch:
         ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
         sizes = (ctypes.c_uint64 * len(outs))(*[o.numel() for o in outs])
         _check(lib.fbg_batch_set_dnf_outputs(self._h, ptrs, sizes))
+
+    def set_enum_outputs(self, outs):
+        """outs: one int64 device tensor per program (its capacity), or
+        None for capacity 0."""
+        if len(outs) != len(self._progs):
+            raise ValueError("need %d output tensors" % len(self._progs))
+        self._enum_outs = list(outs)
+        ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() if o is not None else None for o in outs])
+        caps = (ctypes.c_uint64 * len(outs))(*[o.numel() if o is not None else 0 for o in outs])
+        _check(lib.fbg_batch_set_enum_outputs(self._h, ptrs, caps))
+
+    def enumerate(self, stream=None):
+        """Models of every program into its enumeration output, ascending
+        (after eval_dnf on the same stream)."""
+        _check(lib.fbg_batch_enumerate(self._h, _stream(stream)))
 
     def eval_dnf(self, counts=None, stream=None):
         """Every program's DNF vector into its output tensor and its count

@@ -107,6 +107,7 @@ class ServeLoop:
         self.admission = Admission(arena_bytes)
         self.max_active = int(max_active)
         self.max_items = int(max_items)
+        self.max_requests_per_slice = max(1, int(max_items) // 4)
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.copy_stream = torch.cuda.Stream()
         self.server = fbg.Server(max_programs=max_active, max_items=max_items, words_per_lane=self.W,
@@ -161,11 +162,8 @@ class ServeLoop:
                 share = self.slice_words / len(active)
                 words_per_tile = 64 * self.W
                 still = []
-                # each request's share is cut into several work items so that
-                # a slice keeps many waves busy, not one wave per request
-                per_req = max(1, self.max_items // len(active))
                 for r in active:
-                    if len(items) >= self.max_items or len(progs) >= self.max_active:
+                    if len(items) >= self.max_requests_per_slice or len(progs) >= self.max_active:
                         still.append(r)
                         continue
                     chunk = max(1, int(share // (r.nins * words_per_tile)))
@@ -173,10 +171,9 @@ class ServeLoop:
                     if id(r.prog) not in local:
                         local[id(r.prog)] = len(progs)
                         progs.append(r.prog)
-                    room = max(1, min(per_req, self.max_items - len(items)))
-                    step = max(1, -(-(t1 - r.next_tile) // room))
-                    for a in range(r.next_tile, t1, step):
-                        items.append((local[id(r.prog)], r.slot, a, min(t1, a + step)))
+                    # one item per request; the server cuts long items into
+                    # pieces so that the slice occupies every compute unit
+                    items.append((local[id(r.prog)], r.slot, r.next_tile, t1))
                     r.next_tile = t1
                     (issued if t1 >= r.ntiles else still).append(r)
                     r.deps.append(k)

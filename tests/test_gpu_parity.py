@@ -397,3 +397,43 @@ def test_registers_beyond_the_vgpr_set(F, k):
         progs = [p, F.Program(*cnf)]
         want = [oracle.count(text, n), oracle.count(*cnf)]
         assert host(F.count_batch(progs)).tolist() == want
+
+
+def test_batch_enumerate_lists_every_program(F):
+    import torch
+    rng = random.Random(91)
+    texts = [("x0", 1), ("0", 9), ("x1 | ~x1", 4)]
+    texts += [workloads.random_3cnf(rng.choice([16, 19, 22]), 60, s) for s in range(5)]
+    texts += [workloads.random_dag(rng.choice([12, 17]), rng.randrange(50, 300), s) for s in range(3)]
+    texts += [workloads.triangle_free(6), workloads.baequ4()]
+    progs = [F.Program(t, n) for t, n in texts]
+    wants = [oracle.models(t, n) for t, n in texts]
+    caps = [w[1] + 2 if i % 3 == 0 else (max(0, w[1] // 2) if i % 3 == 1 else 0) for i, w in enumerate(wants)]
+    for wpl in (0, 2, 16):
+        b = F.Batch(progs, words_per_lane=wpl)
+        dnfs = [torch.empty(F.dnf_words(n), dtype=torch.int64, device="cuda") for _, n in texts]
+        b.set_dnf_outputs(dnfs)
+        outs = [torch.full((c,), -1, dtype=torch.int64, device="cuda") if c else None for c in caps]
+        b.set_enum_outputs(outs)
+        for rep in range(2):
+            counts = host(b.eval_dnf())
+            b.enumerate()
+            for (m, total), c, o, got_c in zip(wants, caps, outs, counts):
+                assert int(got_c) == total
+                if c:
+                    got = host(o)
+                    k = min(c, total)
+                    assert np.array_equal(got[:k], m[:k]), (wpl, rep)
+                    assert np.all(got[k:] == np.uint64(2**64 - 1))
+        b.free()
+
+
+def test_batch_enumerate_needs_outputs(F):
+    import torch
+    p = F.Program("x1 & x5", 9)
+    b = F.Batch([p])
+    with pytest.raises(F.FbgError):
+        b.enumerate()
+    with pytest.raises(F.FbgError):      # DNF outputs first
+        b.set_enum_outputs([torch.empty(4, dtype=torch.int64, device="cuda")])
+    b.free()
