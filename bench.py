@@ -55,9 +55,10 @@ METRIC = "valuations/sec and % VALU bitwise peak (batched vs plain, bit-exact co
 # HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
 # the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
-# half the bytes copied, WRITE_SIZE all of them).  None whenever that kernel
-# has changed since the counters were taken.
-C1_TRAFFIC = None
+# half the bytes copied, WRITE_SIZE all of them): 2 x 2611.8 KiB fetched and
+# 8395435.3 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
+# None whenever that kernel has changed since the counters were taken.
+C1_TRAFFIC = (2 * 2611.8 + 8395435.3) * 1024
 
 
 class ProgramCache:
