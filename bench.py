@@ -51,6 +51,14 @@ if ROOT not in sys.path:
 # operation per 32-bit lane per clock.
 VALU_BITWISE_PEAK = 256 * 64 * 32 * 2.4e9
 METRIC = "valuations/sec and % VALU bitwise peak (batched vs plain, bit-exact counts)"
+HBM_PEAK = 8e12  # bytes/s
+
+# The paper's own figure for this path, on its hardware (Section 2.3): a term
+# of 2^17 nodes over 30 variables in about 1 s on a PC with two GPUs of 2^11
+# 32-bit cores each (OpenCL) -- 2^30 valuations/s, 2^47 node-bit-ops/s.
+PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
+                 "hardware": "PC with 2 GPUs x 2^11 32-bit cores, OpenCL (GPUs not named)",
+                 "workload": "30 variables, 2^17-node term, about 1 s (Section 2.3)"}
 
 # HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
@@ -82,6 +90,33 @@ class ProgramCache:
 
 def ev_ms(a, b):
     return a.elapsed_time(b)
+
+
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo) and its logical CPUs."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
+def cpu_bitparallel(text, n):
+    """The oracle's blocked evaluation of Section 2.3 (64 valuations per
+    word, generator blocks from the definition of M) over the whole valuation
+    space of one instance: the paper-style CPU path, as a cross-check."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    c = oracle.bitpar_count(text, n, threads)
+    dt = time.perf_counter() - t0
+    return {"value": float(1 << n) / dt, "unit": "valuations/s", "cores": threads, "kind": "oracle-bitparallel",
+            "sample": "all 2^%d valuations of seed 0 (%.1f s, %d models)" % (n, dt, c), "count": c}
 
 
 def cpu_baseline(text, n, target_s=15.0):
@@ -220,6 +255,10 @@ def bench_c1(args, torch, fbg):
                              "batched_valuations_per_s": vals / (batch_ms / 1e3),
                              "plain_valuations_per_s": vals / (plain_ms / 1e3),
                              "speedup": plain_ms / batch_ms, "counts_equal": batch_same},
+        "dnf_write_out": {"bytes_per_launch": len(progs) * float(1 << n) / 8,
+                          "gb_per_s": len(progs) * float(1 << n) / 8 / (k_ms / 1e3) / 1e9,
+                          "frac_of_hbm_peak": len(progs) * float(1 << n) / 8 / (k_ms / 1e3) / HBM_PEAK},
+        "paper_context": PAPER_CONTEXT,
         "cofactor": {"batched_count_ms": cof_ms, "valuations_per_s": vals / (cof_ms / 1e3),
                      "speedup_vs_full_evaluation": batch_ms / cof_ms, "counts_equal": cof_same},
         "pct_valu_bitwise_peak": 100.0 * achieved / VALU_BITWISE_PEAK,
@@ -229,6 +268,9 @@ def bench_c1(args, torch, fbg):
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(texts[0][0], n)
+        res["cpu_bitparallel"] = cpu_bitparallel(texts[0][0], n)
+        res["cpu_bitparallel"]["count_equal"] = res["cpu_bitparallel"]["count"] == got[0]
+        res["host"] = host_cpu()
     return res
 
 

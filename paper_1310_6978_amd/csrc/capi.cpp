@@ -178,6 +178,7 @@ struct fbg_batch {
   uint32_t *d_tile_counts = nullptr;
   uint64_t *d_offsets = nullptr;
   uint64_t *d_scan_blk = nullptr;
+  uint32_t *d_tile_list = nullptr;        // tiles holding models, then their number
   fbg::EnumProg *d_enum = nullptr;
   uint32_t *d_head = nullptr;             // one queue head per plan
   // captured graph of (zero fill, persistent kernels) for one counts pointer
@@ -783,12 +784,15 @@ fbg_status fbg_batch_set_enum_outputs(fbg_batch *b, uint64_t *const *d_idx, cons
   if (!b->d_tile_counts) {
     uint64_t total = 0;
     for (const auto &q : b->host_progs) total += q.ntiles;
+    if (total >= (1ull << 32)) return fail(FBG_E_RANGE, "%llu tiles: batched enumeration lists tiles in 32 bits",
+                                           (unsigned long long)total);
     b->total_tiles = total;
     const uint64_t nb = fbg::scan_block_count(total);
     e = hipMalloc((void **)&b->d_tile_counts, std::max<uint64_t>(total, 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_offsets, std::max<uint64_t>(total, 1) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_scan_blk, (nb + 2) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_enum, (size_t)b->np * sizeof(fbg::EnumProg));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tile_list, (std::max<uint64_t>(total, 1) + 64) * sizeof(uint32_t));
     if (e != hipSuccess) return fail(FBG_E_NOMEM, "enumeration buffers: %s", hipGetErrorString(e));
   }
   std::vector<fbg::EnumProg> ep((size_t)b->np);
@@ -829,7 +833,12 @@ fbg_status fbg_batch_enumerate(fbg_batch *b, void *stream) {
   a.total_tiles = b->total_tiles;
   a.tile_counts = b->d_tile_counts;
   a.offsets = b->d_offsets;
+  a.list = b->d_tile_list;
+  a.nlist = b->d_tile_list + std::max<uint64_t>(b->total_tiles, 1);
   const int grid = cu_count(b->device) * 8;
+  e = fbg::launch_zero(nullptr, 0, a.nlist, s);
+  if (e == hipSuccess) e = fbg::launch_list_tiles(a, grid, s);
+  if (e != hipSuccess) return hip_fail(e, "launch of the tile listing");
   for (const auto &pl : b->plans) {
     e = fbg::launch_batch_compact(pl.log2w, a, grid, 256, s);
     if (e != hipSuccess) return hip_fail(e, "launch of the compaction kernel");
@@ -887,6 +896,7 @@ void fbg_batch_free(fbg_batch *b) {
   if (b->d_offsets) (void)hipFree(b->d_offsets);
   if (b->d_scan_blk) (void)hipFree(b->d_scan_blk);
   if (b->d_enum) (void)hipFree(b->d_enum);
+  if (b->d_tile_list) (void)hipFree(b->d_tile_list);
   for (auto &pl : b->plans)
     if (pl.d_items) (void)hipFree(pl.d_items);
   if (b->d_head) (void)hipFree(b->d_head);

@@ -57,6 +57,8 @@ struct BatchEnumArgs {
   uint64_t total_tiles;
   const uint32_t *tile_counts;  // all programs, concatenated
   const uint64_t *offsets;      // exclusive scan of tile_counts
+  uint32_t *list;               // tiles holding models (k_list_tiles)
+  uint32_t *nlist;              // their number (zeroed before k_list_tiles)
 };
 
 struct BatchItem {
@@ -84,6 +86,7 @@ hipError_t launch_batch(int mode, int log2w, int var, const BatchArgs &a, int gr
 // Resident blocks per compute unit of an evaluator or batch launch.
 int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);
 int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);
+hipError_t launch_list_tiles(const BatchEnumArgs &a, int grid, hipStream_t s);
 hipError_t launch_batch_compact(int log2w, const BatchEnumArgs &a, int grid, int block, hipStream_t s);
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
                        hipStream_t s);

@@ -372,6 +372,7 @@ __device__ __forceinline__ void tile_compact(const uint32_t (&acc)[1 << LOG2W], 
 #pragma unroll
   for (int i = 0; i < (1 << LOG2W); i++) {
     uint32_t x = acc[i];
+    if (__ballot(x != 0u) == 0ull) continue;  // wave-uniform: no model in this word of any lane
     const uint32_t c = __popc(x);
     const uint32_t incl = wave_inclusive_scan(c, lane);
     const uint32_t tot = __shfl(incl, 63, 64);
@@ -541,15 +542,10 @@ __global__ __launch_bounds__(256) void k_batch_compact(BatchEnumArgs a) {
   const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
   const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   typedef const __attribute__((address_space(4))) EnumProg *enum_ptr;
-  // 64 tile counts per wave and step, one per lane; the wave then visits
-  // the tiles with models one by one
-  for (uint64_t base = wave * 64; base < a.total_tiles; base += nwaves * 64) {
-    const uint64_t mine = base + lane;
-    const bool has = mine < a.total_tiles && a.tile_counts[mine] != 0u;
-    uint64_t todo = __ballot(has);
-    while (todo) {
-    const uint64_t g = base + (uint64_t)__builtin_ctzll(todo);
-    todo &= todo - 1;
+  // one tile with models per wave and step, from the list k_list_tiles built
+  const uint32_t nlist = *a.nlist;
+  for (uint64_t k = wave; k < nlist; k += nwaves) {
+    const uint64_t g = a.list[k];
     // the program owning global tile g: tile0 ascends with the program index
     uint32_t lo = 0, hi = a.np;
     while (hi - lo > 1) {
@@ -570,8 +566,15 @@ __global__ __launch_bounds__(256) void k_batch_compact(BatchEnumArgs a) {
     }
     const uint64_t first = a.offsets[g] - a.offsets[p->tile0];
     tile_compact<LOG2W>(acc, U0, lane, first, p->out, p->capacity);
-    }
   }
+}
+
+// The global indices of the tiles that hold models, in any order (every
+// tile's output position comes from the scan, not from the list order).
+__global__ __launch_bounds__(256) void k_list_tiles(BatchEnumArgs a) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.total_tiles; g += stride)
+    if (a.tile_counts[g] != 0u) a.list[atomicAdd(a.nlist, 1u)] = (uint32_t)g;
 }
 
 // ------------------------------------------------------------------ scans
@@ -806,6 +809,11 @@ int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
 int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
   if (mode == dev::MODE_DNF) return batch_occ_mode<dev::MODE_DNF>(log2w, var, block, lds);
   return batch_occ_mode<dev::MODE_COUNT>(log2w, var, block, lds);
+}
+
+hipError_t launch_list_tiles(const BatchEnumArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(dev::k_list_tiles, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_compact(int log2w, const BatchEnumArgs &a, int grid, int block, hipStream_t s) {

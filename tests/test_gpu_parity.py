@@ -437,3 +437,37 @@ def test_batch_enumerate_needs_outputs(F):
     with pytest.raises(F.FbgError):      # DNF outputs first
         b.set_enum_outputs([torch.empty(4, dtype=torch.int64, device="cuda")])
     b.free()
+
+
+def test_c1_batched_step_at_full_size(F):
+    """The benchmark step itself (16 instances, n = 32, one batched DNF launch
+    and one batched enumeration, default tiling): counts and model lists
+    against the oracle goldens, and sampled DNF words of every instance
+    against the oracle one valuation at a time."""
+    import torch
+    g = golden("c1_3cnf_n32.json")["seeds"]
+    seeds = list(range(16))
+    if not all(str(s) in g for s in seeds):
+        pytest.skip("c1 golden incomplete")
+    texts = [workloads.random_3cnf(32, 136, s) for s in seeds]
+    progs = [F.Program(t, n) for t, n in texts]
+    b = F.Batch(progs)
+    dnfs = [torch.empty(1 << 26, dtype=torch.int64, device="cuda") for _ in seeds]
+    idx = [torch.full((4096,), -1, dtype=torch.int64, device="cuda") for _ in seeds]
+    b.set_dnf_outputs(dnfs)
+    b.set_enum_outputs(idx)
+    counts = host(b.eval_dnf())
+    b.enumerate()
+    rng = np.random.default_rng(5)
+    for s, (text, n), d, ii, c in zip(seeds, texts, dnfs, idx, counts):
+        rec = g[str(s)]
+        assert int(c) == rec["count"], s
+        assert host(ii)[:rec["count"]].tolist() == rec["models"], s
+        words = np.sort(rng.choice(1 << 26, 64, replace=False))
+        sample = d[torch.from_numpy(words.astype(np.int64)).cuda()].cpu().numpy().view(np.uint64)
+        vals = (words[:, None].astype(np.uint64) * 64 + np.arange(64, dtype=np.uint64)[None, :]).ravel()
+        bits = oracle.eval_at(text, n, vals).reshape(-1, 64)
+        want = (bits.astype(np.uint64) << np.arange(64, dtype=np.uint64)[None, :]).sum(axis=1).astype(np.uint64)
+        assert np.array_equal(sample, want), s
+    b.free()
+    del dnfs
