@@ -598,12 +598,15 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   b->plan_of.assign((size_t)np, 0);
   std::vector<std::vector<fbg::BatchItem>> plan_items;
   // 0: clause-only programs; 1: general programs whose registers all fit in
-  // VGPRs; 2: general programs with LDS registers (their LDS per wave would
-  // otherwise limit the occupancy of every program in the plan)
+  // VGPRs; 2: up to four registers in LDS; 3: more.  The LDS a plan's widest
+  // program needs per wave sets the occupancy of the whole plan, so the few
+  // register-hungry programs do not slow down the rest.
   auto group_of = [](const fbg_program *q) {
-    return !q->general() ? 0 : (lds_regs((uint32_t)q->c.nregs) == 0 ? 1 : 2);
+    if (!q->general()) return 0;
+    const uint32_t r = lds_regs((uint32_t)q->c.nregs);
+    return r == 0 ? 1 : (r <= 4 ? 2 : 3);
   };
-  for (int group = 0; group < 3; group++) {
+  for (int group = 0; group < 4; group++) {
     std::vector<int32_t> members;
     for (int32_t i = 0; i < np; i++)
       if (group_of(ps[i]) == group) members.push_back(i);
