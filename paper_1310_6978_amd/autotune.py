@@ -11,6 +11,7 @@ bucket, clause-only or not) in a JSON file (FBG_TUNE_CACHE, default
 through fbg_program_set_tuning.
 """
 
+import hashlib
 import json
 import math
 import os
@@ -45,6 +46,7 @@ class Tuner:
         self.candidates = tuple(candidates)
         self.reps = reps
         self.table = {}
+        self.last_key = None   # cache key of the last tune_batch
         if os.path.exists(self.path):
             try:
                 with open(self.path) as f:
@@ -85,6 +87,41 @@ class Tuner:
             if save:
                 self.save()
         prog.set_tuning(w)
+        return w
+
+    def tune_batch(self, progs, candidates=(0, 4, 8, 16, 32), save=True):
+        """Words per lane for a batch (0: each plan takes the tiling of its
+        largest program).  Times one batched count per candidate, caches the
+        fastest per (architecture, multiset of program keys) and returns it."""
+        import torch
+        digest = hashlib.sha1("\n".join(sorted(key_of(p) for p in progs)).encode()).hexdigest()[:16]
+        k = "%s|batch=%s|%d" % (_arch(), digest, len(progs))
+        self.last_key = k
+        hit = self.table.get(k, {}).get("words_per_lane")
+        if hit is not None:
+            return hit
+        out = torch.empty(len(progs), dtype=torch.int64, device="cuda")
+        times = {}
+        for w in candidates:
+            try:
+                b = fbg.Batch(progs, words_per_lane=w)
+            except fbg.FbgError:
+                continue  # registers do not fit at this tiling
+            b.count(out=out)  # warm-up
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(self.reps):
+                b.count(out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            times[w] = e0.elapsed_time(e1) / self.reps
+            b.free()
+        w = min(times, key=times.get)
+        self.table[k] = {"words_per_lane": w, "ms": times}
+        if save:
+            self.save()
         return w
 
     def save(self):

@@ -471,3 +471,17 @@ def test_c1_batched_step_at_full_size(F):
         assert np.array_equal(sample, want), s
     b.free()
     del dnfs
+
+
+def test_batch_autotuner_choice_is_exact(F, tmp_path):
+    from paper_1310_6978_amd import autotune
+    rng = random.Random(17)
+    texts = [workloads.random_dag(rng.choice([12, 16, 20]), rng.randrange(50, 400), i) for i in range(20)]
+    texts += [workloads.random_3cnf(21, 89, s) for s in range(4)]
+    progs = [F.Program(t, n) for t, n in texts]
+    t = autotune.Tuner(path=str(tmp_path / "tune.json"), reps=1)
+    w = t.tune_batch(progs, candidates=(0, 4, 16))
+    assert w in (0, 4, 16) and set(t.table[t.last_key]["ms"]) <= {0, 4, 16}
+    assert autotune.Tuner(path=str(tmp_path / "tune.json")).tune_batch(progs) == w   # cached
+    want = [oracle.count(tx, n) for tx, n in texts]
+    assert host(F.count_batch(progs, words_per_lane=w)).tolist() == want
