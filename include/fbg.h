@@ -77,10 +77,13 @@ typedef struct {
                             (NOT is not counted): the node count of the time
                             model of Section 2.3 */
   int32_t n_instr;       /* device instructions (for words_per_lane below) */
-  int32_t n_regs;        /* LDS registers per slice the program needs */
+  int32_t n_regs;        /* registers the general part needs (the first four
+                            live in VGPRs, the rest in LDS) */
   int32_t n_clause_instr;/* instructions that conjoin a literal set directly */
   int32_t words_per_lane;/* tuning the library picked for this program */
   uint64_t dnf_words;    /* max(1, 2^(n-6)) */
+  uint64_t code_bytes;   /* device memory the program holds (0 without a
+                            device): all tilings' encodings and tables */
 } fbg_program_info;
 
 /* Launch tuning.  Zero fields mean "let the library choose". */

@@ -135,6 +135,7 @@ struct fbg_program {
   int device = -1;  // -1: compiled without a device (host only)
   uint32_t *d_code = nullptr;
   int code_class = 0;  // size class in the device's code arena
+  uint64_t code_bytes = 0;  // bytes held on the device
   std::vector<uint32_t> words[kMaxLog2W + 1];
   uint64_t dev_off[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
   uint32_t nins[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
@@ -378,6 +379,7 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
     for (int l = 0; l <= kMaxLog2W; l++) all.insert(all.end(), p->words[l].begin(), p->words[l].end());
     all.resize(all.size() + 64, 0);  // padding: scalar loads never run past the allocation
     e = CodeArena::of(dev).alloc(all.size() * sizeof(uint32_t), (void **)&p->d_code, p->code_class);
+    p->code_bytes = p->code_class >= 0 ? (1ull << p->code_class) : all.size() * sizeof(uint32_t);
     if (e != hipSuccess) {
       delete p;
       return fail(FBG_E_NOMEM, "device memory for the program: %s", hipGetErrorString(e));
@@ -463,6 +465,7 @@ fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out) {
   out->n_clause_instr = (int32_t)p->ncl;
   out->words_per_lane = 1 << p->auto_log2w;
   out->dnf_words = dnf_words_of(p->c.n);
+  out->code_bytes = p->code_bytes;
   return FBG_OK;
 }
 

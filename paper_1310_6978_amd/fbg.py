@@ -38,7 +38,8 @@ class FbgError(RuntimeError):
 class ProgramInfo(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("const_value", ctypes.c_int32), ("l2in", ctypes.c_uint64),
                 ("n_instr", ctypes.c_int32), ("n_regs", ctypes.c_int32), ("n_clause_instr", ctypes.c_int32),
-                ("words_per_lane", ctypes.c_int32), ("dnf_words", ctypes.c_uint64)]
+                ("words_per_lane", ctypes.c_int32), ("dnf_words", ctypes.c_uint64),
+                ("code_bytes", ctypes.c_uint64)]
 
 
 class Tune(ctypes.Structure):

@@ -73,9 +73,8 @@ class ProgramCache:
 
 
 def program_bytes(info):
-    # six encodings of 32-byte instructions plus their pattern tables: an
-    # upper bound on what fbg_compile uploads
-    return 6 * (int(info["n_instr"]) + 8) * 32 + 32 * 243 * 4
+    """Device bytes a compiled program holds (its code arena block)."""
+    return int(info["code_bytes"])
 
 
 class _Req:

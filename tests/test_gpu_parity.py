@@ -485,3 +485,40 @@ def test_batch_autotuner_choice_is_exact(F, tmp_path):
     assert autotune.Tuner(path=str(tmp_path / "tune.json")).tune_batch(progs) == w   # cached
     want = [oracle.count(tx, n) for tx, n in texts]
     assert host(F.count_batch(progs, words_per_lane=w)).tolist() == want
+
+
+def test_maximum_sizes(F):
+    # n = 48, the largest valuation space: 2^48 valuations in a few passes
+    n = 48
+    p = F.Program("x0 & ~x47", n)
+    assert gpu_count(F, p) == 1 << 46
+    full = F.Program(" & ".join("x%d" % k for k in range(n)), n)   # one model, the last index
+    assert gpu_count(F, full) == 1
+    m, t = gpu_models(F, full, 4)
+    assert t == 1 and int(m[0]) == (1 << n) - 1
+    none = F.Program("x5 & ~x5 | x47 & x3 & ~x47", n)                  # folds to 0
+    assert gpu_count(F, none) == 0 and none.info["const_value"] == 0
+    assert host(F.count_batch([p, full, none])).tolist() == [1 << 46, 1, 0]
+    assert p.info["code_bytes"] >= 4096
+
+
+def test_dnf_at_36_variables(F):
+    # an 8 GiB DNF vector: sampled words against the oracle, total = count
+    import torch
+    text, n = workloads.equivalence_relations(9)
+    p = F.Program(text, n)
+    d = F.eval_dnf(p)
+    assert d.numel() == 1 << 30
+    rng = np.random.default_rng(3)
+    words = np.sort(rng.choice(1 << 30, 128, replace=False))
+    sample = d[torch.from_numpy(words.astype(np.int64)).cuda()].cpu().numpy().view(np.uint64)
+    vals = (words[:, None].astype(np.uint64) * 64 + np.arange(64, dtype=np.uint64)[None, :]).ravel()
+    bits = oracle.eval_at(text, n, vals).reshape(-1, 64)
+    want = (bits.astype(np.uint64) << np.arange(64, dtype=np.uint64)[None, :]).sum(axis=1).astype(np.uint64)
+    assert np.array_equal(sample, want)
+    idx, tot = F.enumerate_dnf(d, n, 30000)
+    assert int(host(tot)[0]) == 21147
+    g = golden("c2_theories.json").get("equivalence_k9")
+    if g:
+        assert host(idx)[:21147].tolist() == g["models"]
+    del d
