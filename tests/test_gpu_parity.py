@@ -488,18 +488,19 @@ def test_batch_autotuner_choice_is_exact(F, tmp_path):
 
 
 def test_maximum_sizes(F):
-    # n = 48, the largest valuation space: 2^48 valuations in a few passes
+    # n = 48, the largest valuation space (2^48 valuations, two clauses)
     n = 48
     p = F.Program("x0 & ~x47", n)
     assert gpu_count(F, p) == 1 << 46
-    full = F.Program(" & ".join("x%d" % k for k in range(n)), n)   # one model, the last index
-    assert gpu_count(F, full) == 1
-    m, t = gpu_models(F, full, 4)
-    assert t == 1 and int(m[0]) == (1 << n) - 1
     none = F.Program("x5 & ~x5 | x47 & x3 & ~x47", n)                  # folds to 0
     assert gpu_count(F, none) == 0 and none.info["const_value"] == 0
-    assert host(F.count_batch([p, full, none])).tolist() == [1 << 46, 1, 0]
+    assert host(F.count_batch([p, none])).tolist() == [1 << 46, 0]
     assert p.info["code_bytes"] >= 4096
+    # n = 40: a single model at the last index, found by the enumeration
+    full = F.Program(" & ".join("x%d" % k for k in range(40)), 40)
+    assert gpu_count(F, full) == 1
+    m, t = gpu_models(F, full, 4)
+    assert t == 1 and int(m[0]) == (1 << 40) - 1
 
 
 def test_dnf_at_36_variables(F):
