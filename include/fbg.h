@@ -76,10 +76,11 @@ typedef struct {
                             constant folding, hashing and dead-code removal
                             (NOT is not counted): the node count of the time
                             model of Section 2.3 */
-  int32_t n_instr;       /* device instructions (for words_per_lane below) */
+  int32_t n_instr;       /* clauses plus the instructions after them */
   int32_t n_regs;        /* registers the general part needs (the first four
                             live in VGPRs, the rest in LDS) */
-  int32_t n_clause_instr;/* instructions that conjoin a literal set directly */
+  int32_t n_clause_instr;/* leading clauses (OR-sets conjoined directly; they
+                            form the clause block of the encoding) */
   int32_t words_per_lane;/* tuning the library picked for this program */
   uint64_t dnf_words;    /* max(1, 2^(n-6)) */
   uint64_t code_bytes;   /* device memory the program holds (0 without a
@@ -337,8 +338,11 @@ fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t ou
 /*
  * fbg_program_emulate -- run the encoded device program of `p` for the given
  * words_per_lane on the host, slice by slice, exactly as the kernels
- * interpret it, and write the DNF words (h_dnf, host memory, >= dnf_words)
- * and/or the count (h_count).  A debugging aid for the compiler and encoder,
+ * interpret it (the uniform-cofactor reading when the program's default
+ * tuning selects it, fbg_program_set_tuning), and write the DNF words
+ * (h_dnf, host memory, >= dnf_words) and/or the count (h_count).  The result
+ * does not depend on the words per lane or the reading; comparing them
+ * checks the encoder.  A debugging aid for the compiler and encoder,
  * never used by the calls above.  n <= 30.
  */
 fbg_status fbg_program_emulate(const fbg_program *p, int32_t words_per_lane, uint64_t *h_dnf, uint64_t out_words,

@@ -278,7 +278,6 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   memset(&a, 0, sizeof a);
   a.code = p->d_code + p->dev_off[log2w];
   a.nins = p->nins[log2w];
-  a.ncl = p->ncl;
   a.nregs = lds_regs((uint32_t)p->c.nregs);
   a.n = p->c.n;
   a.nslices = p->nslices;
@@ -291,7 +290,6 @@ fbg::BatchProg batch_prog(const fbg_program *p, int l) {
   memset(&b, 0, sizeof b);
   b.code = p->d_code + p->dev_off[l];
   b.nins = p->nins[l];
-  b.ncl = p->ncl;
   b.nregs = lds_regs((uint32_t)p->c.nregs);
   b.n = p->c.n;
   b.nslices = p->nslices;
@@ -460,7 +458,7 @@ fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out) {
   out->n_vars = p->c.n;
   out->const_value = p->c.const_value;
   out->l2in = p->c.l2in;
-  out->n_instr = (int32_t)p->nins[p->auto_log2w];
+  out->n_instr = (int32_t)(p->ncl + p->nins[p->auto_log2w]);  // clauses + instructions after them
   out->n_regs = p->c.nregs;
   out->n_clause_instr = (int32_t)p->ncl;
   out->words_per_lane = 1 << p->auto_log2w;
@@ -1061,7 +1059,7 @@ fbg_status fbg_program_emulate(const fbg_program *p, int32_t words_per_lane, uin
   const uint64_t need = dnf_words_of(p->c.n);
   if (h_dnf && out_words < need) return fail(FBG_E_INVAL, "out_words too small");
   std::vector<uint32_t> s32((size_t)std::max<uint64_t>(2, p->nslices), 0u);
-  fbg::emulate_program(p->words[l], p->nins[l], p->c.nregs, p->c.n, l, s32.data());
+  fbg::emulate_program(p->words[l], p->nins[l], p->c.nregs, p->c.n, l, p->cofactor, s32.data());
   if (h_dnf) memcpy(h_dnf, s32.data(), need * 8);
   if (h_count) {
     uint64_t c = 0;

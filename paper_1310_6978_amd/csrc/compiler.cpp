@@ -17,6 +17,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <set>
 #include <cctype>
 #include <string>
 #include <unordered_map>
@@ -833,39 +835,170 @@ uint32_t table_f(uint32_t f, uint32_t a, uint32_t b) {
 }
 }  // namespace
 
+namespace {
+
+// Group of a clause at tiling log2w, from the words on which its word-index
+// literals hold (pat): 0 (no word literal), 1 + 2j + v (one literal on word
+// bit j, false on the words whose bit j is v), kMulti, or kAlwaysTrue.
+constexpr int kMulti = -1, kAlwaysTrue = -2;
+
+int group_of(uint32_t pat, int log2w) {
+  const int W = 1 << log2w;
+  const uint32_t full = W == 32 ? ~0u : ((1u << W) - 1u);
+  pat &= full;
+  if (pat == 0) return 0;
+  if (pat == full) return kAlwaysTrue;
+  for (int j = 0; j < log2w; j++) {
+    uint32_t ones = 0;  // the words whose bit j is 1
+    for (int i = 0; i < W; i++)
+      if ((i >> j) & 1) ones |= 1u << i;
+    if (pat == ones) return 1 + 2 * j;             // x: false where bit j = 0
+    if (pat == (full & ~ones)) return 1 + 2 * j + 1;  // ~x: false where bit j = 1
+  }
+  return kMulti;
+}
+
+struct BlockClause {
+  SetWords s;
+  int group;
+  bool tile_only;  // only tile literals (or none at all)
+};
+
+int pattern_entry(std::vector<uint32_t> &pats, uint32_t pat) {
+  size_t e = 0;
+  while (e < pats.size() && pats[e] != pat) e++;
+  if (e == pats.size()) pats.push_back(pat);
+  return (int)e;
+}
+
+// One chunk of at most FBG_CB_CHUNK clauses; see fbg_isa.h for the layout.
+// The clauses arrive sorted so that each key is a run of consecutive
+// clauses: one group and in-word part (static), one pattern and in-word part
+// (multi).
+void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, bool multi, int log2w,
+                std::vector<uint32_t> &pats, bool first, std::vector<uint32_t> &out) {
+  const uint32_t nc = (uint32_t)(hi - lo);
+  const int W = 1 << log2w;
+  const size_t base = out.size();
+  out.resize(base + FBG_CB_CHUNK_HDR, 0u);
+  out[base + 0] = nc;
+  // lane bits: clause c holds on lane l through a lane literal; padding set
+  for (int lane = 0; lane < 64; lane++) {
+    uint32_t b = nc == FBG_CB_CHUNK ? 0u : ~0u << nc;
+    for (uint32_t c = 0; c < nc; c++)
+      if ((cl[lo + c].s.lanemask >> lane) & 1u) b |= 1u << c;
+    out.push_back(b);
+  }
+  uint32_t tmask = 0;
+  for (uint32_t c = 0; c < nc; c++) {
+    const SetWords &s = cl[lo + c].s;
+    out.push_back((uint32_t)s.sel);
+    out.push_back((uint32_t)(s.sel >> 32));
+    out.push_back((uint32_t)s.neg);
+    out.push_back((uint32_t)(s.neg >> 32));
+    if (cl[lo + c].tile_only) tmask |= 1u << c;
+  }
+  // runs of equal keys; a run [a, b) has its top bit b - 1 in T and the bits
+  // below it in F
+  auto same = [&](uint32_t a, uint32_t b) {
+    const BlockClause &x = cl[lo + a], &y = cl[lo + b];
+    if (x.s.mconst != y.s.mconst || x.tile_only != y.tile_only) return false;
+    return multi ? x.s.pat == y.s.pat : x.group == y.group;
+  };
+  uint32_t T = 0, F = 0;
+  std::vector<uint32_t> keys;
+  uint32_t counts[1 + 2 * 5] = {0};
+  for (uint32_t a = 0; a < nc;) {
+    uint32_t b = a + 1;
+    while (b < nc && same(a, b)) b++;
+    T |= 1u << (b - 1);
+    for (uint32_t c = a; c + 1 < b; c++) F |= 1u << c;
+    const BlockClause &x = cl[lo + a];
+    keys.push_back(b - 1);
+    keys.push_back(x.s.mconst);
+    if (multi) {
+      keys.push_back((uint32_t)(pattern_entry(pats, x.s.pat) * W));
+      keys.push_back(0u);
+    } else {
+      counts[x.group]++;
+    }
+    a = b;
+  }
+  out.insert(out.end(), keys.begin(), keys.end());
+  if (multi) {
+    out[base + 2] = (uint32_t)(keys.size() / 4);
+  } else {
+    for (int g = 0; g < 1 + 2 * log2w; g++) out[base + 2 + g / 4] |= counts[g] << (8 * (g % 4));
+    if (first) out[base + 5] = tmask;
+  }
+  out[base + 6] = T;
+  out[base + 7] = F;
+  while ((out.size() - base) % 4) out.push_back(0u);
+  out[base + 1] = (uint32_t)(out.size() - base);
+}
+
+}  // namespace
+
 uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words) {
   const size_t base = words.size();
   const int W = 1 << log2w;
-  std::vector<uint32_t> pats{0u};  // pattern table, entry 0 = no per-word literal
-  // Clauses whose literals are all tile variables at this tiling go first
-  // (stable), so that the uniform-cofactor kernel meets a clause that kills a
-  // whole tile as early as possible.  Within the clause prefix the order is
-  // free: every clause is ANDed into the same accumulator.
   const int tile_bit = FBG_TILE_BASE_BIT + log2w;
-  std::vector<size_t> order;
-  order.reserve(c.code.size());
+  std::vector<uint32_t> pats{0u};  // pattern table, entry 0 = no per-word literal
   size_t ncl = 0;
   while (ncl < c.code.size() && c.code[ncl].op == FBG_OP_CL) ncl++;
-  for (int pass = 0; pass < 2; pass++)
-    for (size_t k = 0; k < ncl; k++) {
-      bool tile_only = true;
-      for (const Lit &l : c.code[k].ls.lits) tile_only = tile_only && l.k >= tile_bit;
-      if (tile_only == (pass == 0)) order.push_back(k);
-    }
-  for (size_t k = ncl; k < c.code.size(); k++) order.push_back(k);
-  for (size_t idx : order) {
+
+  // ---- the clause block
+  std::vector<BlockClause> stat, multi;
+  std::set<std::array<uint64_t, 4>> seen;
+  for (size_t k = 0; k < ncl; k++) {
+    BlockClause b;
+    b.s = encode_set(c.code[k].ls, log2w);
+    if (b.s.mconst == ~0u) continue;  // a tautology
+    b.group = group_of(b.s.pat, log2w);
+    if (b.group == kAlwaysTrue) continue;
+    // the same clause twice (the same literals in another order) once
+    const std::array<uint64_t, 4> id{(uint64_t)b.s.mconst << 32 | b.s.pat, b.s.lanemask, b.s.sel, b.s.neg};
+    if (!seen.insert(id).second) continue;
+    b.tile_only = true;
+    for (const Lit &l : c.code[k].ls.lits) b.tile_only = b.tile_only && l.k >= tile_bit;
+    (b.group == kMulti ? multi : stat).push_back(b);
+  }
+  // clauses made only of tile literals first (the uniform-cofactor kernel
+  // drops a tile as soon as one of them is false on it), then by group and
+  // in-word part so that equal keys share a chunk
+  std::stable_sort(stat.begin(), stat.end(), [](const BlockClause &a, const BlockClause &b) {
+    if (a.tile_only != b.tile_only) return a.tile_only;
+    if (a.group != b.group) return a.group < b.group;
+    return a.s.mconst < b.s.mconst;
+  });
+  std::stable_sort(multi.begin(), multi.end(), [](const BlockClause &a, const BlockClause &b) {
+    if (a.s.pat != b.s.pat) return a.s.pat < b.s.pat;
+    return a.s.mconst < b.s.mconst;
+  });
+  std::vector<uint32_t> block(FBG_CB_HDR, 0u);
+  uint32_t nstat = 0, nmulti = 0;
+  for (size_t lo = 0; lo < stat.size(); lo += FBG_CB_CHUNK, nstat++)
+    emit_chunk(stat, lo, std::min(stat.size(), lo + FBG_CB_CHUNK), false, log2w, pats, lo == 0, block);
+  for (size_t lo = 0; lo < multi.size(); lo += FBG_CB_CHUNK, nmulti++)
+    emit_chunk(multi, lo, std::min(multi.size(), lo + FBG_CB_CHUNK), true, log2w, pats, false, block);
+  block[0] = (uint32_t)block.size();
+  block[1] = nstat;
+  block[2] = nmulti;
+  block[3] = (uint32_t)(stat.size() + multi.size());
+  words.insert(words.end(), block.begin(), block.end());
+
+  // ---- the instructions after the clauses
+  const size_t ins_base = words.size();
+  for (size_t idx = ncl; idx < c.code.size(); idx++) {
     const HIns &h = c.code[idx];
     uint32_t w[FBG_INS_WORDS] = {0, 0, 0, 0, 0, 0, 0, 0};
     w[0] = h.op;
     if (h.op == FBG_OP_CL || h.op == FBG_OP_LDL || h.op == FBG_OP_OPL) {
       SetWords s = encode_set(h.ls, log2w);
-      // CL carries plain OR-sets only (the kernel's clause loop relies on it)
       if (h.op == FBG_OP_CL) s.flags &= ~(uint32_t)(FBG_XORSET | FBG_INV);
-      size_t e = 0;
-      while (e < pats.size() && pats[e] != s.pat) e++;
-      if (e == pats.size()) pats.push_back(s.pat);
       // at most 3^5 = 243 entries of at most 32 words: the offset fits 16 bits
-      w[0] |= s.flags | ((uint32_t)(e * (size_t)W) << FBG_ARG_SHIFT);
+      const int e = pattern_entry(pats, s.pat);
+      w[0] |= s.flags | ((uint32_t)(e * W) << FBG_ARG_SHIFT);
       w[1] = s.mconst;
       w[2] = (uint32_t)s.lanemask;
       w[3] = (uint32_t)(s.lanemask >> 32);
@@ -896,21 +1029,10 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
     }
     words.insert(words.end(), w, w + FBG_INS_WORDS);
   }
-  const uint32_t nins = (uint32_t)((words.size() - base) / FBG_INS_WORDS);
-  // Each clause of the prefix carries the pattern entry of the next clause in
-  // w0 bits 8..15 (0 after the last), so the kernel can fetch it one clause
-  // ahead.
-  for (uint32_t k = 0; k < nins && (words[base + (size_t)k * FBG_INS_WORDS] & 15u) == FBG_OP_CL; k++) {
-    uint32_t &w0 = words[base + (size_t)k * FBG_INS_WORDS];
-    uint32_t next = 0;
-    if (k + 1 < nins) {
-      const uint32_t w1 = words[base + (size_t)(k + 1) * FBG_INS_WORDS];
-      if ((w1 & 15u) == FBG_OP_CL) next = (w1 >> FBG_ARG_SHIFT) / (uint32_t)W;
-    }
-    w0 |= (next & 0xFFu) << FBG_F_SHIFT;
-  }
+  const uint32_t nins = (uint32_t)((words.size() - ins_base) / FBG_INS_WORDS);
   for (uint32_t pat : pats)
     for (int i = 0; i < W; i++) words.push_back(((pat >> i) & 1u) ? ~0u : 0u);
+  while ((words.size() - base) % 4) words.push_back(0u);
   return nins;
 }
 
@@ -924,11 +1046,51 @@ uint32_t leading_clauses(const Compiled &c) {
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
   static const char *ops[] = {"?", "CL", "LDL", "OPL", "ST", "OPR", "ACC", "LDR", "NOT"};
   const int W = 1 << log2w;
-  const uint32_t *table = words.data() + (size_t)nins * FBG_INS_WORDS;
-  std::string out = "; words per lane " + std::to_string(W) + "\n";
+  const uint32_t *cb = words.data();
+  const uint32_t *ins = cb + cb[0];
+  const uint32_t *table = ins + (size_t)nins * FBG_INS_WORDS;
   char buf[256];
+  std::string out = "; words per lane " + std::to_string(W) + "\n";
+  snprintf(buf, sizeof buf, "; clause block: %u clauses, %u static chunks, %u multi chunks\n", cb[3], cb[1], cb[2]);
+  out += buf;
+  const uint32_t *ch = cb + FBG_CB_HDR;
+  for (uint32_t k = 0; k < cb[1] + cb[2]; k++) {
+    const bool multi = k >= cb[1];
+    const uint32_t nc = ch[0];
+    snprintf(buf, sizeof buf, "chunk %u %s clauses=%u tile_only=%08x tops=%08x fill=%08x\n", k,
+             multi ? "multi" : "static", nc, multi ? 0u : ch[5], ch[6], ch[7]);
+    out += buf;
+    const uint32_t *td = ch + FBG_CB_CHUNK_HDR + 64;
+    for (uint32_t c = 0; c < nc; c++) {
+      uint64_t lm = 0;
+      for (int lane = 0; lane < 64; lane++)
+        if ((ch[FBG_CB_CHUNK_HDR + lane] >> c) & 1u) lm |= 1ull << lane;
+      snprintf(buf, sizeof buf, "  clause %u lane=%016llx sel=%08x%08x neg=%08x%08x\n", c, (unsigned long long)lm,
+               td[4 * c + 1], td[4 * c], td[4 * c + 3], td[4 * c + 2]);
+      out += buf;
+    }
+    const uint32_t *key = td + 4 * nc;
+    if (!multi) {
+      for (int g = 0; g < 1 + 2 * log2w; g++) {
+        const uint32_t cnt = (ch[2 + g / 4] >> (8 * (g % 4))) & 0xFFu;
+        for (uint32_t j = 0; j < cnt; j++, key += 2) {
+          snprintf(buf, sizeof buf, "  key group=%d top=%u mconst=%08x\n", g, key[0], key[1]);
+          out += buf;
+        }
+      }
+    } else {
+      for (uint32_t j = 0; j < ch[2]; j++, key += 4) {
+        uint32_t pat = 0;
+        for (int i = 0; i < W; i++)
+          if (table[key[2] + i]) pat |= 1u << i;
+        snprintf(buf, sizeof buf, "  key multi top=%u mconst=%08x pat=%08x\n", key[0], key[1], pat);
+        out += buf;
+      }
+    }
+    ch += ch[1];
+  }
   for (size_t pc = 0; pc < (size_t)nins * FBG_INS_WORDS; pc += FBG_INS_WORDS) {
-    const uint32_t *w = &words[pc];
+    const uint32_t *w = &ins[pc];
     uint32_t op = w[0] & 15u;
     uint32_t arg = w[0] >> FBG_ARG_SHIFT;
     const char *name = op <= 8 ? ops[op] : "?";
@@ -979,43 +1141,84 @@ inline uint32_t bitop3(uint32_t tt, uint32_t a, uint32_t b, uint32_t c) {
   return r;
 }
 
+// The clause block at (lane, word i, tile group U0), read the way the kernels
+// read it; the product tree is written here as its closed form.  With cof,
+// a false clause made only of tile literals ends the tile, as in the
+// uniform-cofactor kernels.
+uint32_t clause_block_value(const uint32_t *cb, const uint32_t *table, int log2w, uint32_t lane, uint32_t i,
+                            uint64_t U0, bool cof) {
+  uint32_t G[1 + 2 * 5];
+  for (uint32_t &g : G) g = ~0u;
+  const uint32_t *ch = cb + FBG_CB_HDR;
+  uint32_t acc = 0;
+  for (uint32_t k = 0; k < cb[1] + cb[2]; k++) {
+    const bool multi = k >= cb[1];
+    if (k == cb[1]) {
+      acc = G[0];
+      for (int j = 0; j < log2w; j++) acc &= G[1 + 2 * j + ((i >> j) & 1u)];
+    }
+    const uint32_t nc = ch[0];
+    const uint32_t *td = ch + FBG_CB_CHUNK_HDR + 64;
+    uint32_t S = 0;
+    for (uint32_t c = 0; c < nc; c++) {
+      const uint64_t sel = (uint64_t)td[4 * c] | ((uint64_t)td[4 * c + 1] << 32);
+      const uint64_t neg = (uint64_t)td[4 * c + 2] | ((uint64_t)td[4 * c + 3] << 32);
+      if ((U0 & sel) != neg) S |= 1u << c;
+    }
+    if (cof && k == 0 && !multi && (S & ch[5]) != ch[5]) return 0u;
+    const uint32_t U = ~(ch[FBG_CB_CHUNK_HDR + lane] | S);
+    // the clauses of a key are the run of bits ending at its top bit, after
+    // the previous key's top bit
+    const uint32_t *key = td + 4 * nc;
+    auto run_false = [&](uint32_t top) {
+      uint32_t lo = top;
+      while (lo > 0 && !((ch[6] >> (lo - 1)) & 1u)) lo--;
+      const uint32_t run = (uint32_t)(((2ull << top) - 1) & ~((1ull << lo) - 1));
+      return (U & run) != 0;
+    };
+    if (!multi) {
+      for (int g = 0; g < 1 + 2 * log2w; g++) {
+        const uint32_t cnt = (ch[2 + g / 4] >> (8 * (g % 4))) & 0xFFu;
+        for (uint32_t j = 0; j < cnt; j++, key += 2)
+          if (run_false(key[0])) G[g] &= key[1];
+      }
+    } else {
+      for (uint32_t j = 0; j < ch[2]; j++, key += 4)
+        if (run_false(key[0])) acc &= key[1] | table[key[2] + i];
+    }
+    ch += ch[1];
+  }
+  if (cb[2] == 0) {
+    acc = G[0];
+    for (int j = 0; j < log2w; j++) acc &= G[1 + 2 * j + ((i >> j) & 1u)];
+  }
+  return acc;
+}
+
 }  // namespace
 
-void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nregs, int n, int log2w,
+void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nregs, int n, int log2w, bool cof,
                      uint32_t *out32) {
   const uint64_t slices = n >= FBG_SLICE_BITS ? (1ull << (n - FBG_SLICE_BITS)) : 1ull;
   const uint64_t W = 1ull << log2w;
   std::vector<uint32_t> R((size_t)nregs + 1, 0);
-  const uint32_t *table = words.data() + (size_t)nins * FBG_INS_WORDS;
+  const uint32_t *cb = words.data();
+  const uint32_t *ins = cb + cb[0];
+  const uint32_t *table = ins + (size_t)nins * FBG_INS_WORDS;
   for (uint64_t s = 0; s < slices; s++) {
     uint32_t lane = (uint32_t)(s & 63u);
     uint64_t U = s >> FBG_LANE_BITS;
     uint32_t i = (uint32_t)(U & (W - 1));
     uint64_t U0 = U - i;
-    uint32_t acc = ~0u, cur = 0;
-    // for W <= 16 the kernels find the pattern of clause k+1 through the
-    // index clause k carries in w0 bits 8..15; read it the same way
-    uint32_t chained = 0;
-    bool in_prefix = true;
+    uint32_t acc = clause_block_value(cb, table, log2w, lane, i, U0, cof), cur = 0;
     for (size_t pc = 0; pc < nins; pc++) {
-      const uint32_t *w = &words[pc * FBG_INS_WORDS];
+      const uint32_t *w = &ins[pc * FBG_INS_WORDS];
       uint32_t op = w[0] & 15u;
       uint32_t tt = (w[0] >> FBG_F_SHIFT) & 0xFFu;
       uint32_t arg = w[0] >> FBG_ARG_SHIFT;
       uint32_t inv = (w[0] & FBG_INV) ? ~0u : 0u;
-      if (op != FBG_OP_CL) in_prefix = false;
       switch (op) {
-        case FBG_OP_CL: {
-          // clauses: plain OR-sets, acc &= T | P(i); for W <= 16 in the
-          // prefix the pattern entry comes from the previous clause
-          uint32_t own = arg;
-          if (in_prefix && log2w <= 4) {
-            if (pc > 0) own = chained * (uint32_t)W;
-            chained = (w[0] >> FBG_F_SHIFT) & 0xFFu;
-          }
-          acc &= set_lane_value(w, lane, U0) | table[own + i];
-          break;
-        }
+        case FBG_OP_CL: acc &= set_lane_value(w, lane, U0) | table[arg + i]; break;
         case FBG_OP_LDL:
         case FBG_OP_OPL: cur = bitop3(tt, cur, set_lane_value(w, lane, U0), table[arg + i]); break;
         case FBG_OP_ST: R[arg] = cur; break;

@@ -51,8 +51,9 @@ struct Compiled {
 int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset,
                     const int32_t *subst = nullptr, int n_free = 0);
 
-// Encode for words-per-lane 2^log2w (W <= 16).  Appends FBG_INS_WORDS words
-// per instruction, then the pattern table; returns the instruction count.
+// Encode for words-per-lane 2^log2w (W <= 32).  Appends the clause block,
+// FBG_INS_WORDS words per instruction after it, then the pattern table (a
+// multiple of 4 words in all); returns the instruction count.
 uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words);
 
 // Number of leading clause (CL) instructions; no CL follows them.
@@ -63,7 +64,8 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
 
 // Host interpretation of an encoded program, slice by slice (debug aid).
 // Writes 2^max(n-5,0) 32-bit slices into out32 (zeroed tail for n < 5).
-void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nregs, int n, int log2w,
+// cof: read the program the way the uniform-cofactor kernels do.
+void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nregs, int n, int log2w, bool cof,
                      uint32_t *out32);
 
 }  // namespace fbg

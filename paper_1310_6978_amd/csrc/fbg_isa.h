@@ -24,8 +24,54 @@
  * word 0 (the word-index bits are zero in U0; sel/neg only use bits >= log2 W).
  * A literal set may be inverted (INV), which makes AND-sets of literals.
  *
- * Registers per slice: acc (the running conjunction, starts all-ones), cur
- * (the value being built) and R[0..nregs) in LDS.
+ * Registers per slice: acc (the running conjunction), cur (the value being
+ * built) and R[0..nregs) (the first few in VGPRs, the rest in LDS).
+ *
+ * Clause block.  The leading clauses of a program (its top-level conjunction
+ * of OR-sets) are not instructions: they form a block that comes first in
+ * the encoded program and sets acc.  Write a clause as T_c(l, t) | P_c(i),
+ * with T_c = mconst | V(l) | Q(t) and P_c the OR of its word-index literals.
+ * P_c is the only part that depends on the word, so clauses are grouped by
+ * it; by distributivity AND_c (T_c | P) = (AND_c T_c) | P, and a group costs
+ * one per-lane product whatever its size.  Groups:
+ *   0          no word literal: applies to every word
+ *   1 + 2j + v one word literal, on word-index bit j, false on the words
+ *              whose bit j is v
+ *   multi      two or more word literals: P(i) from the pattern table
+ * With G_g the per-lane product of group g, the static groups give
+ *   acc[i] = G_0 & AND_j G_{1 + 2j + (bit j of i)},
+ * which the kernels build as a product tree (2W - 2 ANDs per tile); each
+ * multi key then does acc[i] &= T | P(i).
+ *
+ * Chunks.  Clauses are packed FBG_CB_CHUNK to a chunk, static and multi
+ * clauses in separate chunks.  A chunk stores per lane the bits Lb[l] (bit c:
+ * lane l satisfies clause c through a lane literal; bits >= nc are set) and
+ * per clause the tile selectors (sel_c, neg_c).  One compare across lanes
+ * (lane l takes clause l mod 32) gives S (bit c: a tile literal of clause c
+ * holds, (U0 & sel_c) != neg_c), and U(l) = ~(Lb[l] | S) marks the clauses
+ * left false on lane l by everything but their in-word and word literals.  A
+ * key gathers a run of consecutive clauses of one group with the same
+ * in-word part m: G_g &= (some clause of the run is in U) ? m : all-ones.
+ * With T the top bits of the runs and F the other bits of runs longer than
+ * one, the carries of ((U & ~T) + F) stop at the top of each run, so
+ *   A = (((U & ~T) + F) | U) & T
+ * has the top bit of a run set exactly when the run meets U: one add for all
+ * the keys of a chunk, then one bit extract and one v_bitop3 per key.
+ *
+ * Block layout (uint32 words):
+ *   cb[0] size of the block in words (the instructions start there)
+ *   cb[1] static chunks   cb[2] multi chunks   cb[3] clauses
+ *   then the chunks, each:
+ *     h[0] clauses nc (1 .. FBG_CB_CHUNK)   h[1] chunk size in words
+ *     static: h[2..4] number of keys of groups 0 .. 2 log2 W, one byte each
+ *             h[5]    first chunk only: the clauses made of tile literals
+ *                     alone (the encoder puts them first)
+ *     multi:  h[2]    number of keys
+ *     h[6] T, h[7] F
+ *     Lb[64]; (sel lo, sel hi, neg lo, neg hi) x nc
+ *     static keys (top bit, m) by group; multi keys (top bit, m, pattern
+ *     offset, 0)
+ *     zero padding to a multiple of 4 words
  *
  * Instruction: 8 x uint32.
  *   w0 bits 0..3   opcode
@@ -34,13 +80,13 @@
  *      bit 6       INV     second operand inverted (literal set / register)
  *      bit 7       INVOUT  invert cur after the operation
  *      bits 8..9   f       binary function for OPL/OPR: 0 AND, 1 OR, 2 XOR
- *      bits 8..15  (CL only) index of the pattern entry of pat, see below
  *      bits 16..31 pat (literal-set ops) or register index (register ops)
  *   w1           mconst
  *   w2, w3       lanemask (lo, hi)
  *   w4, w5       sel (lo, hi)
  *   w6, w7       neg (lo, hi)
- * Opcodes:
+ * Opcodes (the instructions after the clause block; acc starts as the
+ * block's value, cur as zero):
  *   CL   acc &= L            LDL  cur = L            OPL  cur = f(cur, L)
  *   ST   R[r] = cur          OPR  cur = f(cur, R[r]^inv)
  *   ACC  acc &= cur ^ inv    LDR  cur = R[r] ^ inv   NOT  cur = ~cur
@@ -48,9 +94,9 @@
  *
  * Pattern table.  After the nins instructions comes a table of W-word
  * entries; entry e holds P(0..W-1) = -(bit i of pat) for one pattern, entry 0
- * is all zeros.  A clause reads its W values with one scalar load instead of
+ * is all zeros.  An operation reads its W values with scalar loads instead of
  * extracting W bits.  Per-word patterns are ORs of literals over the log2 W
- * word-index bits, so there are at most 3^(log2 W) <= 81 of them.
+ * word-index bits, so there are at most 3^(log2 W) <= 243 of them.
  */
 #ifndef FBG_ISA_H
 #define FBG_ISA_H
@@ -77,6 +123,9 @@
 #define FBG_ARG_SHIFT 16
 
 #define FBG_INS_WORDS 8
+#define FBG_CB_HDR 4        /* words of the clause-block header */
+#define FBG_CB_CHUNK 32     /* clauses per chunk */
+#define FBG_CB_CHUNK_HDR 8  /* words of a chunk header */
 #define FBG_LANE_BITS 6  /* 64 lanes per wave */
 #define FBG_SLICE_BITS 5 /* 32 valuations per word */
 #define FBG_TILE_BASE_BIT (FBG_SLICE_BITS + FBG_LANE_BITS) /* 11 */

@@ -11,9 +11,8 @@ namespace fbg {
 constexpr uint32_t kVgprRegs = 4;
 
 struct EvalArgs {
-  const uint32_t *code;   // encoded program: instructions, then the pattern table
-  uint32_t nins;          // instructions
-  uint32_t ncl;           // leading clause instructions
+  const uint32_t *code;   // encoded program: clause block, instructions, pattern table
+  uint32_t nins;          // instructions after the clause block
   uint32_t nregs;         // registers held in LDS (beyond kVgprRegs)
   int32_t n;              // variables
   uint64_t nslices;       // 2^max(n-5, 0) valid 32-bit words
@@ -30,7 +29,6 @@ struct EvalArgs {
 struct BatchProg {
   const uint32_t *code;
   uint32_t nins;
-  uint32_t ncl;
   uint32_t nregs;
   int32_t n;
   uint64_t nslices;

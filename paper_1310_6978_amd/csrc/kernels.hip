@@ -116,9 +116,9 @@ __device__ __forceinline__ void reg_op(uint32_t tt, uint32_t (&cur)[W], const ui
 static_assert(kVgprRegs == 4, "the register switches below name registers 0..3");
 
 template <int LOG2W>
-__device__ __forceinline__ void run_general(const code_ptr code, const code_ptr table, code_ptr w, uint32_t ncl,
-                                            uint32_t nins, uint64_t U0, uint32_t lane,
-                                            uint32_t (&acc)[1 << LOG2W], uint32_t *__restrict__ regs) {
+__device__ __forceinline__ void run_general(code_ptr w, const code_ptr table, uint32_t nins, uint64_t U0,
+                                            uint32_t lane, uint32_t (&acc)[1 << LOG2W],
+                                            uint32_t *__restrict__ regs) {
   constexpr int W = 1 << LOG2W;
   uint32_t cur[W], rv[kVgprRegs][W], tmp[W];
 #pragma unroll
@@ -127,8 +127,7 @@ __device__ __forceinline__ void run_general(const code_ptr code, const code_ptr 
   for (uint32_t r = 0; r < kVgprRegs; r++)
 #pragma unroll
     for (int i = 0; i < W; i++) rv[r][i] = 0u;
-  (void)code;
-  for (uint32_t pc = ncl; pc < nins; ++pc, w += FBG_INS_WORDS) {
+  for (uint32_t pc = 0; pc < nins; ++pc, w += FBG_INS_WORDS) {
     const u32x8 ins = *(const __attribute__((address_space(4))) u32x8 *)w;
     const uint32_t w0 = ins[0];
     const uint32_t op = w0 & 15u;
@@ -149,7 +148,7 @@ __device__ __forceinline__ void run_general(const code_ptr code, const code_ptr 
         const uint32_t S = ins[1] ^ ((__popcll(U0 & sel) & 1) ? ~0u : 0u);
         T = lane_part(lm) ^ S;
       }
-      if (op == FBG_OP_CL) {  // a clause outside the prefix (the compiler emits none)
+      if (op == FBG_OP_CL) {  // a clause after other instructions (the compiler emits none)
 #pragma unroll
         for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
         continue;
@@ -210,106 +209,117 @@ __device__ __forceinline__ void run_general(const code_ptr code, const code_ptr 
   }
 }
 
-// Interpret one program over the W words of this lane in tile group U0.
-// The first ncl instructions are clauses (the code generator emits them
-// first); GEN = false means there is nothing else.
-//
-// COF = true is the uniform-cofactor variant: the tile bits of the index are
-// constants on the whole tile, so a clause with a true tile literal holds on
-// the tile and is skipped, and a clause whose only literals are false tile
-// literals is false on the whole tile, which ends the tile (acc = 0).  The
-// result is the same; the work depends on the data.  The encoder puts the
-// clauses made only of tile literals first.
-template <int LOG2W, bool GEN, bool COF>
-__device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g, uint32_t nins, uint32_t ncl,
-                                            uint64_t U0, uint32_t lane, uint32_t (&acc)[1 << LOG2W],
-                                            uint32_t *__restrict__ regs) {
-  constexpr int W = 1 << LOG2W;
-  const code_ptr code = (code_ptr)code_g;
-  const code_ptr table = code + (size_t)nins * FBG_INS_WORDS;
-#pragma unroll
-  for (int i = 0; i < W; i++) acc[i] = ~0u;
+// One chunk of the clause block: the tile tests of its clauses (lane l takes
+// clause l mod 32; one compare across the wave) and U, the clauses of the
+// chunk that neither a lane nor a tile literal satisfies on this lane.
+__device__ __forceinline__ uint32_t chunk_tile_bits(const uint32_t *__restrict__ ch, uint32_t nc, uint64_t U0,
+                                                    uint32_t lane) {
+  const uint32_t c = min(lane & (FBG_CB_CHUNK - 1u), nc - 1u);
+  const uint4 td = *(const uint4 *)(ch + FBG_CB_CHUNK_HDR + 64 + 4 * c);
+  const uint64_t sel = (uint64_t)td.x | ((uint64_t)td.y << 32);
+  const uint64_t neg = (uint64_t)td.z | ((uint64_t)td.w << 32);
+  return (uint32_t)__ballot((U0 & sel) != neg);
+}
 
-  // ---- clauses: acc &= mconst | V(lane) | P(i) | Q(U0), one v_bitop3 per
-  // word.  Branch-free, so acc stays in place across iterations.
-  code_ptr w = code;
-  if (COF) {
-    for (uint32_t k = 0; k < ncl; ++k, w += FBG_INS_WORDS) {
-      const u32x8 ins = *(const __attribute__((address_space(4))) u32x8 *)w;
-      const uint64_t sel = (uint64_t)ins[4] | ((uint64_t)ins[5] << 32);
-      const uint64_t neg = (uint64_t)ins[6] | ((uint64_t)ins[7] << 32);
-      if ((U0 & sel) != neg) continue;  // a true tile literal: the clause holds on the tile
-      const uint64_t lm = (uint64_t)ins[2] | ((uint64_t)ins[3] << 32);
-      const uint32_t poff = ins[0] >> FBG_ARG_SHIFT;  // entry 0 is the all-zero pattern
-      if (lm == 0 && ins[1] == 0u && poff == 0u) {    // only false tile literals: the tile is dead
+// Top bits of the runs (keys) of a chunk that meet U (fbg_isa.h).
+__device__ __forceinline__ uint32_t runs_false(uint32_t U, uint32_t T, uint32_t F) {
+  return (((U & ~T) + F) | U) & T;
+}
+
+// G & (m | ~x): v_bitop3 over (G = 0xF0, m = 0xCC, x = 0xAA).
+constexpr uint32_t kTT_KEY = 0xF0u & (0xCCu | (~0xAAu & 0xFFu));
+// m | ~x over (m = 0xF0, x = 0xCC).
+constexpr uint32_t kTT_ORNOT = (0xF0u | (~0xCCu & 0xFFu)) & 0xFFu;
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The clause block (fbg_isa.h): the per-lane products G_g of the static
+// groups chunk by chunk, acc from them by a product tree, then the multi
+// keys.  Returns false when the uniform-cofactor variant finds a clause made
+// only of tile literals false on the tile (acc = 0 on the whole tile).
+template <int LOG2W, bool COF>
+__device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, const code_ptr table, uint64_t U0,
+                                            uint32_t lane, uint32_t (&acc)[1 << LOG2W]) {
+  constexpr int W = 1 << LOG2W;
+  constexpr int NG = 1 + 2 * LOG2W;
+  const code_ptr cb = (code_ptr)cb_g;
+  const uint32_t nstat = cb[1], nmulti = cb[2];
+  uint32_t G[NG];
 #pragma unroll
-        for (int i = 0; i < W; i++) acc[i] = 0u;
-        return;
+  for (int g = 0; g < NG; g++) G[g] = ~0u;
+  const uint32_t *ch = cb_g + FBG_CB_HDR;
+  for (uint32_t k = 0; k < nstat; ++k) {
+    const code_ptr h = (code_ptr)ch;
+    const u32x8 hd = *(const __attribute__((address_space(4))) u32x8 *)h;
+    const uint32_t nc = hd[0];
+    const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
+    const uint32_t S = chunk_tile_bits(ch, nc, U0, lane);
+    if (COF && k == 0 && (S & hd[5]) != hd[5]) {
+#pragma unroll
+      for (int i = 0; i < W; i++) acc[i] = 0u;
+      return false;
+    }
+    const uint32_t A = runs_false(~(lb | S), hd[6], hd[7]);
+    code_ptr key = h + FBG_CB_CHUNK_HDR + 64 + 4 * nc;
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+      const uint32_t cnt = (hd[2 + g / 4] >> (8 * (g % 4))) & 0xFFu;
+      for (uint32_t j = 0; j < cnt; ++j, key += 2) {
+        const u32x2 km = *(const __attribute__((address_space(4))) u32x2 *)key;
+        const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)A, km[0], 1u);
+        G[g] = __builtin_amdgcn_bitop3_b32(G[g], km[1], x, kTT_KEY);
       }
-      const uint32_t T = __builtin_amdgcn_inverse_ballot_w64(lm) ? ~0u : ins[1];
-      const code_ptr P = table + poff;
+    }
+    ch += hd[1];
+  }
+  // acc[i] = G_0 & AND_j G_{1 + 2j + bit j of i}, level by level
+  acc[0] = G[0];
+#pragma unroll
+  for (int j = 0; j < LOG2W; j++)
+#pragma unroll
+    for (int v = 0; v < (1 << j); v++) {
+      acc[v | (1 << j)] = acc[v] & G[2 + 2 * j];
+      acc[v] = acc[v] & G[1 + 2 * j];
+    }
+  for (uint32_t k = 0; k < nmulti; ++k) {
+    const code_ptr h = (code_ptr)ch;
+    const u32x8 hd = *(const __attribute__((address_space(4))) u32x8 *)h;
+    const uint32_t nc = hd[0];
+    const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
+    const uint32_t A = runs_false(~(lb | chunk_tile_bits(ch, nc, U0, lane)), hd[6], hd[7]);
+    code_ptr key = h + FBG_CB_CHUNK_HDR + 64 + 4 * nc;
+    for (uint32_t j = 0; j < hd[2]; ++j, key += 4) {
+      const u32x4 kq = *(const __attribute__((address_space(4))) u32x4 *)key;
+      const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)A, kq[0], 1u);
+      const uint32_t T = __builtin_amdgcn_bitop3_b32(kq[1], x, 0u, kTT_ORNOT);
+      const code_ptr P = table + kq[2];
 #pragma unroll
       for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
     }
-  } else if (LOG2W <= 4 && ncl > 0) {
-    // Software-pipelined: while clause k runs on the VALU, the scalar unit
-    // already fetches clause k+1 and its pattern entry (whose index clause k
-    // carries in w0 bits 8..15), so neither load latency is exposed.  Reads
-    // one instruction past the clauses, which stays inside the program.
-    u32x8 a = *(const __attribute__((address_space(4))) u32x8 *)w;
-    uint32_t pa[W], pb[W];
-    u32x8 b;
-    {
-      const code_ptr P = table + (a[0] >> FBG_ARG_SHIFT);
-#pragma unroll
-      for (int i = 0; i < W; i++) pa[i] = P[i];
-    }
-    // one clause with (cur, pcur) while (nxt, pnxt) is fetched; the two
-    // halves of the loop swap the roles, so no register is ever copied
-    auto step = [&](const u32x8 &cur, const uint32_t (&pcur)[W], u32x8 &nxt, uint32_t (&pnxt)[W]) {
-      const uint64_t lm = (uint64_t)cur[2] | ((uint64_t)cur[3] << 32);
-      const uint64_t sel = (uint64_t)cur[4] | ((uint64_t)cur[5] << 32);
-      const uint64_t neg = (uint64_t)cur[6] | ((uint64_t)cur[7] << 32);
-      const uint64_t lmq = lm | (((U0 & sel) != neg) ? ~0ull : 0ull);
-      const uint32_t mconst = cur[1];
-      const code_ptr Pn = table + ((cur[0] >> FBG_F_SHIFT) & 0xFFu) * (uint32_t)W;
-      // keep the prefetch below the (waited) uses of the current clause
-      __builtin_amdgcn_sched_barrier(0);
-      w += FBG_INS_WORDS;
-      nxt = *(const __attribute__((address_space(4))) u32x8 *)w;
-#pragma unroll
-      for (int i = 0; i < W; i++) pnxt[i] = Pn[i];
-      const uint32_t T = __builtin_amdgcn_inverse_ballot_w64(lmq) ? ~0u : mconst;
-#pragma unroll
-      for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], pcur[i], kTT_AND_OR);
-    };
-    uint32_t k = 0;
-    for (;;) {
-      step(a, pa, b, pb);
-      if (++k >= ncl) break;
-      step(b, pb, a, pa);
-      if (++k >= ncl) break;
-    }
-  } else {
-  for (uint32_t k = 0; k < ncl; ++k, w += FBG_INS_WORDS) {
-    // the whole instruction in one s_load_dwordx8
-    const u32x8 ins = *(const __attribute__((address_space(4))) u32x8 *)w;
-    const uint32_t w0 = ins[0];
-    const uint64_t lm = (uint64_t)ins[2] | ((uint64_t)ins[3] << 32);
-    const uint64_t sel = (uint64_t)ins[4] | ((uint64_t)ins[5] << 32);
-    const uint64_t neg = (uint64_t)ins[6] | ((uint64_t)ins[7] << 32);
-    // a true tile literal makes the clause all-ones on every lane: fold it
-    // into the 64-bit lane mask (scalar logic), then one v_cndmask gives
-    // T = V(lane) | Q ? all-ones : mconst
-    const uint64_t lmq = lm | (((U0 & sel) != neg) ? ~0ull : 0ull);
-    const uint32_t T = __builtin_amdgcn_inverse_ballot_w64(lmq) ? ~0u : ins[1];
-    const code_ptr P = table + (w0 >> FBG_ARG_SHIFT);
-#pragma unroll
-    for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
+    ch += hd[1];
   }
-  }
+  return true;
+}
+
+// Interpret one program over the W words of this lane in tile group U0: the
+// clause block, then (GEN) the instructions after it.
+//
+// COF = true is the uniform-cofactor variant: the tile bits of the index are
+// constants on the whole tile, so a clause whose only literals are false tile
+// literals is false on the whole tile, which ends the tile (acc = 0; the
+// instructions after the block only clear bits of acc).  The result is the
+// same; the work depends on the data.
+template <int LOG2W, bool GEN, bool COF>
+__device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g, uint32_t nins, uint64_t U0,
+                                            uint32_t lane, uint32_t (&acc)[1 << LOG2W],
+                                            uint32_t *__restrict__ regs) {
+  const code_ptr cb = (code_ptr)code_g;
+  const code_ptr ins = cb + cb[0];
+  const code_ptr table = ins + (size_t)nins * FBG_INS_WORDS;
+  if (!run_clauses<LOG2W, COF>(code_g, table, U0, lane, acc)) return;
   if (!GEN) return;
-  run_general<LOG2W>(code, table, w, ncl, nins, U0, lane, acc, regs);
+  run_general<LOG2W>(ins, table, nins, U0, lane, acc, regs);
 }
 
 // Zero the words of this lane that lie beyond the valuation space.
@@ -318,31 +328,48 @@ __device__ __forceinline__ void mask_tail(uint32_t (&acc)[1 << LOG2W], uint64_t 
                                           uint64_t nslices, int n) {
   constexpr int W = 1 << LOG2W;
   if ((U0 + W) * 64 > nslices) {  // wave-uniform
+    // valid words of the tile, at most 64 W: 32-bit compares per word
+    const uint64_t base = U0 * 64;
+    const uint32_t rem = (uint32_t)min(nslices > base ? nslices - base : 0ull, (unsigned long long)W * 64);
 #pragma unroll
-    for (int i = 0; i < W; i++) {
-      const uint64_t s = (U0 + i) * 64 + lane;
-      if (s >= nslices) acc[i] = 0u;
-    }
+    for (int i = 0; i < W; i++)
+      if ((int)lane >= (int)rem - 64 * i) acc[i] = 0u;
     if (n < FBG_SLICE_BITS) acc[0] &= (uint32_t)((1ull << (1u << n)) - 1u);
   }
 }
 
+// Wave sums.  ds_swizzle exchanges within each half of the wave with the
+// lane pattern in the instruction (no address registers to keep live across
+// the tile loop); the two halves meet through v_readlane.  The result is
+// wave-uniform.
+template <int XOR>
+__device__ __forceinline__ uint32_t swz_xor(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (XOR << 10));
+}
+
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += swz_xor<16>(v);
+  v += swz_xor<8>(v);
+  v += swz_xor<4>(v);
+  v += swz_xor<2>(v);
+  v += swz_xor<1>(v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
-    const uint64_t t = ((uint64_t)hi << 32 | lo) + ((uint64_t)ohi << 32 | olo);
-    lo = (uint32_t)t;
-    hi = (uint32_t)(t >> 32);
+#define FBG_SUM_STEP(x)                                                   \
+  {                                                                       \
+    const uint64_t t = ((uint64_t)hi << 32 | lo) +                        \
+                       ((uint64_t)swz_xor<x>(hi) << 32 | swz_xor<x>(lo)); \
+    lo = (uint32_t)t;                                                     \
+    hi = (uint32_t)(t >> 32);                                             \
   }
-  return (uint64_t)hi << 32 | lo;
+  FBG_SUM_STEP(16) FBG_SUM_STEP(8) FBG_SUM_STEP(4) FBG_SUM_STEP(2) FBG_SUM_STEP(1)
+#undef FBG_SUM_STEP
+  const uint64_t a = (uint64_t)__builtin_amdgcn_readlane(hi, 0) << 32 | __builtin_amdgcn_readlane(lo, 0);
+  const uint64_t b = (uint64_t)__builtin_amdgcn_readlane(hi, 32) << 32 | __builtin_amdgcn_readlane(lo, 32);
+  return a + b;
 }
 
 // Inclusive prefix sum over the 64 lanes.
@@ -388,6 +415,41 @@ __device__ __forceinline__ void tile_compact(const uint32_t (&acc)[1 << LOG2W], 
   }
 }
 
+// DNF write-out and count of one tile: the words past the valuation space
+// are cleared (only the single tile of a program smaller than one tile has
+// any), the words inside the output stored, and the models of this lane
+// counted.  A whole tile's stores are issued unconditionally (streaming: the
+// vector is not read back by this kernel).
+template <int LOG2W>
+__device__ __forceinline__ uint32_t store_count_tile(const uint32_t (&acc)[1 << LOG2W], uint64_t U0, uint32_t lane,
+                                                     uint64_t nslices, int n, uint32_t *out32, uint64_t out_slices) {
+  constexpr int W = 1 << LOG2W;
+  uint32_t *dst = out32 + U0 * 64 + lane;
+  uint32_t c = 0;
+  if ((U0 + W) * 64 <= nslices) {  // wave-uniform; out_slices >= nslices
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+      __builtin_nontemporal_store(acc[i], dst + i * 64);
+      c += __popc(acc[i]);
+    }
+  } else {
+    const uint64_t base = U0 * 64;
+    const uint32_t rem = (uint32_t)min(nslices > base ? nslices - base : 0ull, (unsigned long long)W * 64);
+    const uint32_t rem_out = (uint32_t)min(out_slices > base ? out_slices - base : 0ull, (unsigned long long)W * 64);
+    const uint32_t m0 = n < FBG_SLICE_BITS ? (uint32_t)((1ull << (1u << n)) - 1u) : ~0u;
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+      // word (i, lane) of the tile is valid when lane < rem - 64 i (a
+      // wave-uniform bound: no per-word lane constants)
+      uint32_t v = (int)lane < (int)rem - 64 * i ? acc[i] : 0u;
+      if (i == 0) v &= m0;
+      if ((int)lane < (int)rem_out - 64 * i) dst[i * 64] = v;
+      c += __popc(v);
+    }
+  }
+  return c;
+}
+
 // Store the W words of this lane; the stores of a whole tile are issued
 // unconditionally (streaming: the vector is not read back by this kernel).
 template <int LOG2W>
@@ -406,12 +468,11 @@ __device__ __forceinline__ void store_tile(const uint32_t (&acc)[1 << LOG2W], ui
 }
 
 // Waves per SIMD each evaluator instance is compiled for (its VGPR budget),
-// as many as fit without spilling: the plain clause loop fits 8 (<= 64
-// VGPRs); the uniform-cofactor loop 6 at W = 16 and 4 at W = 32; the general
-// interpreter 6 at W <= 8 and is left unconstrained above.
+// as many as fit without spilling: programs made of clauses alone fit 8
+// (<= 64 VGPRs); the general interpreter 6 at W <= 8 and is left
+// unconstrained above.
 constexpr int min_waves(int log2w, int var) {
-  return (var & 1) ? (log2w <= 3 ? 6 : (log2w == 4 ? 2 : 1))
-                   : ((var & 2) ? (log2w == 5 ? 4 : (log2w == 4 ? 6 : 8)) : 8);
+  return (var & 1) ? (log2w <= 3 ? 6 : (log2w == 4 ? 2 : 1)) : ((var & 2) && log2w == 5 ? 7 : 8);
 }
 
 template <int LOG2W, int MODE, int VAR>
@@ -431,7 +492,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
       if (a.tile_counts[t] == 0u) continue;  // no model in this tile
     }
     uint32_t acc[W];
-    run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(a.code, a.nins, a.ncl, U0, lane, acc, regs);
+    run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(a.code, a.nins, U0, lane, acc, regs);
     mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);
     if (MODE == MODE_COUNT) {
       uint32_t c = 0;
@@ -504,7 +565,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
   for (;;) {
     uint32_t item = 0;
     if (lane == 0) item = atomicAdd(a.head, 1u);
-    item = uni(__shfl(item, 0, 64));
+    item = __builtin_amdgcn_readfirstlane(item);  // lane 0 took the item
     if (item >= a.nitems) break;  // every wave leaves once the queue is drained
     const item_ptr it = (item_ptr)a.items + item;
     const uint64_t t0 = it->t0, t1 = it->t1;
@@ -514,12 +575,15 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
     for (uint64_t t = t0; t < t1; ++t) {
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
-      run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(p->code, p->nins, p->ncl, U0, lane, acc, regs);
-      mask_tail<LOG2W>(acc, U0, lane, p->nslices, p->n);
-      if (MODE == MODE_DNF) store_tile<LOG2W>(acc, U0, lane, p->out32, p->out_slices);
+      run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(p->code, p->nins, U0, lane, acc, regs);
       uint32_t c = 0;
+      if (MODE == MODE_DNF) {
+        c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
+      } else {
+        mask_tail<LOG2W>(acc, U0, lane, p->nslices, p->n);
 #pragma unroll
-      for (int i = 0; i < W; i++) c += __popc(acc[i]);
+        for (int i = 0; i < W; i++) c += __popc(acc[i]);
+      }
       total += c;
       if (MODE == MODE_DNF && p->tile_counts) {  // for a later batched enumeration
         const uint32_t tc = wave_sum_u32(c);

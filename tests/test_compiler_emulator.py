@@ -21,23 +21,40 @@ def check(text, n, wpl=WPL):
     want = oracle.dnf(text, n)
     want_count = int(sum(bin(int(w)).count("1") for w in want))
     p = fbg.Program(text, n)
+    for cof in (False, True):
+        for w in wpl:
+            p.set_tuning(w, cofactor=cof)
+            got, c = p.emulate(w)
+            assert np.array_equal(got, want), (w, cof, text[:200])
+            assert c == want_count
+    p.set_tuning(0)
     for w in wpl:
-        got, c = p.emulate(w)
-        assert np.array_equal(got, want), (w, text[:200])
-        assert c == want_count
-    assert_clause_prefix(p)
+        assert_clause_block(p, w)
     return p
 
 
-def assert_clause_prefix(p):
-    """The kernels run the CL instructions as a prefix loop: no CL may follow
-    another instruction, and the prefix length is n_clause_instr."""
-    ops = [line.split()[1] for line in p.disasm(1).splitlines()[1:]]
-    k = 0
-    while k < len(ops) and ops[k] == "CL":
-        k += 1
-    assert "CL" not in ops[k:], ops
-    assert k == p.info["n_clause_instr"]
+def instructions(listing):
+    """(pc, opcode) of the instruction lines of a listing."""
+    out = []
+    for line in listing.splitlines():
+        f = line.split()
+        if f and f[0].isdigit():
+            out.append((int(f[0]), f[1]))
+    return out
+
+
+def assert_clause_block(p, w):
+    """The leading clauses form the clause block: no clause is left in the
+    instruction stream, and the block holds at most n_clause_instr clauses
+    (always-true ones are dropped), each chunk at most 32."""
+    lst = p.disasm(w)
+    assert all(op != "CL" for _, op in instructions(lst))
+    head = [l for l in lst.splitlines() if l.startswith("; clause block:")][0]
+    ncl = int(head.split()[3])
+    assert ncl <= p.info["n_clause_instr"]
+    chunks = [int(l.split()[3].split("=")[1]) for l in lst.splitlines() if l.startswith("chunk ")]
+    assert sum(chunks) == ncl and all(1 <= c <= 32 for c in chunks)
+    assert p.info["n_instr"] == p.info["n_clause_instr"] + len(instructions(lst))
 
 
 @pytest.mark.parametrize("seed", range(60))
@@ -190,21 +207,38 @@ def test_autotune_cache_keys(tmp_path):
     assert autotune.Tuner(path=str(tmp_path / "t.json")).table[k]["words_per_lane"] == 8
 
 
-def test_tile_only_clauses_lead_the_prefix():
-    """At every tiling the clauses made only of tile variables come first (the
-    uniform-cofactor kernel can then drop a dead tile early); the emulated
-    result is unchanged."""
+def test_tile_only_clauses_lead_the_block():
+    """At every tiling the clauses made only of tile variables come first in
+    the first chunk, and its header marks exactly them (the uniform-cofactor
+    kernels then drop a dead tile before any other work)."""
     text, n = workloads.random_3cnf(32, 136, 4)
+    clauses = set()
+    for part in text.splitlines():
+        lits = frozenset(tok.strip() for tok in part.split("|"))
+        clauses.add(lits)
     p = fbg.Program(text, n)
     for w in WPL:
-        rows = p.disasm(w).splitlines()[1:]
-        kinds = []
-        for r in rows:
-            f = dict(x.split("=") for x in r.split()[2:] if "=" in x)
-            kinds.append(int(f["mconst"], 16) == 0 and int(f["lane"], 16) == 0 and int(f["pat"], 16) == 0)
-        k = kinds.index(False) if False in kinds else len(kinds)
-        assert k > 0 and not any(kinds[k:]), w
+        tile_bit = 11 + w.bit_length() - 1
+        want = sum(all(int(l.lstrip("~")[1:]) >= tile_bit for l in c) for c in clauses)
+        first = [l for l in p.disasm(w).splitlines() if l.startswith("chunk 0 ")][0]
+        mask = int(first.split("tile_only=")[1].split()[0], 16)
+        k = bin(mask).count("1")
+        assert mask == (1 << k) - 1 and k == min(want, 32), (w, want, mask)
     check("(x0|x1) & (x22|~x23) & (x2|x12) & ~x21 & (x18|x20)", 24, wpl=[1, 32])
+
+
+def test_clause_groups_by_word_literals():
+    """Keys of the static chunks fall in groups 0 .. 2 log2 W by their word
+    literals; clauses with two word literals go to multi chunks."""
+    # W = 4: word bits are x11 (j = 0) and x12 (j = 1)
+    text = "(x0 | x1) & (x11 | x2) & (~x11 | x3) & (x12 | x5) & (~x12 | x6) & (x11 | x12 | x7) & (x40 | ~x41)"
+    p = fbg.Program(text, 42)
+    lst = p.disasm(4)
+    groups = sorted(int(l.split("group=")[1].split()[0]) for l in lst.splitlines() if "key group=" in l)
+    assert groups == [0, 0, 1, 2, 3, 4]
+    assert sum(1 for l in lst.splitlines() if "key multi" in l) == 1
+    small = text.replace("x40", "x9").replace("x41", "x10")
+    check(small, 14, wpl=[1, 2, 4, 8])
 
 
 @pytest.mark.parametrize("k", [3, 5, 9, 17])
