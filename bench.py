@@ -17,10 +17,11 @@ programs resident on the device:
                   vectors only in tiles holding models
 
 value = 16 * 2^32 valuations per step / step time.  The JSON line also
-carries the roofline of the dominant kernel (the evaluator: integer VALU
-bitwise work, measured with HIP events on the launch stream), the batched
-versus per-formula ("plain") count rates, and the CPU oracle timed on a
-bounded sample on this host.
+carries the roofline of the dominant kernel (the batched evaluator, measured
+with HIP events on the launch stream: bound by the HBM write of the DNF
+vectors, 1/8 byte per valuation; its integer VALU work is reported beside as
+the algorithmic bit-op rate), the batched versus per-formula ("plain") count
+rates, and the CPU oracle timed on a bounded sample on this host.
 
 Workload c3: 4096 random DAG formulas (n in [10,30], 50..2000 ops), counts
 only, one batched launch per step, compared with 4096 plain launches.
@@ -63,10 +64,10 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
 # the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
-# half the bytes copied, WRITE_SIZE all of them): 2 x 2611.8 KiB fetched and
-# 8395435.3 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
+# half the bytes copied, WRITE_SIZE all of them): 2 x 2839.3 KiB fetched and
+# 8400486.3 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
 # None whenever that kernel has changed since the counters were taken.
-C1_TRAFFIC = (2 * 2611.8 + 8395435.3) * 1024
+C1_TRAFFIC = (2 * 2839.3 + 8400486.3) * 1024
 
 
 class ProgramCache:
@@ -232,6 +233,7 @@ def bench_c1(args, torch, fbg):
     cbatch.free()
 
     vals = len(progs) * float(1 << n)
+    dnf_bytes = vals / 8  # the DNF vectors, 1/8 byte per valuation
     l2in = sum(p.info["l2in"] for p in progs)
     achieved = l2in * float(1 << n) / (k_ms / 1e3)
     res = {
@@ -246,11 +248,13 @@ def bench_c1(args, torch, fbg):
                                "models from the DNF vectors",
                    "n": n, "clauses": 136, "instances": len(progs),
                    "words_per_lane": progs[0].info["words_per_lane"]},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_BITWISE_PEAK / 1e12,
-                     "unit": "Tbitop/s", "frac": achieved / VALU_BITWISE_PEAK, "traffic": C1_TRAFFIC,
+        "roofline": {"bound": "hbm", "achieved": dnf_bytes / (k_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": dnf_bytes / (k_ms / 1e3) / HBM_PEAK, "traffic": C1_TRAFFIC,
                      "kernel": "k_batch MODE_DNF (16 programs: evaluation, DNF write-out, counts)",
-                     "avg_ms": k_ms, "algorithmic_ops_per_launch": l2in * float(1 << n),
-                     "dnf_bytes_per_launch": len(progs) * float(1 << n) / 8},
+                     "avg_ms": k_ms, "algorithmic_bytes_per_launch": dnf_bytes,
+                     "algorithmic_bitops_per_launch": l2in * float(1 << n),
+                     "algorithmic_bitop_rate_T": achieved / 1e12,
+                     "valu_bitwise_peak_T": VALU_BITWISE_PEAK / 1e12},
         "batched_vs_plain": {"batched_count_ms": batch_ms, "plain_count_ms": plain_ms,
                              "batched_valuations_per_s": vals / (batch_ms / 1e3),
                              "plain_valuations_per_s": vals / (plain_ms / 1e3),
