@@ -862,6 +862,8 @@ struct BlockClause {
   SetWords s;
   int group;
   bool tile_only;  // only tile literals (or none at all)
+  int top = 0;     // multi: highest word bit j of its word literals
+  int top_v = 0;   // multi: the value of bit j on which that literal is false
 };
 
 int pattern_entry(std::vector<uint32_t> &pats, uint32_t pat) {
@@ -873,9 +875,10 @@ int pattern_entry(std::vector<uint32_t> &pats, uint32_t pat) {
 
 // One chunk of at most FBG_CB_CHUNK clauses; see fbg_isa.h for the layout.
 // The clauses arrive sorted so that each key is a run of consecutive
-// clauses: one group and in-word part (static), one pattern and in-word part
-// (multi).
-void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, bool multi, int log2w,
+// clauses: one group and in-word part (static), one level, half, pattern and
+// in-word part (multi).  kind: 0 static, 1 the first multi chunk (its keys
+// act inside the product tree), 2 a later multi chunk (after the tree).
+void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, int kind, int log2w,
                 std::vector<uint32_t> &pats, bool first, std::vector<uint32_t> &out) {
   const uint32_t nc = (uint32_t)(hi - lo);
   const int W = 1 << log2w;
@@ -903,11 +906,18 @@ void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, bool m
   auto same = [&](uint32_t a, uint32_t b) {
     const BlockClause &x = cl[lo + a], &y = cl[lo + b];
     if (x.s.mconst != y.s.mconst || x.tile_only != y.tile_only) return false;
-    return multi ? x.s.pat == y.s.pat : x.group == y.group;
+    if (kind == 0) return x.group == y.group;
+    return x.s.pat == y.s.pat && x.top == y.top && x.top_v == y.top_v;
   };
+  // slot of a key: its group (static), its (level, half) (tree), or 0 (late)
+  auto slot = [&](const BlockClause &x) {
+    return kind == 0 ? x.group : kind == 1 ? 2 * (x.top - 1) + x.top_v : 0;
+  };
+  const int nslots = kind == 0 ? 1 + 2 * log2w : kind == 1 ? 2 * (log2w - 1) : 1;
+  const uint32_t kw = kind == 0 ? 2u : 4u;  // words per key
   uint32_t T = 0, F = 0;
   std::vector<uint32_t> keys;
-  uint32_t counts[1 + 2 * 5] = {0};
+  std::vector<uint32_t> counts((size_t)std::max(nslots, 1), 0u);
   for (uint32_t a = 0; a < nc;) {
     uint32_t b = a + 1;
     while (b < nc && same(a, b)) b++;
@@ -916,23 +926,32 @@ void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, bool m
     const BlockClause &x = cl[lo + a];
     keys.push_back(b - 1);
     keys.push_back(x.s.mconst);
-    if (multi) {
-      keys.push_back((uint32_t)(pattern_entry(pats, x.s.pat) * W));
+    if (kind != 0) {
+      uint32_t pat = x.s.pat;
+      if (kind == 1) {
+        // the node pattern of level top + 1 in the half top_v: node v < 2^top
+        // stands for the words whose low top + 1 bits are v | top_v << top
+        const uint32_t half = 1u << x.top;
+        pat = ~0u;
+        for (uint32_t v = 0; v < half; v++)
+          if (!((x.s.pat >> (v | ((uint32_t)x.top_v << x.top))) & 1u)) pat &= ~(1u << v);
+      }
+      keys.push_back((uint32_t)(pattern_entry(pats, pat) * W));
       keys.push_back(0u);
-    } else {
-      counts[x.group]++;
     }
+    counts[(size_t)slot(x)]++;
     a = b;
   }
   out.insert(out.end(), keys.begin(), keys.end());
-  if (multi) {
-    out[base + 2] = (uint32_t)(keys.size() / 4);
-  } else {
-    for (int g = 0; g < 1 + 2 * log2w; g++) out[base + 2 + g / 4] |= counts[g] << (8 * (g % 4));
-    if (first) out[base + 5] = tmask;
+  out[base + 2] = T;
+  out[base + 3] = F;
+  if (kind == 0 && first) out[base + 4] = tmask;
+  // end of each slot's keys, in bytes from the chunk start
+  uint32_t end = (uint32_t)(FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4u;
+  for (int sl = 0; sl < nslots; sl++) {
+    end += counts[(size_t)sl] * kw * 4u;
+    out[base + 5 + sl] = end;
   }
-  out[base + 6] = T;
-  out[base + 7] = F;
   while ((out.size() - base) % 4) out.push_back(0u);
   out[base + 1] = (uint32_t)(out.size() - base);
 }
@@ -960,7 +979,15 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
     const std::array<uint64_t, 4> id{(uint64_t)b.s.mconst << 32 | b.s.pat, b.s.lanemask, b.s.sel, b.s.neg};
     if (!seen.insert(id).second) continue;
     b.tile_only = true;
-    for (const Lit &l : c.code[k].ls.lits) b.tile_only = b.tile_only && l.k >= tile_bit;
+    b.top = -1;
+    for (const Lit &l : c.code[k].ls.lits) {
+      b.tile_only = b.tile_only && l.k >= tile_bit;
+      const int j = l.k - FBG_TILE_BASE_BIT;
+      if (j >= 0 && j < log2w && j > b.top) {
+        b.top = j;
+        b.top_v = l.neg ? 1 : 0;  // x is false where the bit is 0, ~x where it is 1
+      }
+    }
     (b.group == kMulti ? multi : stat).push_back(b);
   }
   // clauses made only of tile literals first (the uniform-cofactor kernel
@@ -971,16 +998,20 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
     if (a.group != b.group) return a.group < b.group;
     return a.s.mconst < b.s.mconst;
   });
+  // multi clauses by (level, half) so that the first chunk's keys come in
+  // the order the product tree meets them, then by pattern and in-word part
   std::stable_sort(multi.begin(), multi.end(), [](const BlockClause &a, const BlockClause &b) {
+    if (a.top != b.top) return a.top < b.top;
+    if (a.top_v != b.top_v) return a.top_v < b.top_v;
     if (a.s.pat != b.s.pat) return a.s.pat < b.s.pat;
     return a.s.mconst < b.s.mconst;
   });
   std::vector<uint32_t> block(FBG_CB_HDR, 0u);
   uint32_t nstat = 0, nmulti = 0;
   for (size_t lo = 0; lo < stat.size(); lo += FBG_CB_CHUNK, nstat++)
-    emit_chunk(stat, lo, std::min(stat.size(), lo + FBG_CB_CHUNK), false, log2w, pats, lo == 0, block);
+    emit_chunk(stat, lo, std::min(stat.size(), lo + FBG_CB_CHUNK), 0, log2w, pats, lo == 0, block);
   for (size_t lo = 0; lo < multi.size(); lo += FBG_CB_CHUNK, nmulti++)
-    emit_chunk(multi, lo, std::min(multi.size(), lo + FBG_CB_CHUNK), true, log2w, pats, false, block);
+    emit_chunk(multi, lo, std::min(multi.size(), lo + FBG_CB_CHUNK), lo == 0 ? 1 : 2, log2w, pats, false, block);
   block[0] = (uint32_t)block.size();
   block[1] = nstat;
   block[2] = nmulti;
@@ -1055,10 +1086,11 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
   out += buf;
   const uint32_t *ch = cb + FBG_CB_HDR;
   for (uint32_t k = 0; k < cb[1] + cb[2]; k++) {
-    const bool multi = k >= cb[1];
+    const int kind = k < cb[1] ? 0 : k == cb[1] ? 1 : 2;
+    static const char *kinds[] = {"static", "multi-tree", "multi"};
     const uint32_t nc = ch[0];
-    snprintf(buf, sizeof buf, "chunk %u %s clauses=%u tile_only=%08x tops=%08x fill=%08x\n", k,
-             multi ? "multi" : "static", nc, multi ? 0u : ch[5], ch[6], ch[7]);
+    snprintf(buf, sizeof buf, "chunk %u %s clauses=%u tile_only=%08x tops=%08x fill=%08x\n", k, kinds[kind], nc,
+             kind == 0 ? ch[4] : 0u, ch[2], ch[3]);
     out += buf;
     const uint32_t *td = ch + FBG_CB_CHUNK_HDR + 64;
     for (uint32_t c = 0; c < nc; c++) {
@@ -1069,21 +1101,25 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
                td[4 * c + 1], td[4 * c], td[4 * c + 3], td[4 * c + 2]);
       out += buf;
     }
-    const uint32_t *key = td + 4 * nc;
-    if (!multi) {
-      for (int g = 0; g < 1 + 2 * log2w; g++) {
-        const uint32_t cnt = (ch[2 + g / 4] >> (8 * (g % 4))) & 0xFFu;
-        for (uint32_t j = 0; j < cnt; j++, key += 2) {
-          snprintf(buf, sizeof buf, "  key group=%d top=%u mconst=%08x\n", g, key[0], key[1]);
-          out += buf;
+    uint32_t off = (uint32_t)(FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4u;
+    const int nslots = kind == 0 ? 1 + 2 * log2w : kind == 1 ? 2 * (log2w - 1) : 1;
+    for (int sl = 0; sl < nslots; sl++) {
+      for (; off < ch[5 + sl]; off += kind == 0 ? 8u : 16u) {
+        const uint32_t *key = ch + off / 4;
+        if (kind == 0) {
+          snprintf(buf, sizeof buf, "  key group=%d top=%u mconst=%08x\n", sl, key[0], key[1]);
+        } else {
+          const int j = kind == 1 ? 1 + sl / 2 : log2w;
+          const int n = kind == 1 ? 1 << j : W;
+          uint32_t pat = 0;
+          for (int v = 0; v < n; v++)
+            if (table[key[2] + v]) pat |= 1u << v;
+          if (kind == 1)
+            snprintf(buf, sizeof buf, "  key multi level=%d half=%d top=%u mconst=%08x nodes=%08x\n", j, sl % 2,
+                     key[0], key[1], pat);
+          else
+            snprintf(buf, sizeof buf, "  key multi top=%u mconst=%08x pat=%08x\n", key[0], key[1], pat);
         }
-      }
-    } else {
-      for (uint32_t j = 0; j < ch[2]; j++, key += 4) {
-        uint32_t pat = 0;
-        for (int i = 0; i < W; i++)
-          if (table[key[2] + i]) pat |= 1u << i;
-        snprintf(buf, sizeof buf, "  key multi top=%u mconst=%08x pat=%08x\n", key[0], key[1], pat);
         out += buf;
       }
     }
@@ -1150,13 +1186,9 @@ uint32_t clause_block_value(const uint32_t *cb, const uint32_t *table, int log2w
   uint32_t G[1 + 2 * 5];
   for (uint32_t &g : G) g = ~0u;
   const uint32_t *ch = cb + FBG_CB_HDR;
-  uint32_t acc = 0;
+  uint32_t extra = ~0u;  // the multi keys' factors of word i
   for (uint32_t k = 0; k < cb[1] + cb[2]; k++) {
-    const bool multi = k >= cb[1];
-    if (k == cb[1]) {
-      acc = G[0];
-      for (int j = 0; j < log2w; j++) acc &= G[1 + 2 * j + ((i >> j) & 1u)];
-    }
+    const int kind = k < cb[1] ? 0 : k == cb[1] ? 1 : 2;
     const uint32_t nc = ch[0];
     const uint32_t *td = ch + FBG_CB_CHUNK_HDR + 64;
     uint32_t S = 0;
@@ -1165,33 +1197,36 @@ uint32_t clause_block_value(const uint32_t *cb, const uint32_t *table, int log2w
       const uint64_t neg = (uint64_t)td[4 * c + 2] | ((uint64_t)td[4 * c + 3] << 32);
       if ((U0 & sel) != neg) S |= 1u << c;
     }
-    if (cof && k == 0 && !multi && (S & ch[5]) != ch[5]) return 0u;
+    if (cof && k == 0 && (S & ch[4]) != ch[4]) return 0u;
     const uint32_t U = ~(ch[FBG_CB_CHUNK_HDR + lane] | S);
     // the clauses of a key are the run of bits ending at its top bit, after
     // the previous key's top bit
-    const uint32_t *key = td + 4 * nc;
     auto run_false = [&](uint32_t top) {
       uint32_t lo = top;
-      while (lo > 0 && !((ch[6] >> (lo - 1)) & 1u)) lo--;
+      while (lo > 0 && !((ch[2] >> (lo - 1)) & 1u)) lo--;
       const uint32_t run = (uint32_t)(((2ull << top) - 1) & ~((1ull << lo) - 1));
       return (U & run) != 0;
     };
-    if (!multi) {
-      for (int g = 0; g < 1 + 2 * log2w; g++) {
-        const uint32_t cnt = (ch[2 + g / 4] >> (8 * (g % 4))) & 0xFFu;
-        for (uint32_t j = 0; j < cnt; j++, key += 2)
-          if (run_false(key[0])) G[g] &= key[1];
+    uint32_t off = (uint32_t)(FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4u;  // bytes
+    const int nslots = kind == 0 ? 1 + 2 * log2w : kind == 1 ? 2 * (log2w - 1) : 1;
+    for (int sl = 0; sl < nslots; sl++) {
+      for (; off < ch[5 + sl]; off += kind == 0 ? 8u : 16u) {
+        const uint32_t *key = ch + off / 4;
+        if (!run_false(key[0])) continue;
+        if (kind == 0) {
+          G[sl] &= key[1];
+        } else if (kind == 1) {
+          const int j = 1 + sl / 2;  // level j + 1, half bit j = sl % 2
+          if (((i >> j) & 1u) == (uint32_t)(sl % 2)) extra &= key[1] | table[key[2] + (i & ((1u << j) - 1u))];
+        } else {
+          extra &= key[1] | table[key[2] + i];
+        }
       }
-    } else {
-      for (uint32_t j = 0; j < ch[2]; j++, key += 4)
-        if (run_false(key[0])) acc &= key[1] | table[key[2] + i];
     }
     ch += ch[1];
   }
-  if (cb[2] == 0) {
-    acc = G[0];
-    for (int j = 0; j < log2w; j++) acc &= G[1 + 2 * j + ((i >> j) & 1u)];
-  }
+  uint32_t acc = G[0] & extra;
+  for (int j = 0; j < log2w; j++) acc &= G[1 + 2 * j + ((i >> j) & 1u)];
   return acc;
 }
 

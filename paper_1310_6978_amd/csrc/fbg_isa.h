@@ -40,8 +40,14 @@
  *   multi      two or more word literals: P(i) from the pattern table
  * With G_g the per-lane product of group g, the static groups give
  *   acc[i] = G_0 & AND_j G_{1 + 2j + (bit j of i)},
- * which the kernels build as a product tree (2W - 2 ANDs per tile); each
- * multi key then does acc[i] &= T | P(i).
+ * which the kernels build as a product tree, level by level (2W - 2 ANDs per
+ * tile): level j + 1 holds the 2^(j+1) products of the words' low j + 1
+ * bits.  A multi key whose highest word literal is on bit j (false where bit
+ * j is v) touches only the level-(j + 1) nodes of the half v, and within it
+ * the nodes its lower word literals leave false: it is applied there, 2^j
+ * operations instead of W, and the tree carries it to the words.  The keys of
+ * the first multi chunk act this way; later multi chunks (more than 32 such
+ * clauses) act on the W words after the tree.
  *
  * Chunks.  Clauses are packed FBG_CB_CHUNK to a chunk, static and multi
  * clauses in separate chunks.  A chunk stores per lane the bits Lb[l] (bit c:
@@ -61,16 +67,18 @@
  * Block layout (uint32 words):
  *   cb[0] size of the block in words (the instructions start there)
  *   cb[1] static chunks   cb[2] multi chunks   cb[3] clauses
- *   then the chunks, each:
+ *   then the chunks (static ones first), each:
  *     h[0] clauses nc (1 .. FBG_CB_CHUNK)   h[1] chunk size in words
- *     static: h[2..4] number of keys of groups 0 .. 2 log2 W, one byte each
- *             h[5]    first chunk only: the clauses made of tile literals
- *                     alone (the encoder puts them first)
- *     multi:  h[2]    number of keys
- *     h[6] T, h[7] F
+ *     h[2] T   h[3] F
+ *     h[4] first static chunk only: the clauses made of tile literals alone
+ *          (the encoder puts them first)
+ *     h[5 ..] end of each slot's keys, in bytes from the chunk start; slots
+ *          are the groups 0 .. 2 log2 W (static), the (level j, half v)
+ *          pairs 2 (j - 1) + v (first multi chunk), or one (later ones)
  *     Lb[64]; (sel lo, sel hi, neg lo, neg hi) x nc
- *     static keys (top bit, m) by group; multi keys (top bit, m, pattern
- *     offset, 0)
+ *     keys: static (top bit, m); multi (top bit, m, pattern offset, 0), the
+ *     pattern of the first multi chunk's keys over the 2^j nodes of their
+ *     half
  *     zero padding to a multiple of 4 words
  *
  * Instruction: 8 x uint32.
@@ -125,7 +133,7 @@
 #define FBG_INS_WORDS 8
 #define FBG_CB_HDR 4        /* words of the clause-block header */
 #define FBG_CB_CHUNK 32     /* clauses per chunk */
-#define FBG_CB_CHUNK_HDR 8  /* words of a chunk header */
+#define FBG_CB_CHUNK_HDR 16 /* words of a chunk header */
 #define FBG_LANE_BITS 6  /* 64 lanes per wave */
 #define FBG_SLICE_BITS 5 /* 32 valuations per word */
 #define FBG_TILE_BASE_BIT (FBG_SLICE_BITS + FBG_LANE_BITS) /* 11 */

@@ -234,10 +234,15 @@ constexpr uint32_t kTT_ORNOT = (0xF0u | (~0xCCu & 0xFFu)) & 0xFFu;
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+typedef const __attribute__((address_space(4))) char *code_bytes;
+
 // The clause block (fbg_isa.h): the per-lane products G_g of the static
-// groups chunk by chunk, acc from them by a product tree, then the multi
-// keys.  Returns false when the uniform-cofactor variant finds a clause made
-// only of tile literals false on the tile (acc = 0 on the whole tile).
+// groups chunk by chunk, acc from them by a product tree that also applies
+// the keys of the first multi chunk at their levels, then any later multi
+// chunk on the W words.  Returns false when the uniform-cofactor variant
+// finds a clause made only of tile literals false on the tile (acc = 0 on
+// the whole tile).
 template <int LOG2W, bool COF>
 __device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, const code_ptr table, uint64_t U0,
                                             uint32_t lane, uint32_t (&acc)[1 << LOG2W]) {
@@ -251,53 +256,84 @@ __device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, c
   const uint32_t *ch = cb_g + FBG_CB_HDR;
   for (uint32_t k = 0; k < nstat; ++k) {
     const code_ptr h = (code_ptr)ch;
-    const u32x8 hd = *(const __attribute__((address_space(4))) u32x8 *)h;
+    const u32x16 hd = *(const __attribute__((address_space(4))) u32x16 *)h;
     const uint32_t nc = hd[0];
     const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
     const uint32_t S = chunk_tile_bits(ch, nc, U0, lane);
-    if (COF && k == 0 && (S & hd[5]) != hd[5]) {
+    if (COF && k == 0 && (S & hd[4]) != hd[4]) {
 #pragma unroll
       for (int i = 0; i < W; i++) acc[i] = 0u;
       return false;
     }
-    const uint32_t A = runs_false(~(lb | S), hd[6], hd[7]);
-    code_ptr key = h + FBG_CB_CHUNK_HDR + 64 + 4 * nc;
+    const uint32_t A = runs_false(~(lb | S), hd[2], hd[3]);
+    // keys by group; hd[5 + g] is where group g's keys end (bytes)
+    const code_bytes hb = (code_bytes)h;
+    uint32_t off = (FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4;
 #pragma unroll
     for (int g = 0; g < NG; g++) {
-      const uint32_t cnt = (hd[2 + g / 4] >> (8 * (g % 4))) & 0xFFu;
-      for (uint32_t j = 0; j < cnt; ++j, key += 2) {
-        const u32x2 km = *(const __attribute__((address_space(4))) u32x2 *)key;
+      for (; off < hd[5 + g]; off += 8) {
+        const u32x2 km = *(const __attribute__((address_space(4))) u32x2 *)(hb + off);
         const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)A, km[0], 1u);
         G[g] = __builtin_amdgcn_bitop3_b32(G[g], km[1], x, kTT_KEY);
       }
     }
     ch += hd[1];
   }
-  // acc[i] = G_0 & AND_j G_{1 + 2j + bit j of i}, level by level
+  // the first multi chunk: its false runs now, its keys inside the tree
+  u32x16 mh = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t Am = 0, moff = 0;
+  const code_bytes mb = (code_bytes)ch;
+  if (nmulti) {
+    mh = *(const __attribute__((address_space(4))) u32x16 *)ch;
+    const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
+    Am = runs_false(~(lb | chunk_tile_bits(ch, mh[0], U0, lane)), mh[2], mh[3]);
+    moff = (FBG_CB_CHUNK_HDR + 64 + 4 * mh[0]) * 4;
+  }
+  // level j + 1 of the tree: the 2^(j+1) products of the words' low j + 1
+  // bits; a multi key of level j + 1 acts on the nodes of its half
   acc[0] = G[0];
 #pragma unroll
-  for (int j = 0; j < LOG2W; j++)
+  for (int j = 0; j < LOG2W; j++) {
 #pragma unroll
     for (int v = 0; v < (1 << j); v++) {
       acc[v | (1 << j)] = acc[v] & G[2 + 2 * j];
       acc[v] = acc[v] & G[1 + 2 * j];
     }
-  for (uint32_t k = 0; k < nmulti; ++k) {
-    const code_ptr h = (code_ptr)ch;
-    const u32x8 hd = *(const __attribute__((address_space(4))) u32x8 *)h;
-    const uint32_t nc = hd[0];
-    const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
-    const uint32_t A = runs_false(~(lb | chunk_tile_bits(ch, nc, U0, lane)), hd[6], hd[7]);
-    code_ptr key = h + FBG_CB_CHUNK_HDR + 64 + 4 * nc;
-    for (uint32_t j = 0; j < hd[2]; ++j, key += 4) {
-      const u32x4 kq = *(const __attribute__((address_space(4))) u32x4 *)key;
-      const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)A, kq[0], 1u);
-      const uint32_t T = __builtin_amdgcn_bitop3_b32(kq[1], x, 0u, kTT_ORNOT);
-      const code_ptr P = table + kq[2];
+    if (j >= 1) {
 #pragma unroll
-      for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
+      for (int half = 0; half < 2; half++) {
+        for (; moff < mh[5 + 2 * (j - 1) + half]; moff += 16) {
+          const u32x4 kq = *(const __attribute__((address_space(4))) u32x4 *)(mb + moff);
+          const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)Am, kq[0], 1u);
+          const uint32_t T = __builtin_amdgcn_bitop3_b32(kq[1], x, 0u, kTT_ORNOT);
+          const code_ptr P = table + kq[2];
+#pragma unroll
+          for (int v = 0; v < (1 << j); v++)
+            acc[(half << j) | v] = __builtin_amdgcn_bitop3_b32(T, acc[(half << j) | v], P[v], kTT_AND_OR);
+        }
+      }
     }
-    ch += hd[1];
+  }
+  // later multi chunks (more than 32 multi clauses): on the W words
+  if (nmulti > 1) {
+    ch += mh[1];
+    for (uint32_t k = 1; k < nmulti; ++k) {
+      const code_ptr h = (code_ptr)ch;
+      const u32x16 hd = *(const __attribute__((address_space(4))) u32x16 *)h;
+      const uint32_t nc = hd[0];
+      const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
+      const uint32_t A = runs_false(~(lb | chunk_tile_bits(ch, nc, U0, lane)), hd[2], hd[3]);
+      const code_bytes hb = (code_bytes)h;
+      for (uint32_t off = (FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4; off < hd[5]; off += 16) {
+        const u32x4 kq = *(const __attribute__((address_space(4))) u32x4 *)(hb + off);
+        const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)A, kq[0], 1u);
+        const uint32_t T = __builtin_amdgcn_bitop3_b32(kq[1], x, 0u, kTT_ORNOT);
+        const code_ptr P = table + kq[2];
+#pragma unroll
+        for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
+      }
+      ch += hd[1];
+    }
   }
   return true;
 }

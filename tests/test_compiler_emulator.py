@@ -241,6 +241,27 @@ def test_clause_groups_by_word_literals():
     check(small, 14, wpl=[1, 2, 4, 8])
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_multi_keys_inside_and_after_the_tree(seed):
+    """Clauses with two or more word-index literals (x11..x15 at 32 words per
+    lane): the first 32 act inside the product tree at their level and half,
+    the rest after it on the words.  Every level, half and pattern shape."""
+    rng = random.Random(4700 + seed)
+    n = 17
+    clauses = []
+    for _ in range(rng.choice([12, 40, 75])):
+        k = rng.choice([2, 3, 3, 4])
+        vs = rng.sample(range(11, 16), min(k, 5) - 1) + [rng.randrange(n)]
+        clauses.append("(" + " | ".join(("~" if rng.random() < 0.5 else "") + "x%d" % v for v in vs) + ")")
+    # a few static clauses as well
+    for _ in range(10):
+        vs = rng.sample(range(n), 3)
+        clauses.append("(" + " | ".join(("~" if rng.random() < 0.5 else "") + "x%d" % v for v in vs) + ")")
+    p = check(" & ".join(clauses), n, wpl=[4, 8, 16, 32])
+    lst = p.disasm(32)
+    assert "multi-tree" in lst
+
+
 @pytest.mark.parametrize("k", [3, 5, 9, 17])
 def test_registers_beyond_the_vgpr_set(k):
     # registers 0..3 live in VGPRs, the rest in LDS: programs on both sides
