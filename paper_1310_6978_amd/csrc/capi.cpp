@@ -648,7 +648,10 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       total_cost += (double)q.ntiles * (q.nins + 4);
       b->plan_of[(size_t)i] = (int)b->plans.size();
     }
-    // about four items per wave; never split below one tile
+    // about four items per wave; never split below one tile.  A program's
+    // K items interleave: item k takes tiles k, k + K, k + 2K, ..., so the
+    // waves working on neighbouring items at the same time write neighbouring
+    // tiles (DNF vectors), which keeps the HBM writes close together.
     const double target = std::max(1.0, total_cost / (double)(waves * 4));
     std::vector<fbg::BatchItem> items;
     std::vector<double> cost;
@@ -656,14 +659,16 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       const fbg::BatchProg &q = b->host_progs[(size_t)i];
       const double per_tile = q.nins + 4.0;
       const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
-      for (uint64_t t = 0; t < q.ntiles; t += chunk) {
+      const uint64_t K = (q.ntiles + chunk - 1) / chunk;
+      for (uint64_t k = 0; k < K; k++) {
         fbg::BatchItem it;
         it.prog = (uint32_t)i;
         it.slot = (uint32_t)i;
-        it.t0 = t;
-        it.t1 = std::min(q.ntiles, t + chunk);
+        it.t0 = k;
+        it.t1 = q.ntiles;
+        it.step = K;
         items.push_back(it);
-        cost.push_back((double)(it.t1 - it.t0) * per_tile);
+        cost.push_back((double)((q.ntiles - k + K - 1) / K) * per_tile);
       }
     }
     if (items.size() > 0xFFFFFFF0ull) {
@@ -1011,6 +1016,7 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
       q.slot = (uint32_t)items[k].slot;
       q.t0 = t;
       q.t1 = t + std::min(piece, items[k].tile_end - t);
+      q.step = 1;
     }
   }
   hipStream_t s = (hipStream_t)stream;

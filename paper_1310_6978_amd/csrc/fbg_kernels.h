@@ -62,7 +62,8 @@ struct BatchEnumArgs {
 struct BatchItem {
   uint32_t prog;    // index into the program table
   uint32_t slot;    // index into the counts array
-  uint64_t t0, t1;  // tile range [t0, t1)
+  uint64_t t0, t1;  // tiles t0, t0 + step, t0 + 2 step, ... below t1
+  uint64_t step;
 };
 
 struct BatchArgs {

@@ -389,7 +389,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   v += swz_xor<4>(v);
   v += swz_xor<2>(v);
   v += swz_xor<1>(v);
-  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
+  return (uint32_t)__builtin_amdgcn_readlane(v, 0) + (uint32_t)__builtin_amdgcn_readlane(v, 32);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
@@ -403,8 +403,11 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   }
   FBG_SUM_STEP(16) FBG_SUM_STEP(8) FBG_SUM_STEP(4) FBG_SUM_STEP(2) FBG_SUM_STEP(1)
 #undef FBG_SUM_STEP
-  const uint64_t a = (uint64_t)__builtin_amdgcn_readlane(hi, 0) << 32 | __builtin_amdgcn_readlane(lo, 0);
-  const uint64_t b = (uint64_t)__builtin_amdgcn_readlane(hi, 32) << 32 | __builtin_amdgcn_readlane(lo, 32);
+  // readlane returns int: widen through uint32_t, never by sign extension
+  const uint64_t a = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 0) << 32 |
+                     (uint32_t)__builtin_amdgcn_readlane(lo, 0);
+  const uint64_t b = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi, 32) << 32 |
+                     (uint32_t)__builtin_amdgcn_readlane(lo, 32);
   return a + b;
 }
 
@@ -604,11 +607,11 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
     item = __builtin_amdgcn_readfirstlane(item);  // lane 0 took the item
     if (item >= a.nitems) break;  // every wave leaves once the queue is drained
     const item_ptr it = (item_ptr)a.items + item;
-    const uint64_t t0 = it->t0, t1 = it->t1;
+    const uint64_t t0 = it->t0, t1 = it->t1, step = it->step;
     const uint32_t slot = it->slot;
     const prog_ptr p = (prog_ptr)a.progs + it->prog;
     uint64_t total = 0;
-    for (uint64_t t = t0; t < t1; ++t) {
+    for (uint64_t t = t0; t < t1; t += step) {
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
       run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(p->code, p->nins, U0, lane, acc, regs);

@@ -487,6 +487,18 @@ def test_batch_autotuner_choice_is_exact(F, tmp_path):
     assert host(F.count_batch(progs, words_per_lane=w)).tolist() == want
 
 
+@pytest.mark.parametrize("n", [36, 40])
+def test_large_counts_per_wave(F, n):
+    # waves that count more than 2^31 models each: the 64-bit wave sums must
+    # carry exactly (7/8 of 2^n models, single-program and batched paths)
+    p = F.Program("x0 | x1 | x2", n)
+    want = 7 << (n - 3)
+    for w in (1, 8, 32):
+        assert int(host(F.count(p, words_per_lane=w))[0]) == want
+    q = F.Program("x5 | ~x39" if n == 40 else "x5 | ~x35", n)
+    assert host(F.count_batch([p, q])).tolist() == [want, 3 << (n - 2)]
+
+
 def test_maximum_sizes(F):
     # n = 48, the largest valuation space (2^48 valuations, two clauses)
     n = 48
