@@ -64,10 +64,10 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
 # the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
-# half the bytes copied, WRITE_SIZE all of them): 2 x 2839.3 KiB fetched and
-# 8400486.3 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
+# half the bytes copied, WRITE_SIZE all of them): 2 x 2670.7 KiB fetched and
+# 8415177.1 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
 # None whenever that kernel has changed since the counters were taken.
-C1_TRAFFIC = (2 * 2839.3 + 8400486.3) * 1024
+C1_TRAFFIC = (2 * 2670.7 + 8415177.1) * 1024
 
 
 class ProgramCache:
@@ -511,9 +511,24 @@ def bench_copy(args, torch):
         dst.copy_(src)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the write ceiling the DNF write-out is compared with: torch's fill of a
+    # buffer as large as the 16 C1 DNF vectors (8 GiB), timed with HIP events
+    big = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    big.fill_(1)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.steps):
+        big.fill_(1)
+    b.record(stream)
+    torch.cuda.synchronize()
+    fill_ms = a.elapsed_time(b) / args.steps
     return {"metric": "copy bandwidth (counter calibration)", "value": 2 * nbytes / (ms / 1e3) / 1e9,
             "unit": "GB/s", "ms_per_step": ms, "dtype": "u64",
-            "config": {"workload": "device copy of 1 GiB (reads 1 GiB, writes 1 GiB)", "bytes": nbytes}}
+            "config": {"workload": "device copy of 1 GiB (reads 1 GiB, writes 1 GiB)", "bytes": nbytes},
+            "fill_8GiB": {"ms": fill_ms, "gb_per_s": (8 << 30) / (fill_ms / 1e3) / 1e9}}
 
 
 def main():
