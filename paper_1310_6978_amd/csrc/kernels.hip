@@ -235,7 +235,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
-typedef const __attribute__((address_space(4))) char *code_bytes;
+typedef const __attribute__((address_space(4))) char *code_byte_ptr;
 
 // The clause block (fbg_isa.h): the per-lane products G_g of the static
 // groups chunk by chunk, acc from them by a product tree that also applies
@@ -267,7 +267,7 @@ __device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, c
     }
     const uint32_t A = runs_false(~(lb | S), hd[2], hd[3]);
     // keys by group; hd[5 + g] is where group g's keys end (bytes)
-    const code_bytes hb = (code_bytes)h;
+    const code_byte_ptr hb = (code_byte_ptr)h;
     uint32_t off = (FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4;
 #pragma unroll
     for (int g = 0; g < NG; g++) {
@@ -282,7 +282,7 @@ __device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, c
   // the first multi chunk: its false runs now, its keys inside the tree
   u32x16 mh = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   uint32_t Am = 0, moff = 0;
-  const code_bytes mb = (code_bytes)ch;
+  const code_byte_ptr mb = (code_byte_ptr)ch;
   if (nmulti) {
     mh = *(const __attribute__((address_space(4))) u32x16 *)ch;
     const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
@@ -323,7 +323,7 @@ __device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, c
       const uint32_t nc = hd[0];
       const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
       const uint32_t A = runs_false(~(lb | chunk_tile_bits(ch, nc, U0, lane)), hd[2], hd[3]);
-      const code_bytes hb = (code_bytes)h;
+      const code_byte_ptr hb = (code_byte_ptr)h;
       for (uint32_t off = (FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4; off < hd[5]; off += 16) {
         const u32x4 kq = *(const __attribute__((address_space(4))) u32x4 *)(hb + off);
         const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int)A, kq[0], 1u);
@@ -508,10 +508,11 @@ __device__ __forceinline__ void store_tile(const uint32_t (&acc)[1 << LOG2W], ui
 
 // Waves per SIMD each evaluator instance is compiled for (its VGPR budget),
 // as many as fit without spilling: programs made of clauses alone fit 8
-// (<= 64 VGPRs); the general interpreter 6 at W <= 8 and is left
-// unconstrained above.
+// (<= 64 VGPRs), the uniform-cofactor variant 7 at W = 32; the general
+// interpreter 6 at W <= 8, 4 at W = 16 (124 VGPRs: cur, acc and four
+// registers per word) and is left unconstrained above.
 constexpr int min_waves(int log2w, int var) {
-  return (var & 1) ? (log2w <= 3 ? 6 : (log2w == 4 ? 2 : 1)) : ((var & 2) && log2w == 5 ? 7 : 8);
+  return (var & 1) ? (log2w <= 3 ? 6 : (log2w == 4 ? 4 : 1)) : ((var & 2) && log2w == 5 ? 7 : 8);
 }
 
 template <int LOG2W, int MODE, int VAR>

@@ -98,6 +98,36 @@ def test_random_formulas(F, seed):
     full_check(F, text, n)
 
 
+def multi_literal_cnf(rng, n, nmulti):
+    """CNF whose clauses mostly carry two or more literals on the word-index
+    variables x11..x15, plus a few ordinary 3-clauses."""
+    clauses = []
+    for _ in range(nmulti):
+        k = rng.choice([2, 3, 3, 4])
+        vs = rng.sample(range(11, 16), min(k, 5) - 1) + [rng.randrange(n)]
+        clauses.append("(" + " | ".join(("~" if rng.random() < 0.5 else "") + "x%d" % v for v in vs) + ")")
+    for _ in range(8):
+        vs = rng.sample(range(n), 3)
+        clauses.append("(" + " | ".join(("~" if rng.random() < 0.5 else "") + "x%d" % v for v in vs) + ")")
+    return " & ".join(clauses)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_multi_literal_keys_inside_and_after_the_tree(F, seed):
+    # the first 32 multi-literal clauses act inside the product tree at their
+    # level and half, the rest after it: every tiling, both variants, batched
+    rng = random.Random(4900 + seed)
+    n = rng.choice([17, 19, 22])
+    text = multi_literal_cnf(rng, n, rng.choice([12, 40, 75]))
+    p = full_check(F, text, n, wpls=[4, 8, 16, 32])
+    want = oracle.dnf(text, n)
+    for w in (8, 32):
+        assert np.array_equal(host(F.eval_dnf(p, words_per_lane=w, cofactor=True)), want), w
+    q = F.Program(multi_literal_cnf(random.Random(seed), n, 20), n)
+    got = host(F.count_batch([p, q], words_per_lane=32)).tolist()
+    assert got == [gpu_count(F, p, 32), gpu_count(F, q, 32)]
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_random_cnf_several_tiles(F, seed):
     rng = random.Random(700 + seed)
