@@ -240,11 +240,9 @@ typedef const __attribute__((address_space(4))) char *code_byte_ptr;
 // The clause block (fbg_isa.h): the per-lane products G_g of the static
 // groups chunk by chunk, acc from them by a product tree that also applies
 // the keys of the first multi chunk at their levels, then any later multi
-// chunk on the W words.  Returns false when the uniform-cofactor variant
-// finds a clause made only of tile literals false on the tile (acc = 0 on
-// the whole tile).
-template <int LOG2W, bool COF>
-__device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, const code_ptr table, uint64_t U0,
+// chunk on the W words.
+template <int LOG2W>
+__device__ __forceinline__ void run_clauses(const uint32_t *__restrict__ cb_g, const code_ptr table, uint64_t U0,
                                             uint32_t lane, uint32_t (&acc)[1 << LOG2W]) {
   constexpr int W = 1 << LOG2W;
   constexpr int NG = 1 + 2 * LOG2W;
@@ -260,11 +258,6 @@ __device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, c
     const uint32_t nc = hd[0];
     const uint32_t lb = ch[FBG_CB_CHUNK_HDR + lane];
     const uint32_t S = chunk_tile_bits(ch, nc, U0, lane);
-    if (COF && k == 0 && (S & hd[4]) != hd[4]) {
-#pragma unroll
-      for (int i = 0; i < W; i++) acc[i] = 0u;
-      return false;
-    }
     const uint32_t A = runs_false(~(lb | S), hd[2], hd[3]);
     // keys by group; hd[5 + g] is where group g's keys end (bytes)
     const code_byte_ptr hb = (code_byte_ptr)h;
@@ -335,25 +328,69 @@ __device__ __forceinline__ bool run_clauses(const uint32_t *__restrict__ cb_g, c
       ch += hd[1];
     }
   }
-  return true;
+}
+
+// The uniform-cofactor test of one tile (lane-parallel: each lane may ask
+// about another tile): 0 when a clause made only of tile literals is false on
+// the whole tile, which makes the program false there (acc only loses bits
+// after the clause block), else 1.  The encoder puts those clauses first in
+// the first chunk and marks them in its h[4]; their selectors are read as
+// scalars.  Every lane runs it (no divergent branch around it), and the
+// result is a 0/1 word, not a lane-mask boolean.
+template <int LOG2W>
+__device__ __forceinline__ uint32_t tile_alive(const uint32_t *__restrict__ cb_g, uint64_t t) {
+  const code_ptr cb = (code_ptr)cb_g;
+  if (cb[1] == 0) return 1u;
+  const code_ptr h = cb + FBG_CB_HDR;
+  const uint32_t k = __popc(h[4]);  // a prefix of the first chunk
+  const code_ptr td = h + FBG_CB_CHUNK_HDR + 64;
+  const uint64_t U0 = t << LOG2W;
+  uint32_t dead = 0u;
+  for (uint32_t c = 0; c < k; ++c) {
+    const u32x4 e = *(const __attribute__((address_space(4))) u32x4 *)(td + 4 * c);
+    const uint64_t sel = (uint64_t)e[0] | ((uint64_t)e[1] << 32);
+    const uint64_t neg = (uint64_t)e[2] | ((uint64_t)e[3] << 32);
+    dead |= (uint32_t)((U0 & sel) == neg);
+  }
+  return dead ^ 1u;
+}
+
+// Visit the tiles first, first + stride, ... below end.  body(t, alive):
+// alive = false means the tile is known to be all zeros (uniform cofactor)
+// and need not be evaluated.  With COF the wave tests the next 64 tiles at
+// once, one per lane, and visits only the live ones, or (ALL) every tile,
+// the dead ones with alive = false.  Lanes past the end test some tile
+// beyond it; the valid mask removes them.
+template <int LOG2W, bool COF, bool ALL, typename Body>
+__device__ __forceinline__ void for_tiles(const uint32_t *__restrict__ code, uint64_t first, uint64_t stride,
+                                          uint64_t end, uint32_t lane, Body &&body) {
+  if (!COF) {
+    for (uint64_t t = first; t < end; t += stride) body(t, true);
+    return;
+  }
+  for (uint64_t q0 = 0; first + q0 * stride < end; q0 += 64) {
+    const uint64_t tl = first + (q0 + lane) * stride;
+    const uint64_t valid = __ballot(tl < end);
+    const uint64_t alive = __ballot(tile_alive<LOG2W>(code, tl) != 0u) & valid;
+    uint64_t todo = ALL ? valid : alive;
+    while (todo) {
+      const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      body(first + (q0 + l) * stride, ((alive >> l) & 1ull) != 0);
+    }
+  }
 }
 
 // Interpret one program over the W words of this lane in tile group U0: the
 // clause block, then (GEN) the instructions after it.
-//
-// COF = true is the uniform-cofactor variant: the tile bits of the index are
-// constants on the whole tile, so a clause whose only literals are false tile
-// literals is false on the whole tile, which ends the tile (acc = 0; the
-// instructions after the block only clear bits of acc).  The result is the
-// same; the work depends on the data.
-template <int LOG2W, bool GEN, bool COF>
+template <int LOG2W, bool GEN>
 __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g, uint32_t nins, uint64_t U0,
                                             uint32_t lane, uint32_t (&acc)[1 << LOG2W],
                                             uint32_t *__restrict__ regs) {
   const code_ptr cb = (code_ptr)code_g;
   const code_ptr ins = cb + cb[0];
   const code_ptr table = ins + (size_t)nins * FBG_INS_WORDS;
-  if (!run_clauses<LOG2W, COF>(code_g, table, U0, lane, acc)) return;
+  run_clauses<LOG2W>(code_g, table, U0, lane, acc);
   if (!GEN) return;
   run_general<LOG2W>(ins, table, nins, U0, lane, acc, regs);
 }
@@ -526,14 +563,22 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
   const uint64_t wave = (uint64_t)blockIdx.x * wpb + wib;
   const uint64_t nwaves = (uint64_t)gridDim.x * wpb;
   uint64_t total = 0;
-  for (uint64_t t = wave; t < a.ntiles; t += nwaves) {
+  // dead tiles (uniform cofactor) still write their zeros in DNF and
+  // tile-count modes; counting and compaction skip them
+  constexpr bool ALL = MODE == MODE_DNF || MODE == MODE_TILECNT;
+  for_tiles<LOG2W, (VAR & 2) != 0, ALL>(a.code, wave, nwaves, a.ntiles, lane, [&](uint64_t t, bool alive) {
     const uint64_t U0 = t << LOG2W;
     if (MODE == MODE_ENUM) {
-      if (a.tile_counts[t] == 0u) continue;  // no model in this tile
+      if (a.tile_counts[t] == 0u) return;  // no model in this tile
     }
     uint32_t acc[W];
-    run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(a.code, a.nins, U0, lane, acc, regs);
-    mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);
+    if (alive) {
+      run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, regs);
+      mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);
+    } else {
+#pragma unroll
+      for (int i = 0; i < W; i++) acc[i] = 0u;
+    }
     if (MODE == MODE_COUNT) {
       uint32_t c = 0;
 #pragma unroll
@@ -546,7 +591,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
     } else {
       tile_compact<LOG2W>(acc, U0, lane, a.tile_offsets[t], a.out_idx, a.capacity);
     }
-  }
+  });
   if (MODE == MODE_COUNT) {
     const uint64_t s = wave_sum_u64(total);
     if (lane == 0 && s) atomicAdd((unsigned long long *)a.out_count, (unsigned long long)s);
@@ -612,10 +657,15 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
     const uint32_t slot = it->slot;
     const prog_ptr p = (prog_ptr)a.progs + it->prog;
     uint64_t total = 0;
-    for (uint64_t t = t0; t < t1; t += step) {
+    for_tiles<LOG2W, (VAR & 2) != 0, MODE == MODE_DNF>(p->code, t0, step, t1, lane, [&](uint64_t t, bool alive) {
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
-      run_program<LOG2W, (VAR & 1) != 0, (VAR & 2) != 0>(p->code, p->nins, U0, lane, acc, regs);
+      if (alive) {
+        run_program<LOG2W, (VAR & 1) != 0>(p->code, p->nins, U0, lane, acc, regs);
+      } else {
+#pragma unroll
+        for (int i = 0; i < W; i++) acc[i] = 0u;
+      }
       uint32_t c = 0;
       if (MODE == MODE_DNF) {
         c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
@@ -629,7 +679,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
         const uint32_t tc = wave_sum_u32(c);
         if (lane == 0) p->tile_counts[t] = tc;
       }
-    }
+    });
     const uint64_t s = wave_sum_u64(total);
     if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + slot), (unsigned long long)s);
   }
