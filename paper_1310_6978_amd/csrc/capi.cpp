@@ -181,7 +181,7 @@ struct fbg_batch {
   uint64_t *d_scan_blk = nullptr;
   uint32_t *d_tile_list = nullptr;        // tiles holding models, then their number
   fbg::EnumProg *d_enum = nullptr;
-  uint32_t *d_head = nullptr;             // one queue head per plan
+  uint32_t *d_head = nullptr;             // kHeadWords of queue heads per plan (at most 4 plans)
   // captured graph of (zero fill, persistent kernels) for one counts pointer
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -700,7 +700,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     plan_items.push_back(std::move(sorted));
   }
   hipError_t e = hipMalloc((void **)&b->d_progs, (size_t)np * sizeof(fbg::BatchProg));
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_head, 256);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_head, 4 * fbg::kHeadWords * sizeof(uint32_t));
   for (size_t k = 0; k < b->plans.size() && e == hipSuccess; k++) {
     e = hipMalloc((void **)&b->plans[k].d_items, plan_items[k].size() * sizeof(fbg::BatchItem));
     if (e == hipSuccess)
@@ -723,7 +723,7 @@ namespace {
 
 fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, uint64_t *d_counts, hipStream_t s) {
   // zero the counts and every plan's queue head, then one persistent kernel per plan
-  hipError_t e = fbg::launch_zero(d_counts, (uint64_t)b->np, b->d_head, s);
+  hipError_t e = fbg::launch_zero(d_counts, (uint64_t)b->np, b->d_head, (uint32_t)b->plans.size() * fbg::kHeadWords, s);
   if (e != hipSuccess) return hip_fail(e, "launch of the zero fill");
   for (size_t k = 0; k < b->plans.size(); k++) {
     const fbg_batch::Plan &pl = b->plans[k];
@@ -732,7 +732,7 @@ fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, u
     a.items = pl.d_items;
     a.nitems = pl.nitems;
     a.max_regs = pl.max_regs;
-    a.head = b->d_head + k;
+    a.head = b->d_head + k * fbg::kHeadWords;
     a.counts = d_counts;
     e = fbg::launch_batch(mode, pl.log2w, pl.var, a, mode == fbg::EVAL_DNF ? pl.grid_dnf : pl.grid, pl.block, pl.lds,
                           s);
@@ -845,7 +845,7 @@ fbg_status fbg_batch_enumerate(fbg_batch *b, void *stream) {
   a.list = b->d_tile_list;
   a.nlist = b->d_tile_list + std::max<uint64_t>(b->total_tiles, 1);
   const int grid = cu_count(b->device) * 8;
-  e = fbg::launch_zero(nullptr, 0, a.nlist, s);
+  e = fbg::launch_zero(nullptr, 0, a.nlist, 1, s);
   if (e == hipSuccess) e = fbg::launch_list_tiles(a, grid, s);
   if (e != hipSuccess) return hip_fail(e, "launch of the tile listing");
   for (const auto &pl : b->plans) {
@@ -951,7 +951,7 @@ fbg_status fbg_server_create(int32_t max_programs, int32_t max_items, int32_t wo
   for (auto &sl : sv->slots) {
     e = hipHostMalloc((void **)&sl.h, bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void **)&sl.d, bytes);
-    if (e == hipSuccess) e = hipMalloc((void **)&sl.d_head, 256);
+    if (e == hipSuccess) e = hipMalloc((void **)&sl.d_head, fbg::kHeadWords * sizeof(uint32_t));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     if (e != hipSuccess) {
       fbg_server_free(sv);
@@ -1025,7 +1025,7 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   e = hipMemcpyAsync(dp, hp, (size_t)np * sizeof(fbg::BatchProg), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && npieces > 0)
     e = hipMemcpyAsync(di, hi, (size_t)npieces * sizeof(fbg::BatchItem), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = fbg::launch_zero(nullptr, 0, sl.d_head, s);
+  if (e == hipSuccess) e = fbg::launch_zero(nullptr, 0, sl.d_head, fbg::kHeadWords, s);
   if (e != hipSuccess) return hip_fail(e, "server upload");
   fbg::BatchArgs a;
   a.progs = (const fbg::BatchProg *)dp;

@@ -66,12 +66,20 @@ struct BatchItem {
   uint64_t step;
 };
 
+// A plan's work items are split over kQueues queues (item i in queue
+// i mod kQueues), one per XCD, each with its own head counter kQueueStride
+// words (64 bytes) from the next, so that the queue atomics of the eight
+// XCDs do not all meet at one address.
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kQueueStride = 16;
+constexpr uint32_t kHeadWords = kQueues * kQueueStride;
+
 struct BatchArgs {
   const BatchProg *progs;
   const BatchItem *items;
   uint32_t nitems;
   uint32_t max_regs;      // LDS registers per wave (beyond kVgprRegs)
-  uint32_t *head;     // queue head, zeroed before the launch
+  uint32_t *head;     // kHeadWords words of queue heads, zeroed before the launch
   uint64_t *counts;   // per slot; the kernel adds to it
 };
 
@@ -90,8 +98,8 @@ hipError_t launch_batch_compact(int log2w, const BatchEnumArgs &a, int grid, int
 hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
                        hipStream_t s);
 uint64_t scan_block_count(uint64_t n);
-// p[0..n) = 0 and, if head is not null, head[0..4) = 0 (a 16-byte area).
-hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, hipStream_t s);
+// p[0..n) = 0 and head[0..nhead) = 0.
+hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, uint32_t nhead, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 
 }  // namespace fbg

@@ -647,16 +647,21 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
   uint32_t *regs = lds + (size_t)wib * a.max_regs * (W * 64);
   typedef const __attribute__((address_space(4))) BatchItem *item_ptr;
   typedef const __attribute__((address_space(4))) BatchProg *prog_ptr;
-  for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(a.head, 1u);
-    item = __builtin_amdgcn_readfirstlane(item);  // lane 0 took the item
-    if (item >= a.nitems) break;  // every wave leaves once the queue is drained
+  // A wave adds its count to a program's slot once per run of items of
+  // that program, not once per item: same-address device atomics serialize.
+  uint64_t total = 0;
+  uint32_t cur_slot = ~0u;
+  auto process = [&](uint32_t item) {
     const item_ptr it = (item_ptr)a.items + item;
     const uint64_t t0 = it->t0, t1 = it->t1, step = it->step;
     const uint32_t slot = it->slot;
     const prog_ptr p = (prog_ptr)a.progs + it->prog;
-    uint64_t total = 0;
+    if (slot != cur_slot) {  // wave-uniform
+      const uint64_t s = wave_sum_u64(total);
+      if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + cur_slot), (unsigned long long)s);
+      total = 0;
+      cur_slot = slot;
+    }
     for_tiles<LOG2W, (VAR & 2) != 0, MODE == MODE_DNF>(p->code, t0, step, t1, lane, [&](uint64_t t, bool alive) {
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
@@ -680,9 +685,27 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
         if (lane == 0) p->tile_counts[t] = tc;
       }
     });
-    const uint64_t s = wave_sum_u64(total);
-    if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + slot), (unsigned long long)s);
+  };
+  // Items come sorted by cost, largest first, dealt over kQueues queues:
+  // queue q holds items q, q + kQueues, ...  A wave pops from the queue of
+  // its XCD (workgroups go to the XCDs round-robin), then from the others
+  // until all are drained; a drained queue is seen by a plain read before
+  // any atomic is spent on it.
+  const uint32_t q0 = blockIdx.x % kQueues;
+  for (uint32_t k = 0; k < kQueues; ++k) {
+    const uint32_t q = (q0 + k) % kQueues;
+    uint32_t *head = a.head + q * kQueueStride;
+    if (k > 0 && q + kQueues * __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)head) >= a.nitems) continue;
+    for (;;) {
+      uint32_t r = 0;
+      if (lane == 0) r = atomicAdd(head, 1u);
+      const uint32_t item = q + kQueues * __builtin_amdgcn_readfirstlane(r);  // lane 0 took the item
+      if (item >= a.nitems) break;  // this queue is drained
+      process(item);
+    }
   }
+  const uint64_t s = wave_sum_u64(total);
+  if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + cur_slot), (unsigned long long)s);
 }
 
 // Batched enumeration from the stored DNF vectors: every wave strides over
@@ -798,11 +821,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *in,
 
 // ------------------------------------------------------------------ fills
 
-// p[0..n) = 0 and, when head is given, the four queue heads head[0..4).
-__global__ void k_zero_u64(uint64_t *p, uint64_t n, uint32_t *head) {
+// p[0..n) = 0 and head[0..nhead) = 0 (queue heads and list counters).
+__global__ void k_zero_u64(uint64_t *p, uint64_t n, uint32_t *head, uint32_t nhead) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
-  if (head && i < 4) head[i] = 0;
+  if (i < nhead) head[i] = 0;
 }
 
 __global__ void k_set_u64(uint64_t *p, uint64_t v) {
@@ -998,10 +1021,11 @@ hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *
 
 uint64_t scan_block_count(uint64_t n) { return (n + dev::SCAN_BLOCK - 1) / dev::SCAN_BLOCK; }
 
-hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, hipStream_t s) {
-  const uint64_t threads = n > 0 ? n : 1;
+hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, uint32_t nhead, hipStream_t s) {
+  if (!head) nhead = 0;
+  const uint64_t threads = std::max<uint64_t>(std::max<uint64_t>(n, nhead), 1);
   const unsigned grid = (unsigned)((threads + 255) / 256);
-  hipLaunchKernelGGL(dev::k_zero_u64, dim3(grid), dim3(256), 0, s, p, n, head);
+  hipLaunchKernelGGL(dev::k_zero_u64, dim3(grid), dim3(256), 0, s, p, n, head, nhead);
   return hipGetLastError();
 }
 
