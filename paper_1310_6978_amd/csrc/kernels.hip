@@ -17,8 +17,9 @@
 //                         VAR bit 1 (COF): the uniform-cofactor variant
 //   k_dnf_scan<MODE>      the two enumeration passes over a stored DNF vector
 //   k_batch<LOG2W, VAR, MODE>  many programs, persistent waves popping work
-//                         items (program, tile range) from a device queue;
-//                         counts, and with MODE_DNF the DNF vectors too
+//                         items (program, tiles t0 + k step) from eight
+//                         device queues, one per XCD, with stealing; counts,
+//                         and with MODE_DNF the DNF vectors too
 //   k_scan_*              exclusive scan of per-tile counts
 //   k_zero_*, k_set_u64   fills (used instead of memset so that a caller may
 //                         capture the launches into a graph)
