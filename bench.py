@@ -34,7 +34,10 @@ examples, at every tiling, with and without the uniform-cofactor variant.
 Workload unlabeled: non-isomorphic partial orders (7 elements) and graphs (7
 vertices) by the Frobenius-Burnside lemma.
 Workload copy: a 1 GiB device copy, the calibration kernel for the HBM byte
-counters.
+counters, and an 8 GiB fill (the write ceiling).
+Workload valu: the attainable v_bitop3 issue rate (independent chains on a
+full grid), the check of the VALU peak the bitwise fractions are quoted
+against.
 """
 
 import argparse
@@ -497,6 +500,47 @@ def bench_unlabeled(args, torch, fbg):
             "runs": rows}
 
 
+def bench_valu(args, torch):
+    """The attainable integer-bitwise VALU rate (independent v_bitop3 chains,
+    full grid): the check of the denominator of the algorithmic fraction."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1310_6978_amd", "libfbg_probe.so"))
+    lib.fbg_probe_valu_peak.restype = ctypes.c_int
+    lib.fbg_probe_valu_peak.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = cus * 8                       # 8 waves per SIMD
+    iters = 4096
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        rc = lib.fbg_probe_valu_peak(ctypes.c_void_p(out.data_ptr()), blocks, iters, 12345,
+                                     ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError("probe launch failed: %d" % rc)
+    for _ in range(max(args.warmup, 1)):
+        launch()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.steps):
+        launch()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    lane_instr = float(blocks) * 256 * iters * 64
+    rate = lane_instr / (ms / 1e3)
+    spec = cus * 64 * 2.4e9                # one VALU instruction per lane per clock
+    return {"metric": "attainable v_bitop3 rate (VALU peak probe)", "value": rate, "unit": "lane-instr/s",
+            "ms_per_step": ms, "dtype": "u32",
+            "config": {"workload": "%d blocks x 256 threads, 8 independent v_bitop3 chains, %d x 64 per lane"
+                                   % (blocks, iters)},
+            "fraction_of_spec": rate / spec, "spec_lane_instr_per_s": spec,
+            "bitops_per_s_2input": rate * 32, "valu_bitwise_peak_2input": VALU_BITWISE_PEAK}
+
+
 def bench_copy(args, torch):
     """A plain device-to-device copy of 1 GiB: the calibration kernel for the
     FETCH_SIZE / WRITE_SIZE counters (it must read and write 1 GiB)."""
@@ -536,7 +580,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4", "posets", "theories", "unlabeled", "copy"])
+    ap.add_argument("--workload", default="c1",
+                    choices=["c1", "c3", "c4", "posets", "theories", "unlabeled", "copy", "valu"])
     ap.add_argument("--posets-n", type=int, default=11, help="posets: bounded posets on n elements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=20000, help="c4: requests in the timed run")
@@ -567,6 +612,8 @@ def main():
         res = bench_theories(args, torch, fbg)
     elif args.workload == "unlabeled":
         res = bench_unlabeled(args, torch, fbg)
+    elif args.workload == "valu":
+        res = bench_valu(args, torch)
     else:
         res = bench_copy(args, torch)
     out = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,

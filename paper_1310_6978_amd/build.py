@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfbg.so")
+PROBE_LIB = os.path.join(HERE, "libfbg_probe.so")
 ARCH = os.environ.get("FBG_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kernels.hip", "compiler.cpp", "capi.cpp"]
@@ -52,6 +53,19 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the measurement probes bench.py loads beside the library
+    obj = os.path.join(HERE, "_build", "probe.o")
+    cmd = [hipcc()] + common + ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
+                                "-packed-fp32-ops", "-c", os.path.join(CSRC, "probe.hip"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 
