@@ -210,7 +210,9 @@ class Program:
         self.info = {f: getattr(info, f) for f, _ in ProgramInfo._fields_}
 
     def emulate(self, words_per_lane=1):
-        """Host interpretation of the encoded program: (dnf uint64 array, count)."""
+        """Host interpretation of the encoded program: (dnf uint64 array, count).
+        Reads it the way the uniform-cofactor kernels do when the program's
+        default tuning selects them (set_tuning(..., cofactor=True))."""
         out = np.zeros(dnf_words(self.n), dtype=np.uint64)
         cnt = ctypes.c_uint64(0)
         _check(lib.fbg_program_emulate(self.handle, int(words_per_lane),
