@@ -569,10 +569,36 @@ def bench_copy(args, torch):
     b.record(stream)
     torch.cuda.synchronize()
     fill_ms = a.elapsed_time(b) / args.steps
+    # the evaluator's DNF store pattern alone (tiles of 32 x 256-byte stores
+    # per wave), plain and non-temporal, over the same 8 GiB
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1310_6978_amd", "libfbg_probe.so"))
+    lib.fbg_probe_store_tiles.restype = ctypes.c_int
+    lib.fbg_probe_store_tiles.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    ntiles = (8 << 30) // (2048 * 4)
+    tiles = {}
+    for nt in (0, 1):
+        def launch():
+            rc = lib.fbg_probe_store_tiles(ctypes.c_void_p(big.data_ptr()), ntiles, cus * 8, nt,
+                                           ctypes.c_void_p(stream.cuda_stream))
+            if rc != 0:
+                raise RuntimeError("probe launch failed: %d" % rc)
+        launch()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(args.steps):
+            launch()
+        b.record(stream)
+        torch.cuda.synchronize()
+        t_ms = a.elapsed_time(b) / args.steps
+        tiles["nontemporal" if nt else "plain"] = {"ms": t_ms, "gb_per_s": (8 << 30) / (t_ms / 1e3) / 1e9}
     return {"metric": "copy bandwidth (counter calibration)", "value": 2 * nbytes / (ms / 1e3) / 1e9,
             "unit": "GB/s", "ms_per_step": ms, "dtype": "u64",
             "config": {"workload": "device copy of 1 GiB (reads 1 GiB, writes 1 GiB)", "bytes": nbytes},
-            "fill_8GiB": {"ms": fill_ms, "gb_per_s": (8 << 30) / (fill_ms / 1e3) / 1e9}}
+            "fill_8GiB": {"ms": fill_ms, "gb_per_s": (8 << 30) / (fill_ms / 1e3) / 1e9},
+            "dnf_store_pattern_8GiB": tiles}
 
 
 def main():

@@ -1,6 +1,7 @@
 // probe.hip -- measurement kernels used by bench.py beside the evaluator (not
 // part of the evaluation path): the attainable integer-bitwise VALU rate of
-// the device, the denominator check of the algorithmic fraction.
+// the device, the denominator check of the algorithmic fraction, and the
+// write rate of the DNF write-out's store pattern alone.
 //
 // k_valu_peak: every lane runs 8 independent chains of v_bitop3_b32 (each
 // chain depends only on itself and on two loop-invariant operands), so the
@@ -33,9 +34,43 @@ __global__ __launch_bounds__(256) void k_valu_peak(uint32_t *out, uint32_t iters
   out[tid] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
 }
 
+// The DNF write-out's store pattern without the evaluation: a wave writes
+// tiles of 32 x 64 words, word i of lane l at tile * 2048 + i * 64 + l (32
+// stores of 256 contiguous bytes), striding over the tiles; NT selects
+// non-temporal stores, as the evaluator uses.
+template <bool NT>
+__global__ __launch_bounds__(256) void k_store_tiles(uint32_t *p, uint64_t ntiles) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t t = wave; t < ntiles; t += nw) {
+    uint32_t *dst = p + t * 2048 + lane;
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+      const uint32_t v = (uint32_t)t ^ (uint32_t)i ^ lane;
+      if (NT)
+        __builtin_nontemporal_store(v, dst + i * 64);
+      else
+        dst[i * 64] = v;
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+// Queue one launch writing ntiles x 2048 uint32 words of `out` (device
+// memory of at least that size) with the evaluator's tile pattern.
+int fbg_probe_store_tiles(uint32_t *out, uint64_t ntiles, int32_t blocks, int32_t nontemporal, void *stream) {
+  if (!out || blocks <= 0) return (int)hipErrorInvalidValue;
+  if (nontemporal)
+    hipLaunchKernelGGL(k_store_tiles<true>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, out, ntiles);
+  else
+    hipLaunchKernelGGL(k_store_tiles<false>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, out, ntiles);
+  return (int)hipGetLastError();
+}
+
 
 // Queue one launch of `blocks` x 256 threads, each issuing 64 * iters
 // v_bitop3_b32; `out` holds blocks * 256 uint32 words (device memory).
