@@ -67,10 +67,10 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
 # the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
-# half the bytes copied, WRITE_SIZE all of them): 2 x 2670.7 KiB fetched and
-# 8415177.1 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
+# half the bytes copied, WRITE_SIZE all of them): 2 x 4017.8 KiB fetched and
+# 8433405.9 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
 # None whenever that kernel has changed since the counters were taken.
-C1_TRAFFIC = (2 * 2670.7 + 8415177.1) * 1024
+C1_TRAFFIC = (2 * 4017.8 + 8433405.9) * 1024
 
 
 class ProgramCache:
