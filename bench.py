@@ -291,6 +291,7 @@ def bench_c3(args, torch, fbg):
     tuner = autotune.Tuner()
     wpl = tuner.tune_batch(progs)                       # cached per device and program set
     tuned = tuner.table.get(tuner.last_key, {})
+    print(f"c3: {len(progs)} programs compiled, {wpl} words per lane", file=sys.stderr, flush=True)
     b = fbg.Batch(progs, words_per_lane=wpl)
     counts = torch.empty(len(progs), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
@@ -307,6 +308,8 @@ def bench_c3(args, torch, fbg):
     t0 = time.perf_counter()
     for i, p in enumerate(progs):
         fbg.count(p, out=outs[i:i + 1], stream=stream)
+        if i % 1024 == 1023:
+            print(f"c3: {i + 1} plain launches", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t0) * 1e3
     got = counts.cpu().numpy().view("uint64").tolist()
