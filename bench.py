@@ -572,19 +572,25 @@ def bench_copy(args, torch):
     b.record(stream)
     torch.cuda.synchronize()
     fill_ms = a.elapsed_time(b) / args.steps
-    # the evaluator's DNF store pattern alone (tiles of 32 x 256-byte stores
-    # per wave), plain and non-temporal, over the same 8 GiB
+    # the evaluator's DNF store pattern alone (tiles of 8 KiB per wave), over
+    # the same 8 GiB: 4-byte stores of the register rows, 16-byte stores,
+    # and the rows turned into 16-byte stores through LDS; plain and
+    # non-temporal
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1310_6978_amd", "libfbg_probe.so"))
     lib.fbg_probe_store_tiles.restype = ctypes.c_int
     lib.fbg_probe_store_tiles.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
-                                          ctypes.c_void_p]
+                                          ctypes.c_uint32, ctypes.c_void_p]
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     ntiles = (8 << 30) // (2048 * 4)
     tiles = {}
-    for nt in (0, 1):
+    forms = ("rows_b32", "b128", "rows_via_lds_b128", "rows_b32_runs_of")
+    runs = [(flags, cus * 8, 1, "") for flags in range(6)]
+    runs += [(flags, cus * 8, r, "_%d_tiles" % r) for r in (4, 8, 32) for flags in (6, 7)]
+    runs += [(flags, ntiles // 4, 1, "_one_tile_per_wave") for flags in (0, 1)]   # a grid of 2^18 blocks
+    for flags, blocks, run, grid in runs:
         def launch():
-            rc = lib.fbg_probe_store_tiles(ctypes.c_void_p(big.data_ptr()), ntiles, cus * 8, nt,
+            rc = lib.fbg_probe_store_tiles(ctypes.c_void_p(big.data_ptr()), ntiles, blocks, flags, run,
                                            ctypes.c_void_p(stream.cuda_stream))
             if rc != 0:
                 raise RuntimeError("probe launch failed: %d" % rc)
@@ -596,7 +602,8 @@ def bench_copy(args, torch):
         b.record(stream)
         torch.cuda.synchronize()
         t_ms = a.elapsed_time(b) / args.steps
-        tiles["nontemporal" if nt else "plain"] = {"ms": t_ms, "gb_per_s": (8 << 30) / (t_ms / 1e3) / 1e9}
+        key = forms[flags >> 1] + grid + ("_nontemporal" if flags & 1 else "_plain")
+        tiles[key] = {"ms": t_ms, "gb_per_s": (8 << 30) / (t_ms / 1e3) / 1e9}
     return {"metric": "copy bandwidth (counter calibration)", "value": 2 * nbytes / (ms / 1e3) / 1e9,
             "unit": "GB/s", "ms_per_step": ms, "dtype": "u64",
             "config": {"workload": "device copy of 1 GiB (reads 1 GiB, writes 1 GiB)", "bytes": nbytes},

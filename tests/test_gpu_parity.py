@@ -400,6 +400,35 @@ def test_batch_eval_dnf_writes_every_vector(F):
         b.free()
 
 
+def test_dnf_into_offset_views(F):
+    """An output that starts 8 bytes past an aligned address (a view into a
+    larger buffer) receives the same words, solo and batched, and nothing
+    around it is written."""
+    import torch
+    texts = [workloads.random_3cnf(21, 90, 3), workloads.random_dag(19, 300, 5), ("x4 & ~x17", 24)]
+    progs = [F.Program(t, n) for t, n in texts]
+    for (t, n), p in zip(texts, progs):
+        want = oracle.dnf(t, n)
+        for w in (0, 4, 8, 16, 32):
+            for off in (0, 1):
+                buf = torch.full((F.dnf_words(n) + 2,), -1, dtype=torch.int64, device="cuda")
+                got = host(F.eval_dnf(p, out=buf[off:off + F.dnf_words(n)], words_per_lane=w))
+                assert np.array_equal(got, want), (n, w, off)
+                assert np.all(host(buf)[:off] == np.uint64(2**64 - 1))
+    for off in (0, 1):
+        bufs = [torch.full((F.dnf_words(n) + 2,), -1, dtype=torch.int64, device="cuda") for _, n in texts]
+        b = F.Batch(progs, words_per_lane=32)
+        b.set_dnf_outputs([o[off:] for o in bufs])
+        counts = host(b.eval_dnf())
+        for (t, n), o, c in zip(texts, bufs, counts):
+            want = oracle.dnf(t, n)
+            got = host(o)
+            assert np.array_equal(got[off:off + len(want)], want), (n, off)
+            assert np.all(got[:off] == np.uint64(2**64 - 1)) and np.all(got[off + len(want):] == np.uint64(2**64 - 1))
+            assert int(c) == int(np.unpackbits(want.view(np.uint8)).sum())
+        b.free()
+
+
 def test_batch_eval_dnf_argument_errors(F):
     import torch
     p = F.Program("x3 | x9", 12)
