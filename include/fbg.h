@@ -90,7 +90,9 @@ typedef struct {
 /* Launch tuning.  Zero fields mean "let the library choose". */
 typedef struct {
   int32_t words_per_lane;  /* 1, 2, 4, 8, 16 or 32 (32-bit words per lane per tile) */
-  int32_t grid_blocks;     /* blocks of 256 threads for persistent launches */
+  int32_t grid_blocks;     /* grid size in blocks (capped at one wave per tile or
+                              item); 0: as many as stay resident, except for
+                              fbg_eval_dnf without the cofactor: one wave per tile */
   int32_t flags;           /* FBG_TUNE_* */
   int32_t reserved1;
 } fbg_tune;

@@ -252,6 +252,12 @@ fbg_status geometry(const fbg_program *p, const fbg_tune *tune, int mode, Geomet
   const uint64_t blocks = (ntiles + wpb - 1) / wpb;
   const int occ = fbg::eval_blocks_per_cu(mode, l, p->variant(tune), 64 * wpb, g.lds);
   uint64_t maxb = (uint64_t)cu_count(p->device) * (uint64_t)occ;
+  // A DNF write-out without the cofactor runs one tile per wave on a grid of
+  // fresh blocks: the blocks start in order, so the writes advance through
+  // the vector together (a 2^32-bit vector at W = 32: 0.101 ms against 0.109
+  // on a resident grid).  Counting keeps the resident grid, whose waves add
+  // their counts once each; the cofactor filters 64 tiles per wave at once.
+  if (mode == fbg::EVAL_DNF && !(p->variant(tune) & 2)) maxb = blocks;
   if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
   g.log2w = l;
   g.block = 64 * wpb;
