@@ -164,6 +164,12 @@ struct fbg_batch {
     uint32_t nitems = 0;
     uint32_t max_regs = 0;  // LDS registers per wave
     fbg::BatchItem *d_items = nullptr;
+    // clause-only programs without the cofactor: the DNF write-out runs one
+    // wave per tile over this table (one entry per program, its tiles in the
+    // plan's order) once the tile counts exist (fbg_batch_set_enum_outputs)
+    fbg::BatchItem *d_direct = nullptr;
+    uint32_t ndirect = 0;
+    uint64_t ntiles = 0, max_prog_tiles = 0;
   };
   int device = -1;
   int32_t np = 0;
@@ -604,6 +610,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   b->host_progs.resize((size_t)np);
   b->plan_of.assign((size_t)np, 0);
   std::vector<std::vector<fbg::BatchItem>> plan_items;
+  std::vector<std::vector<fbg::BatchItem>> plan_direct;  // per plan: one entry per program (clause-only plans)
   // 0: clause-only programs; 1: general programs whose registers all fit in
   // VGPRs; 2: up to four registers in LDS; 3: more.  The LDS a plan's widest
   // program needs per wave sets the occupancy of the whole plan, so the few
@@ -702,8 +709,25 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       if (tune && tune->grid_blocks > 0) maxb = (uint64_t)tune->grid_blocks;
       (mode == fbg::EVAL_COUNT ? pl.grid : pl.grid_dnf) = (int)std::max<uint64_t>(1, std::min<uint64_t>(want, maxb));
     }
+    std::vector<fbg::BatchItem> direct;
+    if (var == 0 && !(tune && tune->grid_blocks > 0)) {
+      for (int32_t i : members) {
+        const fbg::BatchProg &q = b->host_progs[(size_t)i];
+        fbg::BatchItem it;
+        it.prog = (uint32_t)i;
+        it.slot = (uint32_t)i;
+        it.t0 = pl.ntiles;
+        it.t1 = pl.ntiles + q.ntiles;
+        it.step = 1;
+        direct.push_back(it);
+        pl.ntiles += q.ntiles;
+        pl.max_prog_tiles = std::max<uint64_t>(pl.max_prog_tiles, q.ntiles);
+      }
+      pl.ndirect = (uint32_t)direct.size();
+    }
     b->plans.push_back(pl);
     plan_items.push_back(std::move(sorted));
+    plan_direct.push_back(std::move(direct));
   }
   hipError_t e = hipMalloc((void **)&b->d_progs, (size_t)np * sizeof(fbg::BatchProg));
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_head, 4 * fbg::kHeadWords * sizeof(uint32_t));
@@ -712,6 +736,12 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     if (e == hipSuccess)
       e = hipMemcpy(b->plans[k].d_items, plan_items[k].data(), plan_items[k].size() * sizeof(fbg::BatchItem),
                     hipMemcpyHostToDevice);
+    if (e == hipSuccess && !plan_direct[k].empty()) {
+      e = hipMalloc((void **)&b->plans[k].d_direct, plan_direct[k].size() * sizeof(fbg::BatchItem));
+      if (e == hipSuccess)
+        e = hipMemcpy(b->plans[k].d_direct, plan_direct[k].data(), plan_direct[k].size() * sizeof(fbg::BatchItem),
+                      hipMemcpyHostToDevice);
+    }
   }
   if (e == hipSuccess)
     e = hipMemcpy(b->d_progs, b->host_progs.data(), (size_t)np * sizeof(fbg::BatchProg), hipMemcpyHostToDevice);
@@ -740,6 +770,18 @@ fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, u
     a.max_regs = pl.max_regs;
     a.head = b->d_head + k * fbg::kHeadWords;
     a.counts = d_counts;
+    if (mode == fbg::EVAL_DNF && pl.d_direct && b->d_tile_counts) {
+      // one wave per tile over the plan's programs in order; counts from the
+      // tile counts
+      a.items = pl.d_direct;
+      a.nitems = pl.ndirect;
+      const uint64_t wpb = (uint64_t)(pl.block / 64);
+      const uint64_t grid = (pl.ntiles + wpb - 1) / wpb;
+      const int sum_blocks = (int)std::min<uint64_t>(64, std::max<uint64_t>(1, pl.max_prog_tiles / 4096));
+      e = fbg::launch_batch_direct(pl.log2w, a, (int)grid, pl.block, sum_blocks, s);
+      if (e != hipSuccess) return hip_fail(e, "launch of the batch kernel");
+      continue;
+    }
     e = fbg::launch_batch(mode, pl.log2w, pl.var, a, mode == fbg::EVAL_DNF ? pl.grid_dnf : pl.grid, pl.block, pl.lds,
                           s);
     if (e != hipSuccess) return hip_fail(e, "launch of the batch kernel");
@@ -912,8 +954,10 @@ void fbg_batch_free(fbg_batch *b) {
   if (b->d_scan_blk) (void)hipFree(b->d_scan_blk);
   if (b->d_enum) (void)hipFree(b->d_enum);
   if (b->d_tile_list) (void)hipFree(b->d_tile_list);
-  for (auto &pl : b->plans)
+  for (auto &pl : b->plans) {
     if (pl.d_items) (void)hipFree(pl.d_items);
+    if (pl.d_direct) (void)hipFree(pl.d_direct);
+  }
   if (b->d_head) (void)hipFree(b->d_head);
   delete b;
 }

@@ -90,6 +90,11 @@ hipError_t launch_eval(int mode, int log2w, int var, const EvalArgs &a, int grid
 hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hipStream_t s);
 hipError_t launch_batch(int mode, int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds,
                         hipStream_t s);
+// The DNF write-out of a plan of clause-only programs without the cofactor,
+// one wave per tile (a.items: one entry per program, [t0, t1) its tiles in the
+// plan, ascending; every program has tile counts), then the per-program sums
+// of those tile counts into a.counts (sum_blocks blocks per program).
+hipError_t launch_batch_direct(int log2w, const BatchArgs &a, int grid, int block, int sum_blocks, hipStream_t s);
 // Resident blocks per compute unit of an evaluator or batch launch.
 int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);
 int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds);

@@ -709,6 +709,62 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
   if (lane == 0 && s) atomicAdd((unsigned long long *)(a.counts + cur_slot), (unsigned long long)s);
 }
 
+// Batched DNF write-out of a plan of clause-only programs without the uniform
+// cofactor, one tile per wave on a grid of fresh blocks: the blocks start in
+// order, so the waves write the vectors in order together, and no wave spends
+// a queue pop or a count atomic.  a.items holds the plan's programs, one
+// entry each, with [t0, t1) its tiles in the plan's tile order (ascending,
+// contiguous, a.nitems >= 1); wave g takes plan tile g.  Every program has a
+// tile-count array: the tile's model count goes there, and the program's count
+// is the later sum over them (k_sum_tile_counts).
+template <int LOG2W>
+__global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(BatchArgs a) {
+  constexpr int W = 1 << LOG2W;
+  typedef const __attribute__((address_space(4))) BatchItem *item_ptr;
+  typedef const __attribute__((address_space(4))) BatchProg *prog_ptr;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = uni(threadIdx.x) >> 6;
+  const uint64_t g = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+  const item_ptr items = (item_ptr)a.items;
+  if (g >= items[a.nitems - 1].t1) return;  // wave-uniform: past the plan's last tile
+  uint32_t lo = 0, hi = a.nitems;            // the entry with t0 <= g < t1
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (items[mid].t0 <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const item_ptr it = items + lo;
+  const prog_ptr p = (prog_ptr)a.progs + it->prog;
+  const uint64_t t = g - it->t0;
+  const uint64_t U0 = t << LOG2W;
+  uint32_t acc[W];
+  run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, nullptr);
+  const uint32_t c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
+  const uint32_t tc = wave_sum_u32(c);
+  if (lane == 0) p->tile_counts[t] = tc;
+}
+
+// Counts after k_batch_direct: block (m, y) adds its share of the tile counts
+// of entry m's program into that program's count slot (zeroed before).
+__global__ __launch_bounds__(256) void k_sum_tile_counts(BatchArgs a) {
+  __shared__ uint64_t part[4];
+  const BatchItem &it = a.items[blockIdx.x];
+  const BatchProg &p = a.progs[it.prog];
+  uint64_t s = 0;
+  for (uint64_t t = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; t < p.ntiles; t += (uint64_t)gridDim.y * blockDim.x)
+    s += p.tile_counts[t];
+  s = wave_sum_u64(s);
+  if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tot = 0;
+    for (uint32_t w = 0; w < (blockDim.x >> 6); w++) tot += part[w];
+    if (tot) atomicAdd((unsigned long long *)(a.counts + it.slot), (unsigned long long)tot);
+  }
+}
+
 // Batched enumeration from the stored DNF vectors: every wave strides over
 // the global tile list of all programs (tile counts and their exclusive scan
 // concatenated in program order), skips programs of the other plan and tiles
@@ -911,6 +967,22 @@ hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hip
     hipLaunchKernelGGL((dev::k_dnf_scan<dev::MODE_ENUM>), dim3(grid), dim3(block), 0, s, a);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_direct(int log2w, const BatchArgs &a, int grid, int block, int sum_blocks, hipStream_t s) {
+  switch (log2w) {
+    case 0: hipLaunchKernelGGL((dev::k_batch_direct<0>), dim3(grid), dim3(block), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((dev::k_batch_direct<1>), dim3(grid), dim3(block), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((dev::k_batch_direct<2>), dim3(grid), dim3(block), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((dev::k_batch_direct<3>), dim3(grid), dim3(block), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((dev::k_batch_direct<4>), dim3(grid), dim3(block), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((dev::k_batch_direct<5>), dim3(grid), dim3(block), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dev::k_sum_tile_counts, dim3(a.nitems, (unsigned)sum_blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

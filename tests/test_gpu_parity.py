@@ -487,6 +487,37 @@ def test_batch_enumerate_lists_every_program(F):
         b.free()
 
 
+def test_batch_dnf_with_tile_counts(F):
+    """Once the tile counts exist (enumeration outputs set), the DNF write-out
+    of clause-only programs without the cofactor runs one wave per tile and
+    takes its counts from the tile counts: vectors and counts still equal the
+    oracle's, at every tiling, next to general programs, on repeated calls;
+    the cofactor and an explicit grid keep the queued launch."""
+    import torch
+    texts = [("x0", 1), ("0", 9), ("x3 & ~x11", 14)]
+    texts += [workloads.random_3cnf(n, 4 * n, s) for s, n in enumerate((12, 17, 21, 23))]
+    texts += [workloads.random_dag(n, 200, s) for s, n in enumerate((13, 18))]
+    texts.append(workloads.triangle_free(6))
+    progs = [F.Program(t, n) for t, n in texts]
+    wants = [oracle.dnf(t, n) for t, n in texts]
+    for wpl, grid, cof in ((0, 0, False), (1, 0, False), (4, 0, False), (16, 0, False), (32, 0, False),
+                           (32, 0, True), (8, 64, False)):
+        b = F.Batch(progs, words_per_lane=wpl, grid_blocks=grid, cofactor=cof)
+        dnfs = [torch.full((F.dnf_words(n) + 1,), -1, dtype=torch.int64, device="cuda") for _, n in texts]
+        b.set_dnf_outputs(dnfs)
+        b.set_enum_outputs([None] * len(progs))
+        for rep in range(2):
+            for o in dnfs:
+                o.fill_(-1)
+            counts = host(b.eval_dnf())
+            for (t, n), w, o, c in zip(texts, wants, dnfs, counts):
+                got = host(o)
+                assert np.array_equal(got[:len(w)], w), (wpl, grid, cof, n, rep)
+                assert got[len(w)] == np.uint64(2**64 - 1)
+                assert int(c) == int(np.unpackbits(w.view(np.uint8)).sum()), (wpl, grid, cof, n, rep)
+        b.free()
+
+
 def test_batch_enumerate_needs_outputs(F):
     import torch
     p = F.Program("x1 & x5", 9)
