@@ -67,10 +67,10 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # HBM bytes of one launch of the dominant kernel, from the FETCH_SIZE and
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
 # the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
-# half the bytes copied, WRITE_SIZE all of them): 2 x 4017.8 KiB fetched and
-# 8433405.9 KiB written by k_batch<5, 0, 1> (16 DNF vectors + tile counts).
-# None whenever that kernel has changed since the counters were taken.
-C1_TRAFFIC = (2 * 4017.8 + 8433405.9) * 1024
+# half the bytes copied, WRITE_SIZE all of them), for k_batch_direct<5> (16
+# DNF vectors + tile counts).  None whenever that kernel has changed since the
+# counters were taken.
+C1_TRAFFIC = (2 * 544.7 + 8401970.0) * 1024
 
 
 class ProgramCache:
@@ -246,14 +246,15 @@ def bench_c1(args, torch, fbg):
         "ms_per_step": ms_step,
         "dtype": "u32",
         "config": {"workload": "random 3-CNF model counting, n=32, m=136 (ratio 4.25), seeds 0-15; per step: "
-                               "one batched launch writing the 2^32-bit DNF vector, the count and the per-tile "
-                               "model counts of every instance, then one batched enumeration of all "
-                               "models from the DNF vectors",
+                               "one batched launch writing the 2^32-bit DNF vector and the per-tile model "
+                               "counts of every instance, the counts summed from the tile counts, then one "
+                               "batched enumeration of all models from the DNF vectors",
                    "n": n, "clauses": 136, "instances": len(progs),
                    "words_per_lane": progs[0].info["words_per_lane"]},
         "roofline": {"bound": "hbm", "achieved": dnf_bytes / (k_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": dnf_bytes / (k_ms / 1e3) / HBM_PEAK, "traffic": C1_TRAFFIC,
-                     "kernel": "k_batch MODE_DNF (16 programs: evaluation, DNF write-out, counts)",
+                     "kernel": "k_batch_direct<5> (16 programs: evaluation, DNF write-out, tile counts; "
+                               "with the per-program sums of k_sum_tile_counts in the timed call)",
                      "avg_ms": k_ms, "algorithmic_bytes_per_launch": dnf_bytes,
                      "algorithmic_bitops_per_launch": l2in * float(1 << n),
                      "algorithmic_bitop_rate_T": achieved / 1e12,
