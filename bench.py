@@ -70,7 +70,7 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # half the bytes copied, WRITE_SIZE all of them), for k_batch_direct<5> (16
 # DNF vectors + tile counts).  None whenever that kernel has changed since the
 # counters were taken.
-C1_TRAFFIC = (2 * 544.7 + 8401970.0) * 1024
+C1_TRAFFIC = (2 * 630.2 + 8400173.6) * 1024
 
 
 class ProgramCache:

@@ -81,6 +81,7 @@ struct BatchArgs {
   uint32_t max_regs;      // LDS registers per wave (beyond kVgprRegs)
   uint32_t *head;     // kHeadWords words of queue heads, zeroed before the launch
   uint64_t *counts;   // per slot; the kernel adds to it
+  uint32_t run = 1;   // k_batch_direct: consecutive tiles per wave
 };
 
 enum { EVAL_COUNT = 0, EVAL_DNF = 1, EVAL_TILECNT = 2, EVAL_ENUM = 3 };
@@ -91,7 +92,7 @@ hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hip
 hipError_t launch_batch(int mode, int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds,
                         hipStream_t s);
 // The DNF write-out of a plan of clause-only programs without the cofactor,
-// one wave per tile (a.items: one entry per program, [t0, t1) its tiles in the
+// a.run consecutive tiles per wave (a.items: one entry per program, [t0, t1) its tiles in the
 // plan, ascending; every program has tile counts), then the per-program sums
 // of those tile counts into a.counts (sum_blocks blocks per program).
 hipError_t launch_batch_direct(int log2w, const BatchArgs &a, int grid, int block, int sum_blocks, hipStream_t s);

@@ -710,11 +710,13 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
 }
 
 // Batched DNF write-out of a plan of clause-only programs without the uniform
-// cofactor, one tile per wave on a grid of fresh blocks: the blocks start in
-// order, so the waves write the vectors in order together, and no wave spends
-// a queue pop or a count atomic.  a.items holds the plan's programs, one
-// entry each, with [t0, t1) its tiles in the plan's tile order (ascending,
-// contiguous, a.nitems >= 1); wave g takes plan tile g.  Every program has a
+// cofactor, on a grid of fresh blocks whose waves take a.run consecutive
+// tiles each: the blocks start in order, so the waves write the vectors in
+// order together, and no wave spends a queue pop or a count atomic.  a.items
+// holds the plan's programs, one entry each, with [t0, t1) its tiles in the
+// plan's tile order (ascending, contiguous, a.nitems >= 1); wave w takes plan
+// tiles [w run, (w + 1) run), each tile finding its own program (a run may
+// cross from one program into the next).  Every program has a
 // tile-count array: the tile's model count goes there, and the program's count
 // is the later sum over them (k_sum_tile_counts).
 template <int LOG2W>
@@ -724,26 +726,28 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
   typedef const __attribute__((address_space(4))) BatchProg *prog_ptr;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = uni(threadIdx.x) >> 6;
-  const uint64_t g = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+  const uint64_t g0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wib) * a.run;
   const item_ptr items = (item_ptr)a.items;
-  if (g >= items[a.nitems - 1].t1) return;  // wave-uniform: past the plan's last tile
-  uint32_t lo = 0, hi = a.nitems;            // the entry with t0 <= g < t1
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (items[mid].t0 <= g)
-      lo = mid;
-    else
-      hi = mid;
+  const uint64_t end = items[a.nitems - 1].t1;
+  for (uint64_t g = g0; g < g0 + a.run && g < end; ++g) {  // wave-uniform
+    uint32_t lo = 0, hi = a.nitems;  // the entry with t0 <= g < t1
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (items[mid].t0 <= g)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const item_ptr it = items + lo;
+    const prog_ptr p = (prog_ptr)a.progs + it->prog;
+    const uint64_t t = g - it->t0;
+    const uint64_t U0 = t << LOG2W;
+    uint32_t acc[W];
+    run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, nullptr);
+    const uint32_t c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
+    const uint32_t tc = wave_sum_u32(c);
+    if (lane == 0) p->tile_counts[t] = tc;
   }
-  const item_ptr it = items + lo;
-  const prog_ptr p = (prog_ptr)a.progs + it->prog;
-  const uint64_t t = g - it->t0;
-  const uint64_t U0 = t << LOG2W;
-  uint32_t acc[W];
-  run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, nullptr);
-  const uint32_t c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
-  const uint32_t tc = wave_sum_u32(c);
-  if (lane == 0) p->tile_counts[t] = tc;
 }
 
 // Counts after k_batch_direct: block (m, y) adds its share of the tile counts
