@@ -248,7 +248,11 @@ fbg_status fbg_batch_count_graph(fbg_batch *b, uint64_t *d_counts, void *stream)
  * is pending.  May be called again to change the buffers.
  * fbg_batch_eval_dnf -- for every program i: its DNF vector into d_outs[i]
  *   (layout as fbg_eval_dnf) and d_counts[i] = its number of models
- *   (overwritten), in one persistent launch that computes each word once.
+ *   (overwritten), computing each word once: one launch per plan.  Once the
+ *   tile counts exist (fbg_batch_set_enum_outputs), a plan of clause-only
+ *   programs without the cofactor runs four consecutive tiles per wave on a
+ *   grid of fresh blocks and its counts are summed from the tile counts by a
+ *   second small launch; other plans run persistent waves over work queues.
  *   FBG_E_INVAL if no outputs were set.  Allocates nothing.
  */
 fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, const uint64_t *out_words);
