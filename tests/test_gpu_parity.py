@@ -400,6 +400,20 @@ def test_batch_eval_dnf_writes_every_vector(F):
         b.free()
 
 
+def test_dnf_on_any_grid(F):
+    """The single-program DNF write-out runs one wave per tile by default;
+    an explicit grid (a single block, a few blocks, more than the tiles)
+    strides over the tiles instead, with the same words."""
+    texts = [workloads.random_3cnf(19, 80, 2), workloads.random_dag(17, 250, 9), ("x2 | x15", 21)]
+    for t, n in texts:
+        p = F.Program(t, n)
+        want = oracle.dnf(t, n)
+        for w in (1, 4, 32):
+            for grid in (0, 1, 7, 1 << 20):
+                got = host(F.eval_dnf(p, words_per_lane=w, grid_blocks=grid))
+                assert np.array_equal(got, want), (n, w, grid)
+
+
 def test_dnf_into_offset_views(F):
     """An output that starts 8 bytes past an aligned address (a view into a
     larger buffer) receives the same words, solo and batched, and nothing
