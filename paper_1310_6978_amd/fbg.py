@@ -379,7 +379,9 @@ class Batch:
 
     def eval_dnf(self, counts=None, stream=None):
         """Every program's DNF vector into its output tensor and its count
-        into counts, in one launch (fbg_batch_eval_dnf)."""
+        into counts, computing each word once (fbg_batch_eval_dnf: one launch
+        per plan, plus a sum of tile counts for plans written one run of
+        tiles per wave)."""
         if counts is None:
             counts = _device_u64(len(self._progs))
         _check(lib.fbg_batch_eval_dnf(self._h, _ptr(counts), _stream(stream)))
