@@ -19,12 +19,13 @@ programs resident on the device:
 value = 16 * 2^32 valuations per step / step time.  The JSON line also
 carries the roofline of the dominant kernel (the batched evaluator, measured
 with HIP events on the launch stream: bound by the HBM write of the DNF
-vectors, 1/8 byte per valuation; its integer VALU work is reported beside as
-the algorithmic bit-op rate), the batched versus per-formula ("plain") count
-rates, and the CPU oracle timed on a bounded sample on this host.
+vectors, 1/8 byte per valuation), the batched versus per-formula ("plain")
+count rates, the CPU oracle timed on a bounded sample on this host, and a
+"c3" block: the 4096-formula batch (one batched count per step replayed from
+a HIP graph against 4096 plain launches, and the unspecialized interpreter's
+fraction of the VALU bitwise peak on the programs that have a general part).
 
-Workload c3: 4096 random DAG formulas (n in [10,30], 50..2000 ops), counts
-only, one batched launch per step, compared with 4096 plain launches.
+Workload c3: the same 4096-formula block as the line's workload.
 Workload c4: the serving loop (Poisson arrivals, continuous batching),
 reporting p50/p99 latency beside valuations/s.
 Workload posets: labeled partial orders through the c-partition counting
@@ -68,9 +69,25 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
 # the reading of the same counter for a device copy of 1 GiB (FETCH_SIZE reads
 # half the bytes copied, WRITE_SIZE all of them), for k_batch_direct<5> (16
-# DNF vectors + tile counts).  None whenever that kernel has changed since the
-# counters were taken.
-C1_TRAFFIC = (2 * 630.2 + 8400173.6) * 1024
+# DNF vectors + tile counts), together with the SHA-1 of the kernel sources
+# the counters were taken on.  The bench line reports the bytes only while
+# the sources still have that digest, and null otherwise.
+C1_TRAFFIC = {"bytes": None, "kernel_sources_sha1": None}
+KERNEL_SOURCES = ("kernels.hip", "fbg_isa.h", "fbg_kernels.h")
+
+
+def kernel_sources_sha1():
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1310_6978_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def c1_traffic():
+    if C1_TRAFFIC["bytes"] is None or C1_TRAFFIC["kernel_sources_sha1"] != kernel_sources_sha1():
+        return None
+    return C1_TRAFFIC["bytes"]
 
 
 class ProgramCache:
@@ -252,7 +269,7 @@ def bench_c1(args, torch, fbg):
                    "n": n, "clauses": 136, "instances": len(progs),
                    "words_per_lane": progs[0].info["words_per_lane"]},
         "roofline": {"bound": "hbm", "achieved": dnf_bytes / (k_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": dnf_bytes / (k_ms / 1e3) / HBM_PEAK, "traffic": C1_TRAFFIC,
+                     "unit": "GB/s", "frac": dnf_bytes / (k_ms / 1e3) / HBM_PEAK, "traffic": c1_traffic(),
                      "kernel": "k_batch_direct<5> (16 programs: evaluation, DNF write-out, tile counts; "
                                "with the per-program sums of k_sum_tile_counts in the timed call)",
                      "avg_ms": k_ms, "algorithmic_bytes_per_launch": dnf_bytes,
@@ -269,7 +286,12 @@ def bench_c1(args, torch, fbg):
         "paper_context": PAPER_CONTEXT,
         "cofactor": {"batched_count_ms": cof_ms, "valuations_per_s": vals / (cof_ms / 1e3),
                      "speedup_vs_full_evaluation": batch_ms / cof_ms, "counts_equal": cof_same},
-        "pct_valu_bitwise_peak": 100.0 * achieved / VALU_BITWISE_PEAK,
+        # The clause block factors the clauses over the index classes (one
+        # per-lane product per group of clauses, a product tree over the
+        # words), so this C1 figure is the factored path's algorithmic rate
+        # over the bitwise peak, not a roofline: it exceeds 1.  The
+        # unspecialized interpreter's fraction is c3.general_plans below.
+        "factored_algorithmic_rate_over_valu_peak": achieved / VALU_BITWISE_PEAK,
         "counts": got,
         "bit_exact_vs_oracle": exact,
         "cold_compile_ms_per_program": cold_compile_s * 1e3 / len(progs),
@@ -282,58 +304,97 @@ def bench_c1(args, torch, fbg):
     return res
 
 
-def bench_c3(args, torch, fbg):
+def c3_block(args, torch, fbg):
+    """The 4096 random DAG formulas (n in [10,30], 50..2000 ops, seed 0):
+    one batched count per step replayed from a captured HIP graph, against
+    4096 plain single-program launches; and the unspecialized interpreter's
+    algorithmic fraction: sum of L_2in 2^n over the programs that have a
+    general part (every program operation on every word), over the time of
+    their own batched launch, over the VALU bitwise peak."""
     from workloads.formulas import random_dag_batch
-    batch_f = random_dag_batch(4096, 0)
-    progs = [fbg.Program(t, n) for t, n in batch_f]
-    vals = float(sum(1 << n for _, n in batch_f))
-    l2in = sum(p.info["l2in"] * float(1 << n) for p, (_, n) in zip(progs, batch_f))
     from paper_1310_6978_amd import autotune
+    log = lambda m: print("c3: " + m, file=sys.stderr, flush=True)  # noqa: E731
+    batch_f = random_dag_batch(4096, 0)
+    t0 = time.perf_counter()
+    progs = [fbg.Program(t, n) for t, n in batch_f]
+    compile_ms = (time.perf_counter() - t0) * 1e3
+    vals = float(sum(1 << n for _, n in batch_f))
     tuner = autotune.Tuner()
     wpl = tuner.tune_batch(progs)                       # cached per device and program set
     tuned = tuner.table.get(tuner.last_key, {})
-    print(f"c3: {len(progs)} programs compiled, {wpl} words per lane", file=sys.stderr, flush=True)
+    log("%d programs compiled in %.0f ms, %d words per lane" % (len(progs), compile_ms, wpl))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(args.steps, 3)
     b = fbg.Batch(progs, words_per_lane=wpl)
     counts = torch.empty(len(progs), dtype=torch.int64, device="cuda")
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        b.count(out=counts, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.count(out=counts, stream=stream)
-    torch.cuda.synchronize()
-    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    outs = torch.empty(len(progs), dtype=torch.int64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i, p in enumerate(progs):
-        fbg.count(p, out=outs[i:i + 1], stream=stream)
-        if i % 1024 == 1023:
-            print(f"c3: {i + 1} plain launches", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t0) * 1e3
+    eager_ms = timed(lambda: b.count(out=counts, stream=stream), reps)
+    graph_ms = timed(lambda: b.count(out=counts, stream=stream, graph=True), reps)
     got = counts.cpu().numpy().view("uint64").tolist()
+    outs = torch.empty(len(progs), dtype=torch.int64, device="cuda")
+
+    def plain():
+        for i, p in enumerate(progs):
+            fbg.count(p, out=outs[i:i + 1], stream=stream)
+    plain_ms = timed(plain, 1)
+    log("batched %.2f ms (graph) / %.2f ms (eager), plain %.1f ms" % (graph_ms, eager_ms, plain_ms))
     same = got == outs.cpu().numpy().view("uint64").tolist()
     exact = None
     path = os.path.join(ROOT, "tests", "golden", "c3_dag_batch.json")
     if os.path.exists(path):
         with open(path) as f:
             exact = [r["count"] for r in json.load(f)["formulas"]] == got
-    achieved = l2in / (ms_step / 1e3)
+    # the programs with a general part, as a batch of their own
+    gen = [p for p in progs if p.info["n_instr"] > p.info["n_clause_instr"]]
+    gen_l2in = sum(p.info["l2in"] * 2.0 ** p.n for p in gen)
+    gb = fbg.Batch(gen, words_per_lane=wpl)
+    gout = torch.empty(len(gen), dtype=torch.int64, device="cuda")
+    gen_ms = timed(lambda: gb.count(out=gout, stream=stream), reps)
+    gen_rate = gen_l2in / (gen_ms / 1e3)
+    gb.free()
+    b.free()
+    l2in = sum(p.info["l2in"] * 2.0 ** p.n for p in progs)
     return {
-        "metric": METRIC, "value": vals / (ms_step / 1e3), "unit": "valuations/s", "ms_per_step": ms_step,
+        "formulas": len(progs), "words_per_lane": wpl, "autotune_ms": tuned.get("ms"),
+        "compile_ms": compile_ms,
+        "batched_step_ms_graph": graph_ms, "batched_step_ms_eager": eager_ms,
+        "plain_4096_launches_ms": plain_ms, "speedup_batched_vs_plain": plain_ms / graph_ms,
+        "valuations_per_s": vals / (graph_ms / 1e3),
+        "algorithmic_bitops_per_step": l2in,
+        "general_plans": {"programs": len(gen), "sum_l2in_2n": gen_l2in, "ms": gen_ms,
+                          "algorithmic_rate_T": gen_rate / 1e12,
+                          "frac_of_valu_bitwise_peak": gen_rate / VALU_BITWISE_PEAK},
+        "counts_equal_oracle": exact, "batched_equals_plain": same,
+    }
+
+
+def bench_c3(args, torch, fbg):
+    r = c3_block(args, torch, fbg)
+    ms = r["batched_step_ms_graph"]
+    g = r["general_plans"]
+    return {
+        "metric": METRIC, "value": r["valuations_per_s"], "unit": "valuations/s", "ms_per_step": ms,
         "dtype": "u32",
-        "config": {"workload": "4096 random DAG formulas, n in [10,30], 50-2000 ops, seed 0; "
-                               "per step one batched count (one persistent launch per plan)",
-                   "formulas": len(progs), "words_per_lane": wpl,
-                   "autotune_ms": tuned.get("ms")},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_BITWISE_PEAK / 1e12,
-                     "unit": "Tbitop/s", "frac": achieved / VALU_BITWISE_PEAK, "traffic": None,
-                     "kernel": "k_batch MODE_COUNT (4096 programs)"},
-        "batched_vs_plain": {"batched_ms": ms_step, "plain_ms": plain_ms, "speedup": plain_ms / ms_step,
-                             "batched_equals_plain": same},
-        "bit_exact_vs_oracle": exact,
+        "config": {"workload": "4096 random DAG formulas, n in [10,30], 50-2000 ops, seed 0; per step one "
+                               "batched count replayed from a HIP graph",
+                   "formulas": r["formulas"], "words_per_lane": r["words_per_lane"]},
+        "roofline": {"bound": "alu", "achieved": g["algorithmic_rate_T"], "peak": VALU_BITWISE_PEAK / 1e12,
+                     "unit": "Tbitop/s", "frac": g["frac_of_valu_bitwise_peak"], "traffic": None,
+                     "kernel": "the batched count of the %d programs with a general part" % g["programs"]},
+        "c3": r,
+        "bit_exact_vs_oracle": r["counts_equal_oracle"],
     }
 
 
@@ -573,43 +634,10 @@ def bench_copy(args, torch):
     b.record(stream)
     torch.cuda.synchronize()
     fill_ms = a.elapsed_time(b) / args.steps
-    # the evaluator's DNF store pattern alone (tiles of 8 KiB per wave), over
-    # the same 8 GiB: 4-byte stores of the register rows, 16-byte stores,
-    # and the rows turned into 16-byte stores through LDS; plain and
-    # non-temporal
-    import ctypes
-    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1310_6978_amd", "libfbg_probe.so"))
-    lib.fbg_probe_store_tiles.restype = ctypes.c_int
-    lib.fbg_probe_store_tiles.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
-                                          ctypes.c_uint32, ctypes.c_void_p]
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    ntiles = (8 << 30) // (2048 * 4)
-    tiles = {}
-    forms = ("rows_b32", "b128", "rows_via_lds_b128", "rows_b32_runs_of")
-    runs = [(flags, cus * 8, 1, "") for flags in range(6)]
-    runs += [(flags, cus * 8, r, "_%d_tiles" % r) for r in (4, 8, 32) for flags in (6, 7)]
-    runs += [(flags, ntiles // 4, 1, "_one_tile_per_wave") for flags in (0, 1)]   # a grid of 2^18 blocks
-    for flags, blocks, run, grid in runs:
-        def launch():
-            rc = lib.fbg_probe_store_tiles(ctypes.c_void_p(big.data_ptr()), ntiles, blocks, flags, run,
-                                           ctypes.c_void_p(stream.cuda_stream))
-            if rc != 0:
-                raise RuntimeError("probe launch failed: %d" % rc)
-        launch()
-        torch.cuda.synchronize()
-        a.record(stream)
-        for _ in range(args.steps):
-            launch()
-        b.record(stream)
-        torch.cuda.synchronize()
-        t_ms = a.elapsed_time(b) / args.steps
-        key = forms[flags >> 1] + grid + ("_nontemporal" if flags & 1 else "_plain")
-        tiles[key] = {"ms": t_ms, "gb_per_s": (8 << 30) / (t_ms / 1e3) / 1e9}
     return {"metric": "copy bandwidth (counter calibration)", "value": 2 * nbytes / (ms / 1e3) / 1e9,
             "unit": "GB/s", "ms_per_step": ms, "dtype": "u64",
             "config": {"workload": "device copy of 1 GiB (reads 1 GiB, writes 1 GiB)", "bytes": nbytes},
-            "fill_8GiB": {"ms": fill_ms, "gb_per_s": (8 << 30) / (fill_ms / 1e3) / 1e9},
-            "dnf_store_pattern_8GiB": tiles}
+            "fill_8GiB": {"ms": fill_ms, "gb_per_s": (8 << 30) / (fill_ms / 1e3) / 1e9}}
 
 
 def main():
@@ -621,6 +649,7 @@ def main():
                     choices=["c1", "c3", "c4", "posets", "theories", "unlabeled", "copy", "valu"])
     ap.add_argument("--posets-n", type=int, default=11, help="posets: bounded posets on n elements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="c1: leave out the 4096-formula batch block")
     ap.add_argument("--requests", type=int, default=20000, help="c4: requests in the timed run")
     ap.add_argument("--sat-requests", type=int, default=1000, help="c4: requests of the saturation run")
     ap.add_argument("--load", type=float, default=0.6, help="c4: arrival rate as a fraction of saturation")
@@ -639,6 +668,8 @@ def main():
     from paper_1310_6978_amd import fbg
     if args.workload == "c1":
         res = bench_c1(args, torch, fbg)
+        if not args.no_c3:
+            res["c3"] = c3_block(args, torch, fbg)
     elif args.workload == "c3":
         res = bench_c3(args, torch, fbg)
     elif args.workload == "c4":

@@ -69,7 +69,10 @@ typedef enum {
 typedef struct fbg_program fbg_program; /* opaque, library-owned */
 typedef struct fbg_batch fbg_batch;     /* opaque, library-owned */
 
-typedef struct {
+/* Metadata of a compiled program (Section 2.3 time model: the node count l
+   and the work per valuation).  Used as `struct fbg_program_info`: the tag
+   shares its name with the call fbg_program_info below. */
+struct fbg_program_info {
   int32_t n_vars;        /* n: the valuation space is 2^n */
   int32_t const_value;   /* -1, or 0/1 when the formula folds to a constant */
   uint64_t l2in;         /* 2-input AND/OR/XOR operations of the term after
@@ -85,7 +88,13 @@ typedef struct {
   uint64_t dnf_words;    /* max(1, 2^(n-6)) */
   uint64_t code_bytes;   /* device memory the program holds (0 without a
                             device): all tilings' encodings and tables */
-} fbg_program_info;
+  double l_valu;         /* VALU instructions the evaluator issues per 32-bit
+                            slice (one lane, one word) for this program at
+                            words_per_lane: a static count over the encoded
+                            program (clause block, product tree, general
+                            instructions), per tile divided by the words per
+                            lane; the popcount and store epilogue excluded */
+};
 
 /* Launch tuning.  Zero fields mean "let the library choose". */
 typedef struct {
@@ -166,8 +175,15 @@ fbg_status fbg_compile_subst(const char *src, int32_t n_vars, const int32_t *sub
    make sure no launch that uses it is still pending. */
 void fbg_program_free(fbg_program *p);
 
-/* Metadata of a compiled program (host memory `out`). */
-fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out);
+/*
+ * fbg_program_info -- metadata of a compiled program: n, the node count
+ * L_2in of the time model (Section 2.3), L_valu, registers, tiling, sizes.
+ *   out  host memory, written in full.
+ * FBG_E_INVAL for a NULL argument.  Synchronous; no device work.
+ * fbg_program_get_info is the same call under its earlier name.
+ */
+fbg_status fbg_program_info(const fbg_program *p, struct fbg_program_info *out);
+fbg_status fbg_program_get_info(const fbg_program *p, struct fbg_program_info *out);
 
 /* Make tune->words_per_lane (non-zero) the program's default tiling, and
    tune->flags (FBG_TUNE_COFACTOR) its default evaluation variant, for

@@ -468,7 +468,7 @@ void fbg_program_free(fbg_program *p) {
   delete p;
 }
 
-fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out) {
+fbg_status fbg_program_info(const fbg_program *p, struct fbg_program_info *out) {
   if (!p || !out) return fail(FBG_E_INVAL, "NULL argument");
   memset(out, 0, sizeof *out);
   out->n_vars = p->c.n;
@@ -480,7 +480,13 @@ fbg_status fbg_program_get_info(const fbg_program *p, fbg_program_info *out) {
   out->words_per_lane = 1 << p->auto_log2w;
   out->dnf_words = dnf_words_of(p->c.n);
   out->code_bytes = p->code_bytes;
+  const int l = p->auto_log2w;
+  out->l_valu = fbg::valu_per_slice(p->words[l], p->nins[l], l, (uint32_t)p->c.nregs);
   return FBG_OK;
+}
+
+fbg_status fbg_program_get_info(const fbg_program *p, struct fbg_program_info *out) {
+  return fbg_program_info(p, out);
 }
 
 fbg_status fbg_program_set_tuning(fbg_program *p, const fbg_tune *tune) {

@@ -1067,6 +1067,51 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
   return nins;
 }
 
+double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log2w, uint32_t nregs) {
+  // The per-tile VALU instructions of the kernels, instruction by
+  // instruction of the encoding (kernels.hip, run_clauses / run_general).
+  const uint32_t W = 1u << log2w;
+  if (words.empty()) return 0.0;
+  const uint32_t *cb = words.data();
+  double per_tile = 0;
+  const uint32_t *ch = cb + FBG_CB_HDR;
+  const uint32_t nchunks = cb[1] + cb[2];
+  // a chunk: the tile compare of its clauses (64-bit and, compare), U and the
+  // segmented add of its runs (about 6), then per key a bit extract and a
+  // v_bitop3; first multi chunk keys act on 2^j tree nodes, later ones on W
+  for (uint32_t k = 0; k < nchunks; k++) {
+    const int kind = k < cb[1] ? 0 : k == cb[1] ? 1 : 2;
+    const uint32_t nc = ch[0];
+    per_tile += 8;
+    uint32_t off = (uint32_t)(FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4u;
+    const int nslots = kind == 0 ? 1 + 2 * log2w : kind == 1 ? 2 * (log2w - 1) : 1;
+    for (int sl = 0; sl < nslots; sl++)
+      for (; off < ch[5 + sl]; off += kind == 0 ? 8u : 16u) {
+        per_tile += 2;
+        if (kind == 1) per_tile += (double)(1u << (1 + sl / 2));
+        if (kind == 2) per_tile += W;
+      }
+    ch += ch[1];
+  }
+  if (nchunks) per_tile += 2.0 * W - 2.0;  // the product tree
+  const uint32_t *ins = cb + cb[0];
+  for (uint32_t pc = 0; pc < nins; pc++) {
+    const uint32_t w0 = ins[(size_t)pc * FBG_INS_WORDS];
+    const uint32_t op = w0 & 15u;
+    const uint32_t r = w0 >> FBG_ARG_SHIFT;
+    if (op == FBG_OP_CL || op == FBG_OP_LDL || op == FBG_OP_OPL) {
+      per_tile += 1 + W;  // the lane value of the set, one v_bitop3 per word
+    } else if (op == FBG_OP_ST) {
+      per_tile += r < 4 ? W : 0;  // a VGPR copy; LDS registers are ds_write
+    } else {
+      per_tile += W;  // OPR / LDR / ACC / NOT
+    }
+    if ((op == FBG_OP_ST || op == FBG_OP_ACC || op == FBG_OP_NOT) && (w0 & FBG_INVOUT)) per_tile += W;
+  }
+  (void)nregs;
+  return per_tile / W;
+}
+
 uint32_t leading_clauses(const Compiled &c) {
   // the code generator emits every clause before any other instruction
   uint32_t k = 0;

@@ -59,6 +59,11 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
 // Number of leading clause (CL) instructions; no CL follows them.
 uint32_t leading_clauses(const Compiled &c);
 
+// VALU instructions per 32-bit slice the evaluator issues for an encoded
+// program (a static count per tile, divided by the words per lane; the
+// popcount and store epilogue excluded).
+double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log2w, uint32_t nregs);
+
 // Listing of an encoded program.
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w);
 

@@ -87,8 +87,14 @@
  *      bit 5       HASLANE lanemask != 0
  *      bit 6       INV     second operand inverted (literal set / register)
  *      bit 7       INVOUT  invert cur after the operation
- *      bits 8..9   f       binary function for OPL/OPR: 0 AND, 1 OR, 2 XOR
- *      bits 16..31 pat (literal-set ops) or register index (register ops)
+ *      bits 8..15  tt      LDL/OPL/LDR/OPR: the 8-bit truth table of the
+ *                          v_bitop3_b32 the kernel applies per word, over
+ *                          (cur = 0xF0, lane value T or register = 0xCC,
+ *                          word pattern P(i) = 0xAA), with the operation,
+ *                          the set's inversion and the output inversion
+ *                          folded in (INV / INVOUT are then clear)
+ *      bits 16..31 pattern offset (literal-set ops) or register index
+ *                  (register ops)
  *   w1           mconst
  *   w2, w3       lanemask (lo, hi)
  *   w4, w5       sel (lo, hi)

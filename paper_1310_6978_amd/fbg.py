@@ -8,6 +8,7 @@ not been built, importing this module raises: there is no fallback.
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -39,7 +40,7 @@ class ProgramInfo(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("const_value", ctypes.c_int32), ("l2in", ctypes.c_uint64),
                 ("n_instr", ctypes.c_int32), ("n_regs", ctypes.c_int32), ("n_clause_instr", ctypes.c_int32),
                 ("words_per_lane", ctypes.c_int32), ("dnf_words", ctypes.c_uint64),
-                ("code_bytes", ctypes.c_uint64)]
+                ("code_bytes", ctypes.c_uint64), ("l_valu", ctypes.c_double)]
 
 
 class Tune(ctypes.Structure):
@@ -73,6 +74,7 @@ def _load():
         "fbg_compile_subst": (i32, [ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_int32), i32, u32,
                                     ctypes.POINTER(vp)]),
         "fbg_program_free": (None, [vp]),
+        "fbg_program_info": (i32, [vp, ctypes.POINTER(ProgramInfo)]),
         "fbg_program_get_info": (i32, [vp, ctypes.POINTER(ProgramInfo)]),
         "fbg_program_set_tuning": (i32, [vp, ctypes.POINTER(Tune)]),
         "fbg_eval_dnf": (i32, [vp, vp, u64, vp]),
@@ -110,7 +112,8 @@ def _load():
 lib = _load()
 
 # every symbol include/fbg.h declares
-EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_compile_subst", "fbg_program_free", "fbg_program_get_info", "fbg_program_set_tuning",
+EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_compile_subst", "fbg_program_free", "fbg_program_info",
+            "fbg_program_get_info", "fbg_program_set_tuning",
             "fbg_eval_dnf", "fbg_eval_dnf_tuned",
             "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_dnf", "fbg_batch_create",
             "fbg_batch_count", "fbg_batch_count_graph", "fbg_batch_set_dnf_outputs", "fbg_batch_eval_dnf",
@@ -131,11 +134,57 @@ def _tune(words_per_lane=0, grid_blocks=0, cofactor=False):
     return ctypes.byref(Tune(int(words_per_lane), int(grid_blocks), TUNE_COFACTOR if cofactor else 0, 0))
 
 
-def _stream(stream):
+def _torch_stream(stream):
+    """The torch stream object of `stream` (None: the current stream; an
+    integer: a caller-owned hipStream_t)."""
     import torch
     if stream is None:
-        stream = torch.cuda.current_stream()
-    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        return torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        return stream
+    return torch.cuda.ExternalStream(int(stream))
+
+
+def _stream(stream):
+    return ctypes.c_void_p(_torch_stream(stream).cuda_stream)
+
+
+# Deferred release.  A launch reads a program's code (and a batch its work
+# tables) until it finishes, but the library returns a freed block to its
+# arena at once, where the next compile may overwrite it.  So an object that
+# was launched is not freed directly: free() records an event on every
+# stream it was launched on and parks the handle here; it is released once
+# all those events have completed (checked whenever objects are created or
+# freed).
+_graveyard = []
+
+
+def _sweep():
+    keep = []
+    for release, events, keepalive in _graveyard:
+        if all(e.query() for e in events):
+            release()
+        else:
+            keep.append((release, events, keepalive))
+    _graveyard[:] = keep
+
+
+def _release_after(streams, release, keepalive=()):
+    import torch
+    events = []
+    for s in streams.values():
+        e = torch.cuda.Event()
+        e.record(s)
+        events.append(e)
+    _graveyard.append((release, events, tuple(keepalive)))
+    _sweep()
+
+
+def _used_on(objs, stream):
+    """Note that a launch on `stream` uses every object of `objs`."""
+    s = _torch_stream(stream)
+    for o in objs:
+        o._streams[s.cuda_stream] = s
 
 
 def _ptr(t):
@@ -178,8 +227,11 @@ class Program:
             _check(lib.fbg_compile_assume(src, int(n), a.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                                           int(flags), ctypes.byref(h)))
         self._h = h
+        self._streams = {}
+        self._batches = weakref.WeakSet()   # batches holding this program (their launches read it too)
+        _sweep()
         info = ProgramInfo()
-        _check(lib.fbg_program_get_info(h, ctypes.byref(info)))
+        _check(lib.fbg_program_info(h, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in ProgramInfo._fields_}
         self.n = int(info.n_vars)
 
@@ -190,9 +242,19 @@ class Program:
         return self._h
 
     def free(self):
-        if getattr(self, "_h", None) is not None:
-            lib.fbg_program_free(self._h)
-            self._h = None
+        """Release the program once every launch that used it has finished
+        (launches are asynchronous; see _release_after)."""
+        h = getattr(self, "_h", None)
+        if h is None:
+            return
+        self._h = None
+        streams, self._streams = self._streams, {}
+        for b in list(self._batches):
+            streams.update(b._streams)
+        if streams:
+            _release_after(streams, lambda: lib.fbg_program_free(h))
+        else:
+            lib.fbg_program_free(h)
 
     def __del__(self):
         try:
@@ -206,7 +268,7 @@ class Program:
         t = Tune(int(words_per_lane), 0, TUNE_COFACTOR if cofactor else 0, 0)
         _check(lib.fbg_program_set_tuning(self.handle, ctypes.byref(t)))
         info = ProgramInfo()
-        _check(lib.fbg_program_get_info(self.handle, ctypes.byref(info)))
+        _check(lib.fbg_program_info(self.handle, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in ProgramInfo._fields_}
 
     def emulate(self, words_per_lane=1):
@@ -253,6 +315,7 @@ def eval_dnf(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0, cofac
         _check(lib.fbg_eval_dnf(prog.handle, _ptr(out), out.numel(), _stream(stream)))
     else:
         _check(lib.fbg_eval_dnf_tuned(prog.handle, _ptr(out), out.numel(), tune, _stream(stream)))
+    _used_on([prog], stream)
     return out
 
 
@@ -265,6 +328,7 @@ def count(prog, out=None, stream=None, words_per_lane=0, grid_blocks=0, cofactor
         _check(lib.fbg_count(prog.handle, _ptr(out), _stream(stream)))
     else:
         _check(lib.fbg_count_tuned(prog.handle, _ptr(out), tune, _stream(stream)))
+    _used_on([prog], stream)
     return out
 
 
@@ -277,6 +341,7 @@ def enumerate_models(prog, capacity, out=None, total=None, stream=None):
         total = _device_u64(1)
     ptr = _ptr(out) if capacity > 0 else ctypes.c_void_p(0)
     _check(lib.fbg_enumerate(prog.handle, ptr, int(capacity), _ptr(total), _stream(stream)))
+    _used_on([prog], stream)
     return out, total
 
 
@@ -317,6 +382,7 @@ class Server:
         its = (Item * len(items))(*[Item(int(a), int(b), int(c), int(d)) for a, b, c, d in items])
         _check(lib.fbg_server_launch(self._h, arr, len(progs), its, len(items), _ptr(counts), counts.numel(),
                                      _stream(stream)))
+        _used_on(progs, stream)
 
     def free(self):
         if getattr(self, "_h", None) is not None:
@@ -340,6 +406,9 @@ class Batch:
         _check(lib.fbg_batch_create(arr, len(self._progs), _tune(words_per_lane, grid_blocks, cofactor),
                                     ctypes.byref(h)))
         self._h = h
+        self._streams = {}
+        for p in self._progs:
+            p._batches.add(self)
 
     def __len__(self):
         return len(self._progs)
@@ -351,6 +420,7 @@ class Batch:
             out = _device_u64(len(self._progs))
         f = lib.fbg_batch_count_graph if graph else lib.fbg_batch_count
         _check(f(self._h, _ptr(out), _stream(stream)))
+        _used_on([self], stream)
         return out
 
     def set_dnf_outputs(self, outs):
@@ -376,6 +446,7 @@ class Batch:
         """Models of every program into its enumeration output, ascending
         (after eval_dnf on the same stream)."""
         _check(lib.fbg_batch_enumerate(self._h, _stream(stream)))
+        _used_on([self], stream)
 
     def eval_dnf(self, counts=None, stream=None):
         """Every program's DNF vector into its output tensor and its count
@@ -385,12 +456,21 @@ class Batch:
         if counts is None:
             counts = _device_u64(len(self._progs))
         _check(lib.fbg_batch_eval_dnf(self._h, _ptr(counts), _stream(stream)))
+        _used_on([self], stream)
         return counts
 
     def free(self):
-        if getattr(self, "_h", None) is not None:
-            lib.fbg_batch_free(self._h)
-            self._h = None
+        """Release the plan once its launches have finished; the programs
+        stay alive until then."""
+        h = getattr(self, "_h", None)
+        if h is None:
+            return
+        self._h = None
+        streams = dict(self._streams)   # kept: the programs' own free() still waits for these launches
+        if streams:
+            _release_after(streams, lambda: lib.fbg_batch_free(h), keepalive=self._progs)
+        else:
+            lib.fbg_batch_free(h)
 
     def __del__(self):
         try:

@@ -54,9 +54,26 @@ def test_device_calls_fail_without_device():
 
 def test_null_arguments():
     assert fbg.lib.fbg_count(None, None, None) == fbg.FBG_E_INVAL
+    assert fbg.lib.fbg_program_info(None, None) == fbg.FBG_E_INVAL
     assert fbg.lib.fbg_program_get_info(None, None) == fbg.FBG_E_INVAL
     out = ctypes.c_void_p()
     assert fbg.lib.fbg_compile(None, 3, 0, ctypes.byref(out)) == fbg.FBG_E_INVAL
     assert fbg.lib.fbg_compile(b"x0", 3, 7, ctypes.byref(out)) == fbg.FBG_E_INVAL
     fbg.lib.fbg_program_free(None)
     fbg.lib.fbg_batch_free(None)
+
+
+def test_program_info_through_the_c_abi():
+    """fbg_program_info fills the struct in full: n, L_2in, L_valu, tiling."""
+    info = fbg.ProgramInfo()
+    p = fbg.Program("a = x0 & x1\na ^ x2\nx3 | ~x4", 7)
+    assert fbg.lib.fbg_program_info(p.handle, ctypes.byref(info)) == fbg.FBG_OK
+    assert info.n_vars == 7 and info.l2in == 4 and info.dnf_words == 2
+    assert info.words_per_lane in (1, 2, 4, 8, 16, 32)
+    # one clause (x3 | ~x4) and a general part: at least one VALU
+    # instruction per slice for each of its operations
+    assert 2.0 <= info.l_valu < 40.0
+    old = fbg.ProgramInfo()
+    assert fbg.lib.fbg_program_get_info(p.handle, ctypes.byref(old)) == fbg.FBG_OK
+    assert old.l_valu == info.l_valu and old.l2in == info.l2in
+    assert p.info["l_valu"] == info.l_valu
