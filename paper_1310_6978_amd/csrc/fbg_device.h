@@ -1,4 +1,4 @@
-// kernels.hip -- gfx950 kernels for evaluating Boolean terms on the free
+// fbg_device.h -- gfx950 kernels for evaluating Boolean terms on the free
 // generators (Section 2.3: d_j = t(b_1j .. b_nj) for every block j, each block
 // computed bitwise; 2^r processors act as one 2^(k+r)-bit processor).
 //
@@ -23,6 +23,13 @@
 //   k_scan_*              exclusive scan of per-tile counts
 //   k_zero_*, k_set_u64   fills (used instead of memset so that a caller may
 //                         capture the launches into a graph)
+//
+// The kernel templates live here; each eval_*.hip / batch.hip / misc.hip
+// translation unit instantiates and launches its share of them, so that the
+// library builds in parallel.
+#ifndef FBG_DEVICE_H
+#define FBG_DEVICE_H
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -750,6 +757,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
   }
 }
 
+#ifdef FBG_DEVICE_BATCH_KERNELS  // defined once, in batch.hip
 // Counts after k_batch_direct: block (m, y) adds its share of the tile counts
 // of entry m's program into that program's count slot (zeroed before).
 __global__ __launch_bounds__(256) void k_sum_tile_counts(BatchArgs a) {
@@ -768,6 +776,8 @@ __global__ __launch_bounds__(256) void k_sum_tile_counts(BatchArgs a) {
     if (tot) atomicAdd((unsigned long long *)(a.counts + it.slot), (unsigned long long)tot);
   }
 }
+
+#endif
 
 // Batched enumeration from the stored DNF vectors: every wave strides over
 // the global tile list of all programs (tile counts and their exclusive scan
@@ -807,6 +817,7 @@ __global__ __launch_bounds__(256) void k_batch_compact(BatchEnumArgs a) {
   }
 }
 
+#ifdef FBG_DEVICE_BATCH_KERNELS
 // The global indices of the tiles that hold models, in any order (every
 // tile's output position comes from the scan, not from the list order).
 __global__ __launch_bounds__(256) void k_list_tiles(BatchEnumArgs a) {
@@ -814,6 +825,8 @@ __global__ __launch_bounds__(256) void k_list_tiles(BatchEnumArgs a) {
   for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.total_tiles; g += stride)
     if (a.tile_counts[g] != 0u) a.list[atomicAdd(a.nlist, 1u)] = (uint32_t)g;
 }
+
+#endif
 
 // ------------------------------------------------------------------ scans
 
@@ -837,6 +850,7 @@ __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *s
   return excl;
 }
 
+#ifdef FBG_DEVICE_MISC_KERNELS  // defined once, in misc.hip
 // Per block of SCAN_BLOCK elements: the block's sum.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *in, uint64_t n, uint64_t *block_sums) {
   __shared__ uint64_t sh[SCAN_THREADS];
@@ -893,222 +907,9 @@ __global__ void k_set_u64(uint64_t *p, uint64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+#endif
+
 }  // namespace dev
-
-// ------------------------------------------------------- host-side launches
-
-namespace {
-
-template <int MODE, int VAR>
-hipError_t launch_eval_w(int log2w, const EvalArgs &a, int grid, int block, size_t lds, hipStream_t s) {
-  switch (log2w) {
-    case 0: hipLaunchKernelGGL((dev::k_eval<0, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 1: hipLaunchKernelGGL((dev::k_eval<1, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((dev::k_eval<2, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((dev::k_eval<3, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((dev::k_eval<4, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((dev::k_eval<5, MODE, VAR>), dim3(grid), dim3(block), lds, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <int MODE>
-hipError_t launch_eval_mode(int log2w, int var, const EvalArgs &a, int grid, int block, size_t lds,
-                            hipStream_t s) {
-  switch (var) {
-    case 0: return launch_eval_w<MODE, 0>(log2w, a, grid, block, lds, s);
-    case 1: return launch_eval_w<MODE, 1>(log2w, a, grid, block, lds, s);
-    case 2: return launch_eval_w<MODE, 2>(log2w, a, grid, block, lds, s);
-    case 3: return launch_eval_w<MODE, 3>(log2w, a, grid, block, lds, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int VAR, int MODE>
-hipError_t launch_batch_w(int log2w, const BatchArgs &a, int grid, int block, size_t lds, hipStream_t s) {
-  switch (log2w) {
-    case 0: hipLaunchKernelGGL((dev::k_batch<0, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
-    case 1: hipLaunchKernelGGL((dev::k_batch<1, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
-    case 2: hipLaunchKernelGGL((dev::k_batch<2, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
-    case 3: hipLaunchKernelGGL((dev::k_batch<3, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((dev::k_batch<4, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
-    case 5: hipLaunchKernelGGL((dev::k_batch<5, VAR, MODE>), dim3(grid), dim3(block), lds, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <int MODE>
-hipError_t launch_batch_mode(int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds,
-                             hipStream_t s) {
-  switch (var) {
-    case 0: return launch_batch_w<0, MODE>(log2w, a, grid, block, lds, s);
-    case 1: return launch_batch_w<1, MODE>(log2w, a, grid, block, lds, s);
-    case 2: return launch_batch_w<2, MODE>(log2w, a, grid, block, lds, s);
-    case 3: return launch_batch_w<3, MODE>(log2w, a, grid, block, lds, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-}  // namespace
-
-hipError_t launch_eval(int mode, int log2w, int var, const EvalArgs &a, int grid, int block, size_t lds,
-                       hipStream_t s) {
-  switch (mode) {
-    case dev::MODE_COUNT: return launch_eval_mode<dev::MODE_COUNT>(log2w, var, a, grid, block, lds, s);
-    case dev::MODE_DNF: return launch_eval_mode<dev::MODE_DNF>(log2w, var, a, grid, block, lds, s);
-    case dev::MODE_TILECNT: return launch_eval_mode<dev::MODE_TILECNT>(log2w, var, a, grid, block, lds, s);
-    case dev::MODE_ENUM: return launch_eval_mode<dev::MODE_ENUM>(log2w, var, a, grid, block, lds, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_dnf_scan(int mode, const EvalArgs &a, int grid, int block, hipStream_t s) {
-  if (mode == dev::MODE_TILECNT)
-    hipLaunchKernelGGL((dev::k_dnf_scan<dev::MODE_TILECNT>), dim3(grid), dim3(block), 0, s, a);
-  else if (mode == dev::MODE_ENUM)
-    hipLaunchKernelGGL((dev::k_dnf_scan<dev::MODE_ENUM>), dim3(grid), dim3(block), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_direct(int log2w, const BatchArgs &a, int grid, int block, int sum_blocks, hipStream_t s) {
-  switch (log2w) {
-    case 0: hipLaunchKernelGGL((dev::k_batch_direct<0>), dim3(grid), dim3(block), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((dev::k_batch_direct<1>), dim3(grid), dim3(block), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((dev::k_batch_direct<2>), dim3(grid), dim3(block), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((dev::k_batch_direct<3>), dim3(grid), dim3(block), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((dev::k_batch_direct<4>), dim3(grid), dim3(block), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((dev::k_batch_direct<5>), dim3(grid), dim3(block), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dev::k_sum_tile_counts, dim3(a.nitems, (unsigned)sum_blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch(int mode, int log2w, int var, const BatchArgs &a, int grid, int block, size_t lds,
-                        hipStream_t s) {
-  if (mode == dev::MODE_COUNT) return launch_batch_mode<dev::MODE_COUNT>(log2w, var, a, grid, block, lds, s);
-  if (mode == dev::MODE_DNF) return launch_batch_mode<dev::MODE_DNF>(log2w, var, a, grid, block, lds, s);
-  return hipErrorInvalidValue;
-}
-
-namespace {
-
-int blocks_per_cu(const void *kernel, int block, size_t lds) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, lds) != hipSuccess || nb <= 0) nb = 1;
-  return nb;
-}
-
-template <int MODE, int VAR>
-int eval_occ_w(int log2w, int block, size_t lds) {
-  switch (log2w) {
-    case 0: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<0, MODE, VAR>), block, lds);
-    case 1: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<1, MODE, VAR>), block, lds);
-    case 2: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<2, MODE, VAR>), block, lds);
-    case 3: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<3, MODE, VAR>), block, lds);
-    case 4: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<4, MODE, VAR>), block, lds);
-    default: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_eval<5, MODE, VAR>), block, lds);
-  }
-}
-
-template <int MODE>
-int eval_occ_mode(int log2w, int var, int block, size_t lds) {
-  switch (var) {
-    case 0: return eval_occ_w<MODE, 0>(log2w, block, lds);
-    case 1: return eval_occ_w<MODE, 1>(log2w, block, lds);
-    case 2: return eval_occ_w<MODE, 2>(log2w, block, lds);
-    default: return eval_occ_w<MODE, 3>(log2w, block, lds);
-  }
-}
-
-template <int VAR, int MODE>
-int batch_occ_w(int log2w, int block, size_t lds) {
-  switch (log2w) {
-    case 0: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<0, VAR, MODE>), block, lds);
-    case 1: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<1, VAR, MODE>), block, lds);
-    case 2: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<2, VAR, MODE>), block, lds);
-    case 3: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<3, VAR, MODE>), block, lds);
-    case 4: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<4, VAR, MODE>), block, lds);
-    default: return blocks_per_cu(reinterpret_cast<const void *>(&dev::k_batch<5, VAR, MODE>), block, lds);
-  }
-}
-
-template <int MODE>
-int batch_occ_mode(int log2w, int var, int block, size_t lds) {
-  switch (var) {
-    case 0: return batch_occ_w<0, MODE>(log2w, block, lds);
-    case 1: return batch_occ_w<1, MODE>(log2w, block, lds);
-    case 2: return batch_occ_w<2, MODE>(log2w, block, lds);
-    default: return batch_occ_w<3, MODE>(log2w, block, lds);
-  }
-}
-
-}  // namespace
-
-int eval_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
-  switch (mode) {
-    case dev::MODE_COUNT: return eval_occ_mode<dev::MODE_COUNT>(log2w, var, block, lds);
-    case dev::MODE_DNF: return eval_occ_mode<dev::MODE_DNF>(log2w, var, block, lds);
-    case dev::MODE_TILECNT: return eval_occ_mode<dev::MODE_TILECNT>(log2w, var, block, lds);
-    default: return eval_occ_mode<dev::MODE_ENUM>(log2w, var, block, lds);
-  }
-}
-
-int batch_blocks_per_cu(int mode, int log2w, int var, int block, size_t lds) {
-  if (mode == dev::MODE_DNF) return batch_occ_mode<dev::MODE_DNF>(log2w, var, block, lds);
-  return batch_occ_mode<dev::MODE_COUNT>(log2w, var, block, lds);
-}
-
-hipError_t launch_list_tiles(const BatchEnumArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(dev::k_list_tiles, dim3(grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_compact(int log2w, const BatchEnumArgs &a, int grid, int block, hipStream_t s) {
-  switch (log2w) {
-    case 0: hipLaunchKernelGGL((dev::k_batch_compact<0>), dim3(grid), dim3(block), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((dev::k_batch_compact<1>), dim3(grid), dim3(block), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((dev::k_batch_compact<2>), dim3(grid), dim3(block), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((dev::k_batch_compact<3>), dim3(grid), dim3(block), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((dev::k_batch_compact<4>), dim3(grid), dim3(block), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((dev::k_batch_compact<5>), dim3(grid), dim3(block), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *block_sums, uint64_t *total,
-                       hipStream_t s) {
-  const uint64_t nb = (n + dev::SCAN_BLOCK - 1) / dev::SCAN_BLOCK;
-  if (nb == 0) {
-    hipLaunchKernelGGL(dev::k_set_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)0);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(dev::k_scan_reduce, dim3((unsigned)nb), dim3(dev::SCAN_THREADS), 0, s, in, n, block_sums);
-  hipLaunchKernelGGL(dev::k_scan_sums, dim3(1), dim3(dev::SCAN_THREADS), 0, s, block_sums, nb, total);
-  hipLaunchKernelGGL(dev::k_scan_apply, dim3((unsigned)nb), dim3(dev::SCAN_THREADS), 0, s, in, n, block_sums, out);
-  return hipGetLastError();
-}
-
-uint64_t scan_block_count(uint64_t n) { return (n + dev::SCAN_BLOCK - 1) / dev::SCAN_BLOCK; }
-
-hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, uint32_t nhead, hipStream_t s) {
-  if (!head) nhead = 0;
-  const uint64_t threads = std::max<uint64_t>(std::max<uint64_t>(n, nhead), 1);
-  const unsigned grid = (unsigned)((threads + 255) / 256);
-  hipLaunchKernelGGL(dev::k_zero_u64, dim3(grid), dim3(256), 0, s, p, n, head, nhead);
-  return hipGetLastError();
-}
-
-hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s) {
-  hipLaunchKernelGGL(dev::k_set_u64, dim3(1), dim3(64), 0, s, p, v);
-  return hipGetLastError();
-}
-
 }  // namespace fbg
+
+#endif
