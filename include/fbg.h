@@ -298,6 +298,26 @@ fbg_status fbg_count_batch(const fbg_program *const *ps, int32_t np, uint64_t *d
                            void *stream);
 
 /*
+ * fbg_enumerate_noalloc -- fbg_enumerate for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  Same arguments, outputs, order and errors as
+ * fbg_enumerate, same kernels; the temporaries (per-tile model counts, their
+ * exclusive scan, block sums) live in a static device array of
+ * FBG_NOALLOC_SCRATCH_BYTES on each device (held until the process ends)
+ * instead of a stream-ordered allocation, so the call allocates nothing.
+ * FBG_E_RANGE when the program has more than FBG_NOALLOC_MAX_TILES tiles at
+ * its tiling (64 * words_per_lane 32-bit words per tile: n <= 36 at 32 words
+ * per lane).  Every call on one device shares that device's array: calls
+ * that overlap on one device, on any streams, race and must be serialised
+ * by the caller.  Nothing in the array needs clearing between calls (every
+ * word is written before it is read).
+ */
+#define FBG_NOALLOC_MAX_TILES (1ull << 20)
+#define FBG_NOALLOC_SCRATCH_BYTES ((12ull << 20) + (64ull << 10))
+fbg_status fbg_enumerate_noalloc(const fbg_program *p, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total,
+                                 void *stream);
+
+/*
  * fbg_enumerate_dnf -- the models read off a stored DNF vector (Section 3.2:
  * all models of T* come from b), in ascending order: the same outputs and
  * conventions as fbg_enumerate, for a vector d_dnf of max(1, 2^(n-6)) words

@@ -18,7 +18,8 @@ ARCH = os.environ.get("FBG_OFFLOAD_ARCH", "gfx950")
 
 # The kernel templates are in fbg_device.h; each .hip unit instantiates a
 # share of them so that the units compile in parallel.
-SOURCES = ["eval_count.hip", "eval_dnf.hip", "eval_enum.hip", "batch.hip", "misc.hip", "compiler.cpp", "capi.cpp"]
+SOURCES = ["eval_count.hip", "eval_dnf.hip", "eval_enum.hip", "batch.hip", "misc.hip", "noalloc.hip", "compiler.cpp",
+           "capi.cpp"]
 
 
 def hipcc():

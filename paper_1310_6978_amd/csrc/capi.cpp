@@ -313,25 +313,29 @@ fbg::BatchProg batch_prog(const fbg_program *p, int l) {
   return b;
 }
 
-// Two-pass enumeration given the pass launcher: counts -> scan -> compaction.
+// Bytes of the enumeration temporaries for nt tiles: per-tile uint32 counts,
+// their uint64 exclusive scan and the scan's block sums (each part 256-byte
+// aligned).
+size_t enum_temp_bytes(uint64_t nt, size_t *bytes_cnt, size_t *bytes_off) {
+  *bytes_cnt = ((nt * 4 + 255) / 256) * 256;
+  *bytes_off = ((nt * 8 + 255) / 256) * 256;
+  return *bytes_cnt + *bytes_off + (fbg::scan_block_count(nt) + 1) * 8;
+}
+
+// Two-pass enumeration given the pass launcher and the temporaries `tmp`
+// (enum_temp_bytes(a.ntiles) bytes of device memory): counts -> scan ->
+// compaction.  Every temporary word is written before it is read.
 template <typename Pass>
-fbg_status enumerate_with(fbg::EvalArgs a, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total, hipStream_t s,
-                          Pass pass) {
+hipError_t enumerate_passes(fbg::EvalArgs a, char *tmp, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total,
+                            hipStream_t s, Pass pass) {
   const uint64_t nt = a.ntiles;
-  const uint64_t nb = fbg::scan_block_count(nt);
-  const size_t bytes_cnt = ((nt * 4 + 255) / 256) * 256;
-  const size_t bytes_off = ((nt * 8 + 255) / 256) * 256;
-  const size_t bytes_blk = (nb + 1) * 8;
-  char *tmp = nullptr;
-  hipError_t e = hipMallocAsync((void **)&tmp, bytes_cnt + bytes_off + bytes_blk, s);
-  if (e != hipSuccess)
-    return fail(FBG_E_NOMEM, "hipMallocAsync of %zu bytes: %s", bytes_cnt + bytes_off + bytes_blk,
-                hipGetErrorString(e));
+  size_t bytes_cnt, bytes_off;
+  enum_temp_bytes(nt, &bytes_cnt, &bytes_off);
   uint32_t *cnt = (uint32_t *)tmp;
   uint64_t *off = (uint64_t *)(tmp + bytes_cnt);
   uint64_t *blk = (uint64_t *)(tmp + bytes_cnt + bytes_off);
   a.tile_counts = cnt;
-  e = pass(fbg::EVAL_TILECNT, a);
+  hipError_t e = pass(fbg::EVAL_TILECNT, a);
   if (e == hipSuccess) e = fbg::launch_scan(cnt, nt, off, blk, d_total, s);
   if (e == hipSuccess && capacity > 0) {
     a.tile_offsets = off;
@@ -339,6 +343,19 @@ fbg_status enumerate_with(fbg::EvalArgs a, uint64_t *d_idx, uint64_t capacity, u
     a.capacity = capacity;
     e = pass(fbg::EVAL_ENUM, a);
   }
+  return e;
+}
+
+// The same with the temporaries allocated on the stream and freed after.
+template <typename Pass>
+fbg_status enumerate_with(fbg::EvalArgs a, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total, hipStream_t s,
+                          Pass pass) {
+  size_t bytes_cnt, bytes_off;
+  const size_t bytes = enum_temp_bytes(a.ntiles, &bytes_cnt, &bytes_off);
+  char *tmp = nullptr;
+  hipError_t e = hipMallocAsync((void **)&tmp, bytes, s);
+  if (e != hipSuccess) return fail(FBG_E_NOMEM, "hipMallocAsync of %zu bytes: %s", bytes, hipGetErrorString(e));
+  e = enumerate_passes(a, tmp, d_idx, capacity, d_total, s, pass);
   hipError_t e2 = hipFreeAsync(tmp, s);
   if (e != hipSuccess) return hip_fail(e, "launch of an enumeration kernel");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
@@ -570,6 +587,35 @@ fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacit
                         [&](int mode, const fbg::EvalArgs &a) {
                           return fbg::launch_eval(mode, g.log2w, var, a, g.grid, g.block, g.lds, s);
                         });
+}
+
+fbg_status fbg_enumerate_noalloc(const fbg_program *p, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total,
+                                 void *stream) {
+  fbg_status st = check_program(p);
+  if (st) return st;
+  if (!d_total) return fail(FBG_E_INVAL, "d_total is NULL");
+  if (capacity > 0 && !d_idx)
+    return fail(FBG_E_INVAL, "d_idx is NULL with capacity %llu", (unsigned long long)capacity);
+  Geometry g;
+  if ((st = geometry(p, nullptr, fbg::EVAL_TILECNT, g))) return st;
+  const fbg::EvalArgs a = base_args(p, g.log2w);
+  size_t bytes_cnt, bytes_off;
+  const size_t bytes = enum_temp_bytes(a.ntiles, &bytes_cnt, &bytes_off);
+  if (a.ntiles > fbg::kNoallocMaxTiles || bytes > fbg::kNoallocScratchBytes)
+    return fail(FBG_E_RANGE,
+                "fbg_enumerate_noalloc: %llu tiles at %d words per lane need %zu bytes of scratch; the static "
+                "scratch holds %llu tiles (%llu bytes)",
+                (unsigned long long)a.ntiles, 1 << g.log2w, bytes, (unsigned long long)fbg::kNoallocMaxTiles,
+                (unsigned long long)fbg::kNoallocScratchBytes);
+  void *scratch = nullptr;
+  hipError_t e = fbg::noalloc_scratch(&scratch);
+  if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+  hipStream_t s = (hipStream_t)stream;
+  const int var = p->variant(nullptr);
+  e = enumerate_passes(a, (char *)scratch, d_idx, capacity, d_total, s, [&](int mode, const fbg::EvalArgs &aa) {
+    return fbg::launch_eval(mode, g.log2w, var, aa, g.grid, g.block, g.lds, s);
+  });
+  return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of an enumeration kernel");
 }
 
 fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_idx, uint64_t capacity,

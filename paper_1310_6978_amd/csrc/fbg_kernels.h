@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include "../../include/fbg.h"
+
 namespace fbg {
 
 // Registers of the general part held in VGPRs; the rest live in LDS.
@@ -107,6 +109,15 @@ uint64_t scan_block_count(uint64_t n);
 // p[0..n) = 0 and head[0..nhead) = 0.
 hipError_t launch_zero(uint64_t *p, uint64_t n, uint32_t *head, uint32_t nhead, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
+
+// The scratch of fbg_enumerate_noalloc (noalloc.hip): a static device array
+// of kNoallocScratchBytes per device, enough for the temporaries of an
+// enumeration over at most kNoallocMaxTiles tiles (4-byte tile counts,
+// 8-byte offsets, block sums).
+constexpr uint64_t kNoallocMaxTiles = FBG_NOALLOC_MAX_TILES;
+constexpr uint64_t kNoallocScratchBytes = FBG_NOALLOC_SCRATCH_BYTES;
+// Its device address on the current device (looked up once per device).
+hipError_t noalloc_scratch(void **out);
 
 }  // namespace fbg
 

@@ -82,6 +82,7 @@ def _load():
         "fbg_count": (i32, [vp, vp, vp]),
         "fbg_count_tuned": (i32, [vp, vp, ctypes.POINTER(Tune), vp]),
         "fbg_enumerate": (i32, [vp, vp, u64, vp, vp]),
+        "fbg_enumerate_noalloc": (i32, [vp, vp, u64, vp, vp]),
         "fbg_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(Tune), ctypes.POINTER(vp)]),
         "fbg_batch_count": (i32, [vp, vp, vp]),
         "fbg_batch_count_graph": (i32, [vp, vp, vp]),
@@ -115,7 +116,7 @@ lib = _load()
 EXPORTED = ("fbg_compile", "fbg_compile_assume", "fbg_compile_subst", "fbg_program_free", "fbg_program_info",
             "fbg_program_get_info", "fbg_program_set_tuning",
             "fbg_eval_dnf", "fbg_eval_dnf_tuned",
-            "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_dnf", "fbg_batch_create",
+            "fbg_count", "fbg_count_tuned", "fbg_enumerate", "fbg_enumerate_noalloc", "fbg_enumerate_dnf", "fbg_batch_create",
             "fbg_batch_count", "fbg_batch_count_graph", "fbg_batch_set_dnf_outputs", "fbg_batch_eval_dnf",
             "fbg_batch_set_enum_outputs", "fbg_batch_enumerate",
             "fbg_batch_free", "fbg_count_batch", "fbg_program_tiles", "fbg_server_create",
@@ -341,6 +342,16 @@ def enumerate_models(prog, capacity, out=None, total=None, stream=None):
         total = _device_u64(1)
     ptr = _ptr(out) if capacity > 0 else ctypes.c_void_p(0)
     _check(lib.fbg_enumerate(prog.handle, ptr, int(capacity), _ptr(total), _stream(stream)))
+    _used_on([prog], stream)
+    return out, total
+
+
+def enumerate_models_noalloc(prog, out, total, stream=None):
+    """fbg_enumerate_noalloc: as enumerate_models into caller-given device
+    tensors (out: capacity int64 words, may be empty; total: one word), with
+    the temporaries in the library's static device scratch."""
+    ptr = _ptr(out) if out.numel() > 0 else ctypes.c_void_p(0)
+    _check(lib.fbg_enumerate_noalloc(prog.handle, ptr, int(out.numel()), _ptr(total), _stream(stream)))
     _used_on([prog], stream)
     return out, total
 
