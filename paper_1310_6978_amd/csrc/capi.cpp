@@ -63,8 +63,11 @@ uint64_t tiles_of(uint64_t nslices, int log2w) {
 }
 
 // Registers beyond the first kVgprRegs live in LDS: W*64 words each per wave.
-uint32_t lds_regs(uint32_t nregs) { return nregs > fbg::kVgprRegs ? nregs - fbg::kVgprRegs : 0u; }
-size_t lds_per_wave(uint32_t nregs, int log2w) { return (size_t)lds_regs(nregs) * (64u << log2w) * 4u; }
+uint32_t lds_regs(uint32_t nregs, int log2w) {
+  const uint32_t v = fbg::vgpr_regs_of(log2w);
+  return nregs > v ? nregs - v : 0u;
+}
+size_t lds_per_wave(uint32_t nregs, int log2w) { return (size_t)lds_regs(nregs, log2w) * (64u << log2w) * 4u; }
 
 // Device memory for programs: size classes of powers of two (>= 4 KiB) carved
 // out of 64 MiB chunks and recycled through free lists, so that compiling a
@@ -294,7 +297,7 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   memset(&a, 0, sizeof a);
   a.code = p->d_code + p->dev_off[log2w];
   a.nins = p->nins[log2w];
-  a.nregs = lds_regs((uint32_t)p->c.nregs);
+  a.nregs = lds_regs((uint32_t)p->c.nregs, log2w);
   a.n = p->c.n;
   a.nslices = p->nslices;
   a.ntiles = tiles_of(p->nslices, log2w);
@@ -306,7 +309,7 @@ fbg::BatchProg batch_prog(const fbg_program *p, int l) {
   memset(&b, 0, sizeof b);
   b.code = p->d_code + p->dev_off[l];
   b.nins = p->nins[l];
-  b.nregs = lds_regs((uint32_t)p->c.nregs);
+  b.nregs = lds_regs((uint32_t)p->c.nregs, l);
   b.n = p->c.n;
   b.nslices = p->nslices;
   b.ntiles = tiles_of(p->nslices, l);
@@ -391,10 +394,15 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
   p->nslices = slices_of(p->c.n);
   p->ncl = fbg::leading_clauses(p->c);
   size_t total = 0;
+  std::string enc_err;
   for (int l = 0; l <= kMaxLog2W; l++) {
-    p->nins[l] = fbg::encode_program(p->c, l, p->words[l]);
+    p->nins[l] = fbg::encode_program(p->c, l, p->words[l], &enc_err);
     p->dev_off[l] = total;
     total += p->words[l].size();
+  }
+  if (!enc_err.empty()) {
+    delete p;
+    return fail(FBG_E_RANGE, "%s", enc_err.c_str());
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
@@ -668,12 +676,12 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   std::vector<std::vector<fbg::BatchItem>> plan_items;
   std::vector<std::vector<fbg::BatchItem>> plan_direct;  // per plan: one entry per program (clause-only plans)
   // 0: clause-only programs; 1: general programs whose registers all fit in
-  // VGPRs; 2: up to four registers in LDS; 3: more.  The LDS a plan's widest
+  // VGPRs (at every tiling); 2: up to four registers in LDS; 3: more.  The LDS a plan's widest
   // program needs per wave sets the occupancy of the whole plan, so the few
   // register-hungry programs do not slow down the rest.
   auto group_of = [](const fbg_program *q) {
     if (!q->general()) return 0;
-    const uint32_t r = lds_regs((uint32_t)q->c.nregs);
+    const uint32_t r = lds_regs((uint32_t)q->c.nregs, FBG_J16_LOG2W);
     return r == 0 ? 1 : (r <= 4 ? 2 : 3);
   };
   for (int group = 0; group < 4; group++) {
@@ -758,7 +766,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     pl.block = 64 * wpb;
     pl.lds = lds;
     pl.nitems = (uint32_t)sorted.size();
-    pl.max_regs = lds_regs(max_regs);
+    pl.max_regs = lds_regs(max_regs, l);
     const uint64_t want = (pl.nitems + wpb - 1) / wpb;
     for (int mode : {fbg::EVAL_COUNT, fbg::EVAL_DNF}) {
       uint64_t maxb = (uint64_t)cus * (uint64_t)fbg::batch_blocks_per_cu(mode, l, var, pl.block, lds);
@@ -1139,7 +1147,7 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   a.progs = (const fbg::BatchProg *)dp;
   a.items = (const fbg::BatchItem *)di;
   a.nitems = (uint32_t)npieces;
-  a.max_regs = lds_regs(max_regs);
+  a.max_regs = lds_regs(max_regs, l);
   a.head = sl.d_head;
   a.counts = d_counts;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((npieces + wpb - 1) / wpb, (int64_t)cus * occ));

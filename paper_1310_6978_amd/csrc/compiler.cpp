@@ -823,7 +823,6 @@ SetWords encode_set(const LitSet &ls, int log2w) {
   } else if (ls.inv) {
     s.flags |= FBG_INV;
   }
-  if (s.lanemask) s.flags |= FBG_HASLANE;
   return s;
 }
 
@@ -958,7 +957,122 @@ void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, int ki
 
 }  // namespace
 
-uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words) {
+namespace {
+
+// registers below this one live in VGPRs in the jump-table form
+constexpr uint32_t kJ16V = FBG_J16_VGPR_REGS;
+
+#define FBG_LIST(x) x,
+const uint32_t kJ16Reg[] = {FBG_J16_REG_TABLES(FBG_LIST)};
+const uint32_t kJ16Np[] = {FBG_J16_NP_TABLES(FBG_LIST)};
+const uint32_t kJ16Or[] = {FBG_J16_OR_TABLES(FBG_LIST)};
+const uint32_t kJ16Xor[] = {FBG_J16_XOR_TABLES(FBG_LIST)};
+#undef FBG_LIST
+
+template <size_t N>
+int table_index(const uint32_t (&list)[N], uint32_t tt) {
+  for (size_t k = 0; k < N; k++)
+    if (list[k] == tt) return (int)k;
+  return -1;
+}
+
+// Rewrite the nins instructions at words[at..] into the jump-table form
+// (fbg_isa.h) and close them with END; returns the instructions kept (a NOT
+// with INVOUT, which changes nothing, is dropped).  *err is set when an
+// instruction has no case (the code generator emits none such).
+uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, std::string *err) {
+  std::vector<uint32_t> out;
+  out.reserve((size_t)(nins + 1) * FBG_INS_WORDS);
+  auto missing = [&](const char *what, uint32_t tt) {
+    if (err && err->empty()) *err = std::string("internal: no jump-table case for ") + what + " table " +
+                                    std::to_string(tt);
+  };
+  for (uint32_t k = 0; k < nins; k++) {
+    const uint32_t *g = &words[at + (size_t)k * FBG_INS_WORDS];
+    uint32_t w[FBG_INS_WORDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t op = g[0] & 15u, tt = (g[0] >> FBG_F_SHIFT) & 0xFFu, arg = g[0] >> FBG_ARG_SHIFT;
+    const uint32_t invout = (g[0] & FBG_INVOUT) ? 1u : 0u;
+    uint32_t cs = 0;
+    if (op == FBG_OP_LDL || op == FBG_OP_OPL) {
+      const bool x = (g[0] & FBG_XORSET) != 0;
+      int idx;
+      if (!(g[0] & FBG_HASPAT)) {
+        idx = table_index(kJ16Np, tt & 0x55u);
+        cs = (x ? FBG_J16_LIT_XOR : FBG_J16_LIT_OR) + (uint32_t)idx;
+      } else {
+        idx = x ? table_index(kJ16Xor, tt) : table_index(kJ16Or, tt);
+        cs = (x ? FBG_J16_LIT_XOR_P : FBG_J16_LIT_OR_P) + (uint32_t)idx;
+        w[0] = (arg * 4u) << 16;  // the pattern words' byte offset
+      }
+      if (idx < 0) missing("literal", tt);
+      for (int j = 1; j < FBG_INS_WORDS; j++) w[j] = g[j];
+    } else if (op == FBG_OP_ST) {
+      cs = (arg < kJ16V ? FBG_J16_ST_V : FBG_J16_ST_L) + invout;
+      w[1] = arg < kJ16V ? arg * 16u : (arg - kJ16V) * 4096u;
+    } else if (op == FBG_OP_OPR || op == FBG_OP_LDR) {
+      const int idx = table_index(kJ16Reg, tt);
+      if (idx < 0) missing("register", tt);
+      cs = (arg < kJ16V ? FBG_J16_REG_V : FBG_J16_REG_L) + (uint32_t)idx;
+      w[1] = arg < kJ16V ? arg * 16u : (arg - kJ16V) * 4096u;
+    } else if (op == FBG_OP_ACC) {
+      cs = FBG_J16_ACC + ((g[0] & FBG_INV) ? 1u : 0u) + 2u * invout;
+    } else if (op == FBG_OP_NOT) {
+      if (invout) continue;  // NOT then NOT
+      cs = FBG_J16_NOT;
+    } else {
+      missing("opcode", op);
+    }
+    w[0] |= cs * FBG_J16_SLOT;
+    out.insert(out.end(), w, w + FBG_INS_WORDS);
+  }
+  const uint32_t kept = (uint32_t)(out.size() / FBG_INS_WORDS);
+  out.resize(out.size() + FBG_INS_WORDS, 0u);  // END
+  words.resize(at);
+  words.insert(words.end(), out.begin(), out.end());
+  return kept;
+}
+
+}  // namespace
+
+// One jump-table instruction back in the plain form (the same semantics: an
+// LDL is an OPL whose table ignores cur).  Returns false for END.
+bool from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
+  for (int j = 0; j < FBG_INS_WORDS; j++) g[j] = 0;
+  const uint32_t cs = (w[0] & 0xFFFFu) / FBG_J16_SLOT;
+  if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) return false;
+  if (cs >= FBG_J16_LIT_OR) {
+    uint32_t tt, flags = 0, arg = 0;
+    if (cs >= FBG_J16_LIT_XOR_P) {
+      tt = kJ16Xor[cs - FBG_J16_LIT_XOR_P], flags = FBG_XORSET | FBG_HASPAT;
+    } else if (cs >= FBG_J16_LIT_OR_P) {
+      tt = kJ16Or[cs - FBG_J16_LIT_OR_P], flags = FBG_HASPAT;
+    } else if (cs >= FBG_J16_LIT_XOR) {
+      tt = kJ16Np[cs - FBG_J16_LIT_XOR], flags = FBG_XORSET;
+    } else {
+      tt = kJ16Np[cs - FBG_J16_LIT_OR];
+    }
+    if (flags & FBG_HASPAT) arg = (w[0] >> 16) / 4u;
+    g[0] = FBG_OP_OPL | flags | (tt << FBG_F_SHIFT) | (arg << FBG_ARG_SHIFT);
+    for (int j = 1; j < FBG_INS_WORDS; j++) g[j] = w[j];
+  } else if (cs >= FBG_J16_REG_V) {
+    const bool lds = cs >= FBG_J16_REG_L;
+    const uint32_t tt = kJ16Reg[cs - (lds ? FBG_J16_REG_L : FBG_J16_REG_V)];
+    const uint32_t r = lds ? kJ16V + w[1] / 4096u : w[1] / 16u;
+    g[0] = FBG_OP_OPR | (tt << FBG_F_SHIFT) | (r << FBG_ARG_SHIFT);
+  } else if (cs >= FBG_J16_ST_V) {
+    const bool lds = cs >= FBG_J16_ST_L;
+    const uint32_t r = lds ? kJ16V + w[1] / 4096u : w[1] / 16u;
+    g[0] = FBG_OP_ST | (r << FBG_ARG_SHIFT) | ((cs - (lds ? FBG_J16_ST_L : FBG_J16_ST_V)) ? FBG_INVOUT : 0u);
+  } else if (cs >= FBG_J16_ACC) {
+    const uint32_t v = cs - FBG_J16_ACC;
+    g[0] = FBG_OP_ACC | ((v & 1u) ? FBG_INV : 0u) | ((v & 2u) ? FBG_INVOUT : 0u);
+  } else {
+    g[0] = FBG_OP_NOT;
+  }
+  return true;
+}
+
+uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words, std::string *err) {
   const size_t base = words.size();
   const int W = 1 << log2w;
   const int tile_bit = FBG_TILE_BASE_BIT + log2w;
@@ -1018,10 +1132,24 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
   block[3] = (uint32_t)(stat.size() + multi.size());
   words.insert(words.end(), block.begin(), block.end());
 
-  // ---- the instructions after the clauses
-  const size_t ins_base = words.size();
+  // ---- the instructions after the clauses (the kernels run no CL there: a
+  // clause after other instructions becomes LDL + ACC; the code generator
+  // emits none)
+  std::vector<HIns> gen;
   for (size_t idx = ncl; idx < c.code.size(); idx++) {
-    const HIns &h = c.code[idx];
+    if (c.code[idx].op == FBG_OP_CL) {
+      HIns l = c.code[idx];
+      l.op = FBG_OP_LDL;
+      gen.push_back(l);
+      HIns a;
+      a.op = FBG_OP_ACC;
+      gen.push_back(a);
+    } else {
+      gen.push_back(c.code[idx]);
+    }
+  }
+  const size_t ins_base = words.size();
+  for (const HIns &h : gen) {
     uint32_t w[FBG_INS_WORDS] = {0, 0, 0, 0, 0, 0, 0, 0};
     w[0] = h.op;
     if (h.op == FBG_OP_CL || h.op == FBG_OP_LDL || h.op == FBG_OP_OPL) {
@@ -1029,7 +1157,7 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
       if (h.op == FBG_OP_CL) s.flags &= ~(uint32_t)(FBG_XORSET | FBG_INV);
       // at most 3^5 = 243 entries of at most 32 words: the offset fits 16 bits
       const int e = pattern_entry(pats, s.pat);
-      w[0] |= s.flags | ((uint32_t)(e * W) << FBG_ARG_SHIFT);
+      w[0] |= s.flags | ((uint32_t)(e * W) << FBG_ARG_SHIFT) | (e != 0 ? FBG_HASPAT : 0u);
       w[1] = s.mconst;
       w[2] = (uint32_t)s.lanemask;
       w[3] = (uint32_t)(s.lanemask >> 32);
@@ -1060,7 +1188,8 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
     }
     words.insert(words.end(), w, w + FBG_INS_WORDS);
   }
-  const uint32_t nins = (uint32_t)((words.size() - ins_base) / FBG_INS_WORDS);
+  uint32_t nins = (uint32_t)((words.size() - ins_base) / FBG_INS_WORDS);
+  if (log2w == FBG_J16_LOG2W) nins = to_jump_table(words, ins_base, nins, err);
   for (uint32_t pat : pats)
     for (int i = 0; i < W; i++) words.push_back(((pat >> i) & 1u) ? ~0u : 0u);
   while ((words.size() - base) % 4) words.push_back(0u);
@@ -1095,6 +1224,26 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
   }
   if (nchunks) per_tile += 2.0 * W - 2.0;  // the product tree
   const uint32_t *ins = cb + cb[0];
+  if (log2w == FBG_J16_LOG2W) {
+    // jump-table form: per instruction its case's VALU work
+    for (uint32_t pc = 0; pc < nins; pc++) {
+      const uint32_t cs = (ins[(size_t)pc * FBG_INS_WORDS] & 0xFFFFu) / FBG_J16_SLOT;
+      if (cs >= FBG_J16_LIT_OR) {
+        per_tile += 2 + W;  // the lane value, one v_bitop3 per word
+      } else if (cs >= FBG_J16_REG_V) {
+        per_tile += W + (cs >= FBG_J16_REG_L ? 1 : 0);
+      } else if (cs >= FBG_J16_ST_V) {
+        const bool lds = cs >= FBG_J16_ST_L;
+        per_tile += (lds ? 1 : W) + ((cs - (lds ? FBG_J16_ST_L : FBG_J16_ST_V)) ? W : 0);
+      } else if (cs >= FBG_J16_ACC) {
+        per_tile += W + ((cs - FBG_J16_ACC) >= 2 ? W : 0);
+      } else if (cs == FBG_J16_NOT) {
+        per_tile += W;
+      }
+    }
+    (void)nregs;
+    return per_tile / W;
+  }
   for (uint32_t pc = 0; pc < nins; pc++) {
     const uint32_t w0 = ins[(size_t)pc * FBG_INS_WORDS];
     const uint32_t op = w0 & 15u;
@@ -1124,7 +1273,7 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
   const int W = 1 << log2w;
   const uint32_t *cb = words.data();
   const uint32_t *ins = cb + cb[0];
-  const uint32_t *table = ins + (size_t)nins * FBG_INS_WORDS;
+  const uint32_t *table = ins + FBG_TABLE_OFFSET(nins, log2w);
   char buf[256];
   std::string out = "; words per lane " + std::to_string(W) + "\n";
   snprintf(buf, sizeof buf, "; clause block: %u clauses, %u static chunks, %u multi chunks\n", cb[3], cb[1], cb[2]);
@@ -1170,8 +1319,14 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
     }
     ch += ch[1];
   }
+  if (log2w == FBG_J16_LOG2W) out += "; jump-table form (listed in the plain form's terms)\n";
   for (size_t pc = 0; pc < (size_t)nins * FBG_INS_WORDS; pc += FBG_INS_WORDS) {
+    uint32_t gw[FBG_INS_WORDS];
     const uint32_t *w = &ins[pc];
+    if (log2w == FBG_J16_LOG2W) {
+      if (!from_jump_table(w, gw)) break;
+      w = gw;
+    }
     uint32_t op = w[0] & 15u;
     uint32_t arg = w[0] >> FBG_ARG_SHIFT;
     const char *name = op <= 8 ? ops[op] : "?";
@@ -1284,7 +1439,16 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
   std::vector<uint32_t> R((size_t)nregs + 1, 0);
   const uint32_t *cb = words.data();
   const uint32_t *ins = cb + cb[0];
-  const uint32_t *table = ins + (size_t)nins * FBG_INS_WORDS;
+  const uint32_t *table = ins + FBG_TABLE_OFFSET(nins, log2w);
+  // the jump-table form, read back into the plain form once
+  std::vector<uint32_t> plain;
+  if (log2w == FBG_J16_LOG2W) {
+    uint32_t g[FBG_INS_WORDS];
+    for (uint32_t pc = 0; pc < nins && from_jump_table(&ins[(size_t)pc * FBG_INS_WORDS], g); pc++)
+      plain.insert(plain.end(), g, g + FBG_INS_WORDS);
+    ins = plain.data();
+    nins = (uint32_t)(plain.size() / FBG_INS_WORDS);
+  }
   for (uint64_t s = 0; s < slices; s++) {
     uint32_t lane = (uint32_t)(s & 63u);
     uint64_t U = s >> FBG_LANE_BITS;

@@ -1,0 +1,213 @@
+// fbg_asm16.h -- the general part of a program at 16 words per lane, run as
+// a jump table (the instruction format is the jump-table form of fbg_isa.h).
+//
+// The interpreter of fbg_device.h decides among its cases with a chain of
+// scalar compares and branches, about 25 scalar instructions for the 16 VALU
+// instructions of one program instruction; the scalar unit, which issues no
+// faster than the VALU, then bounds the loop.  Here every instruction carries
+// the byte offset of its case, and one s_setpc_b64 enters the case's code
+// directly (5 scalar instructions).  Each case fetches the next instruction
+// before its VALU work, so the fetch is waited for only at the next dispatch.
+//
+// Register map (fixed; the C++ side sees acc as a pinned in/out operand and
+// every other register below as clobbered):
+//   v14         T, the lane value of a literal set
+//   v15         LDS address
+//   v[16:31]    cur, word i in v[16+i]
+//   v[32:79]    registers 0..2 in VGPRs, register r word i in v[32+16r+i]
+//               (read and written through VGPR index mode, M0 = 16 r)
+//   v[80:95]    a register read back from LDS
+//   v[96:111]   acc
+// leaving v[0:13] and v[112:127] to the compiler for what lives across.
+//   s[48:55]    the current instruction, s[56:71] its pattern words,
+//   s[72:75]    scratch, s[76:77] the jump table base, s[78:79] the jump
+//               target, s80 the instruction offset, s81 the pattern offset,
+//   s83         M0 saved (index mode changes M0; restored on exit)
+// All 64 lanes are active (the kernels call it on full waves).
+#ifndef FBG_ASM16_H
+#define FBG_ASM16_H
+
+#include <stdint.h>
+
+#include "fbg_isa.h"
+
+namespace fbg {
+namespace dev {
+
+typedef uint32_t j16_u32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
+
+#define FBG_J16_STR2(x) #x
+#define FBG_J16_STR(x) FBG_J16_STR2(x)
+#define FBG_J16_W16(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+
+// Fetch the next instruction (32 bytes further) into s[48:55].
+#define FBG_J16_NEXT "s_add_u32 s80, s80, 32\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
+// Wait for it and jump to its case.  The offset is cut to a whole slot and
+// clamped to the slot past the last case, where the interpreter exits: no
+// instruction word can send the jump outside the table.
+#define FBG_J16_DISPATCH                \
+  "s_waitcnt lgkmcnt(0)\n"              \
+  "s_and_b32 s78, s48, 0xff00\n"        \
+  "s_min_u32 s78, s78, 0x4e00\n"        \
+  "s_add_u32 s78, s76, s78\n"           \
+  "s_addc_u32 s79, s77, 0\n"            \
+  "s_setpc_b64 s[78:79]\n"
+// Start of case k: its slot of the table (an .org that moves backwards, i.e.
+// a case longer than its slot, is an assembly error).
+#define FBG_J16_CASE(k) ".org Lc%=+(" FBG_J16_STR(k) ")*256\n"
+
+// per-word bodies
+#define FBG_J16_NOTCUR(i) "v_not_b32 v[16+" #i "], v[16+" #i "]\n"
+#define FBG_J16_ACCAND(i) "v_and_b32 v[96+" #i "], v[96+" #i "], v[16+" #i "]\n"
+#define FBG_J16_ACCANDN(i) "v_bitop3_b32 v[96+" #i "], v[96+" #i "], v[16+" #i "], 0 bitop3:0x30\n"
+#define FBG_J16_STV(i) "v_mov_b32 v[32+" #i "], v[16+" #i "]\n"
+
+// The lane value T (v14) of the current literal set, from its lane mask,
+// in-word constant and tile selectors (fbg_isa.h): OR-sets all-ones where a
+// lane or tile literal holds, else mconst; XOR-sets the lane part XOR mconst
+// XOR the parity of the tile literals.
+#define FBG_J16_T_OR                           \
+  "s_and_b64 s[72:73], %[u0], s[52:53]\n"      \
+  "s_cmp_lg_u64 s[72:73], s[54:55]\n"          \
+  "s_cselect_b64 s[74:75], -1, s[50:51]\n"     \
+  "v_mov_b32 v14, s49\n"                       \
+  "v_cndmask_b32_e64 v14, v14, -1, s[74:75]\n"
+#define FBG_J16_T_XOR                          \
+  "s_and_b64 s[72:73], %[u0], s[52:53]\n"      \
+  "s_bcnt1_i32_b64 s72, s[72:73]\n"            \
+  "s_and_b32 s72, s72, 1\n"                    \
+  "s_sub_i32 s72, 0, s72\n"                    \
+  "s_xor_b32 s72, s72, s49\n"                  \
+  "v_cndmask_b32_e64 v14, 0, -1, s[50:51]\n"   \
+  "v_xor_b32 v14, s72, v14\n"
+// Load the set's 16 pattern words (issued before T is formed).
+#define FBG_J16_PLOAD "s_lshr_b32 s81, s48, 16\n" "s_load_dwordx16 s[56:71], %[tab], s81\n"
+
+// Case bodies parameterised by a truth table TT.
+#define FBG_J16_LITNP_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v14, 0 bitop3:" TT "\n"
+#define FBG_J16_LITP_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v14, s[56+" #i "] bitop3:" TT "\n"
+#define FBG_J16_REGV_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v[32+" #i "], 0 bitop3:" TT "\n"
+#define FBG_J16_REGL_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v[80+" #i "], 0 bitop3:" TT "\n"
+#define FBG_J16_EACH(M, TT)                                                                             \
+  M(0, TT) M(1, TT) M(2, TT) M(3, TT) M(4, TT) M(5, TT) M(6, TT) M(7, TT) M(8, TT) M(9, TT) M(10, TT) \
+  M(11, TT) M(12, TT) M(13, TT) M(14, TT) M(15, TT)
+
+// literal set without word literals: T, fetch, 16 x v_bitop3(cur, T, 0)
+#define FBG_J16_C_LITOR(TT) FBG_J16_T_OR FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
+#define FBG_J16_C_LITXOR(TT) FBG_J16_T_XOR FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
+// with word literals: the pattern words come in with the next instruction
+#define FBG_J16_C_LITORP(TT) \
+  FBG_J16_PLOAD FBG_J16_T_OR "s_waitcnt lgkmcnt(0)\n" FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITP_W, #TT) FBG_J16_DISPATCH
+#define FBG_J16_C_LITXORP(TT) \
+  FBG_J16_PLOAD FBG_J16_T_XOR "s_waitcnt lgkmcnt(0)\n" FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITP_W, #TT) FBG_J16_DISPATCH
+// register in VGPRs: index mode offsets the register operand by 16 r
+#define FBG_J16_C_REGV(TT)                                                                          \
+  "s_set_gpr_idx_on s49, gpr_idx(SRC1)\n" FBG_J16_NEXT "s_nop 1\n" FBG_J16_EACH(FBG_J16_REGV_W, #TT) \
+  "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
+// register in LDS: four 16-byte reads per lane, then the operation
+#define FBG_J16_C_REGL(TT)                                                                \
+  "v_add_u32 v15, s49, %[lb]\n"                                                           \
+  "ds_read_b128 v[80:83], v15\n"                                                         \
+  "ds_read_b128 v[84:87], v15 offset:16\n"                                               \
+  "ds_read_b128 v[88:91], v15 offset:32\n"                                               \
+  "ds_read_b128 v[92:95], v15 offset:48\n" FBG_J16_NEXT "s_waitcnt lgkmcnt(0)\n"         \
+  FBG_J16_EACH(FBG_J16_REGL_W, #TT) FBG_J16_DISPATCH
+
+#define FBG_J16_C_ST_V(INVOUT)                                                                  \
+  "s_set_gpr_idx_on s49, gpr_idx(DST)\n" FBG_J16_NEXT "s_nop 1\n" FBG_J16_W16(FBG_J16_STV)     \
+  "s_set_gpr_idx_off\n" INVOUT FBG_J16_DISPATCH
+#define FBG_J16_C_ST_L(INVOUT)                                                \
+  "v_add_u32 v15, s49, %[lb]\n"                                               \
+  "ds_write_b128 v15, v[16:19]\n"                                             \
+  "ds_write_b128 v15, v[20:23] offset:16\n"                                   \
+  "ds_write_b128 v15, v[24:27] offset:32\n"                                   \
+  "ds_write_b128 v15, v[28:31] offset:48\n" FBG_J16_NEXT INVOUT FBG_J16_DISPATCH
+// cur inverted after a store: the store has read cur first
+#define FBG_J16_INVOUT_CUR FBG_J16_W16(FBG_J16_NOTCUR)
+#define FBG_J16_INVOUT_AFTER_DS "s_waitcnt lgkmcnt(0)\n" FBG_J16_W16(FBG_J16_NOTCUR)
+
+// The cases in table order (case k at Lc + 256 k).
+#define FBG_J16_CASES_REG(MAC, BASE)                                                                         \
+  FBG_J16_CASE(BASE + 0) MAC(0xC0) FBG_J16_CASE(BASE + 1) MAC(0x30) FBG_J16_CASE(BASE + 2) MAC(0xFC)        \
+  FBG_J16_CASE(BASE + 3) MAC(0xF3) FBG_J16_CASE(BASE + 4) MAC(0x3C) FBG_J16_CASE(BASE + 5) MAC(0xC3)        \
+  FBG_J16_CASE(BASE + 6) MAC(0x3F) FBG_J16_CASE(BASE + 7) MAC(0xCF) FBG_J16_CASE(BASE + 8) MAC(0x03)        \
+  FBG_J16_CASE(BASE + 9) MAC(0x0C) FBG_J16_CASE(BASE + 10) MAC(0xCC) FBG_J16_CASE(BASE + 11) MAC(0x33)
+#define FBG_J16_CASES_NP(MAC, BASE)                                                                          \
+  FBG_J16_CASE(BASE + 0) MAC(0x44) FBG_J16_CASE(BASE + 1) MAC(0x11) FBG_J16_CASE(BASE + 2) MAC(0x40)        \
+  FBG_J16_CASE(BASE + 3) MAC(0x10) FBG_J16_CASE(BASE + 4) MAC(0x15) FBG_J16_CASE(BASE + 5) MAC(0x45)        \
+  FBG_J16_CASE(BASE + 6) MAC(0x54) FBG_J16_CASE(BASE + 7) MAC(0x51) FBG_J16_CASE(BASE + 8) MAC(0x01)        \
+  FBG_J16_CASE(BASE + 9) MAC(0x04) FBG_J16_CASE(BASE + 10) MAC(0x14) FBG_J16_CASE(BASE + 11) MAC(0x41)
+#define FBG_J16_CASES_ORP(MAC, BASE)                                                                         \
+  FBG_J16_CASE(BASE + 0) MAC(0xEE) FBG_J16_CASE(BASE + 1) MAC(0x11) FBG_J16_CASE(BASE + 2) MAC(0xE0)        \
+  FBG_J16_CASE(BASE + 3) MAC(0x10) FBG_J16_CASE(BASE + 4) MAC(0x1F) FBG_J16_CASE(BASE + 5) MAC(0xEF)        \
+  FBG_J16_CASE(BASE + 6) MAC(0xFE) FBG_J16_CASE(BASE + 7) MAC(0xF1) FBG_J16_CASE(BASE + 8) MAC(0x01)        \
+  FBG_J16_CASE(BASE + 9) MAC(0x0E) FBG_J16_CASE(BASE + 10) MAC(0x1E) FBG_J16_CASE(BASE + 11) MAC(0xE1)
+#define FBG_J16_CASES_XORP(MAC, BASE)                                                                        \
+  FBG_J16_CASE(BASE + 0) MAC(0x66) FBG_J16_CASE(BASE + 1) MAC(0x99) FBG_J16_CASE(BASE + 2) MAC(0x60)        \
+  FBG_J16_CASE(BASE + 3) MAC(0x9F) FBG_J16_CASE(BASE + 4) MAC(0xF6) FBG_J16_CASE(BASE + 5) MAC(0x09)        \
+  FBG_J16_CASE(BASE + 6) MAC(0x96) FBG_J16_CASE(BASE + 7) MAC(0x69)
+
+// clang-format off
+#define FBG_J16_PROGRAM                                                                                      \
+  "s_mov_b32 s83, m0\n"                                                                                      \
+  "s_getpc_b64 s[76:77]\n"                                                                                   \
+  "Lb%=:\n"                                                                                                  \
+  "s_add_u32 s76, s76, Lc%=-Lb%=\n"                                                                          \
+  "s_addc_u32 s77, s77, 0\n"                                                                                 \
+  "s_mov_b32 s80, 0\n"                                                                                       \
+  "s_load_dwordx8 s[48:55], %[code], s80\n"                                                                  \
+  FBG_J16_DISPATCH                                                                                           \
+  ".p2align 8\n"                                                                                             \
+  "Lc%=:\n"                                                                                                  \
+  FBG_J16_CASE(0)  "s_branch Ld%=\n"                                                                         \
+  FBG_J16_CASE(1)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_NOTCUR) FBG_J16_DISPATCH                                  \
+  FBG_J16_CASE(2)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCAND) FBG_J16_DISPATCH                                  \
+  FBG_J16_CASE(3)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_DISPATCH                                 \
+  FBG_J16_CASE(4)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCAND) FBG_J16_INVOUT_CUR FBG_J16_DISPATCH               \
+  FBG_J16_CASE(5)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_INVOUT_CUR FBG_J16_DISPATCH              \
+  FBG_J16_CASE(6)  FBG_J16_C_ST_V("")                                                                        \
+  FBG_J16_CASE(7)  FBG_J16_C_ST_V(FBG_J16_INVOUT_CUR)                                                        \
+  FBG_J16_CASE(8)  FBG_J16_C_ST_L("")                                                                        \
+  FBG_J16_CASE(9)  FBG_J16_C_ST_L(FBG_J16_INVOUT_AFTER_DS)                                                   \
+  FBG_J16_CASES_REG(FBG_J16_C_REGV, 10)                                                                      \
+  FBG_J16_CASES_REG(FBG_J16_C_REGL, 22)                                                                      \
+  FBG_J16_CASES_NP(FBG_J16_C_LITOR, 34)                                                                      \
+  FBG_J16_CASES_NP(FBG_J16_C_LITXOR, 46)                                                                     \
+  FBG_J16_CASES_ORP(FBG_J16_C_LITORP, 58)                                                                    \
+  FBG_J16_CASES_XORP(FBG_J16_C_LITXORP, 70)                                                                  \
+  FBG_J16_CASE(78)                                                                                           \
+  "Ld%=:\n"                                                                                                  \
+  "s_mov_b32 m0, s83\n"
+// clang-format on
+
+static_assert(FBG_J16_NCASES == 78 && FBG_J16_SLOT == 256,
+              "the case list of FBG_J16_PROGRAM and the clamp 0x4e00 = 78 x 256 of FBG_J16_DISPATCH");
+
+// Run the general part of a program (jump-table form at `code`, its pattern
+// table at `table`) on the 16 words of this lane of tile group U0.  acc comes
+// in as the clause block's value and leaves as the program's.  `lds_lane` is
+// the LDS byte address of this lane's LDS registers (wave base + 64 lane).
+__device__ __forceinline__ void run_general_j16(const uint32_t *code, const uint32_t *table, uint64_t U0,
+                                                uint32_t lds_lane, uint32_t (&acc)[16]) {
+  j16_u32x16 a;
+#pragma unroll
+  for (int i = 0; i < 16; i++) a[i] = acc[i];
+  j16_u32x16 d0, d1, d2, d3, d4;
+  j16_u32x2 d6;
+  const uint64_t c = (uint64_t)code, t = (uint64_t)table;
+  asm volatile(FBG_J16_PROGRAM
+               : "+{v[96:111]}"(a), "=&{v[16:31]}"(d0), "=&{v[32:47]}"(d1), "=&{v[48:63]}"(d2),
+                 "=&{v[64:79]}"(d3), "=&{v[80:95]}"(d4), "=&{v[14:15]}"(d6)
+               : [code] "s"(c), [tab] "s"(t), [u0] "s"(U0), [lb] "v"(lds_lane)
+               : "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60", "s61",
+                 "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75",
+                 "s76", "s77", "s78", "s79", "s80", "s81", "s83", "scc", "memory");
+#pragma unroll
+  for (int i = 0; i < 16; i++) acc[i] = a[i];
+}
+
+}  // namespace dev
+}  // namespace fbg
+
+#endif

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fbg_asm16.h"
 #include "fbg_isa.h"
 #include "fbg_kernels.h"
 
@@ -104,6 +105,23 @@ __device__ __forceinline__ void lit_op(uint32_t tt, uint32_t (&cur)[W], uint32_t
   }
 }
 
+// The same for a literal set without word-index literals (P = 0 on every
+// word): no pattern words are loaded.
+template <int W>
+__device__ __forceinline__ void lit_op0(uint32_t tt, uint32_t (&cur)[W], uint32_t T) {
+  switch (tt) {
+#define FBG_CASE(x)                                                                    \
+  case x:                                                                              \
+    _Pragma("unroll") for (int i = 0; i < W; i++) FBG_BITOP3_INPLACE_2(cur[i], T, x); \
+    break;
+    FBG_LIT_TABLES(FBG_CASE)
+#undef FBG_CASE
+    default:
+#pragma unroll
+      for (int i = 0; i < W; i++) cur[i] = bitop3_any(cur[i], T, 0u, tt);
+  }
+}
+
 template <int W>
 __device__ __forceinline__ void reg_op(uint32_t tt, uint32_t (&cur)[W], const uint32_t (&R)[W]) {
   switch (tt) {
@@ -123,30 +141,39 @@ __device__ __forceinline__ void reg_op(uint32_t tt, uint32_t (&cur)[W], const ui
 // higher ones in LDS, W*64 words each (the launch sizes LDS for those only).
 static_assert(kVgprRegs == 4, "the register switches below name registers 0..3");
 
+// The VGPR state of the general part: cur and the first kVgprRegs
+// registers.  A kernel keeps one per wave across all its tiles and clears it
+// once: every program writes cur and a register before reading them, so a
+// tile needs no reset.
+template <int W>
+struct GenState {
+  uint32_t cur[W];
+  uint32_t rv[kVgprRegs][W];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int i = 0; i < W; i++) cur[i] = 0u;
+#pragma unroll
+    for (uint32_t r = 0; r < kVgprRegs; r++)
+#pragma unroll
+      for (int i = 0; i < W; i++) rv[r][i] = 0u;
+  }
+};
+
 template <int LOG2W>
 __device__ __forceinline__ void run_general(code_ptr w, const code_ptr table, uint32_t nins, uint64_t U0,
                                             uint32_t lane, uint32_t (&acc)[1 << LOG2W],
-                                            uint32_t *__restrict__ regs) {
+                                            GenState<1 << LOG2W> &st, uint32_t *__restrict__ regs) {
   constexpr int W = 1 << LOG2W;
-  uint32_t cur[W], rv[kVgprRegs][W], tmp[W];
-#pragma unroll
-  for (int i = 0; i < W; i++) cur[i] = 0u;
-#pragma unroll
-  for (uint32_t r = 0; r < kVgprRegs; r++)
-#pragma unroll
-    for (int i = 0; i < W; i++) rv[r][i] = 0u;
+  uint32_t (&cur)[W] = st.cur;
+  uint32_t tmp[W];
   for (uint32_t pc = 0; pc < nins; ++pc, w += FBG_INS_WORDS) {
     const u32x8 ins = *(const __attribute__((address_space(4))) u32x8 *)w;
     const uint32_t w0 = ins[0];
     const uint32_t op = w0 & 15u;
     const uint32_t tt = (w0 >> FBG_F_SHIFT) & 0xFFu;
-    if (op <= FBG_OP_OPL) {
+    if (op <= FBG_OP_OPL) {  // LDL / OPL (the encoder keeps CL in the clause block)
       const uint64_t lm = (uint64_t)ins[2] | ((uint64_t)ins[3] << 32);
       const uint64_t sel = (uint64_t)ins[4] | ((uint64_t)ins[5] << 32);
-      const code_ptr Pp = table + (w0 >> FBG_ARG_SHIFT);
-      uint32_t P[W];
-#pragma unroll
-      for (int i = 0; i < W; i++) P[i] = Pp[i];
       uint32_t T;
       if (!(w0 & FBG_XORSET)) {
         const uint64_t neg = (uint64_t)ins[6] | ((uint64_t)ins[7] << 32);
@@ -156,12 +183,15 @@ __device__ __forceinline__ void run_general(code_ptr w, const code_ptr table, ui
         const uint32_t S = ins[1] ^ ((__popcll(U0 & sel) & 1) ? ~0u : 0u);
         T = lane_part(lm) ^ S;
       }
-      if (op == FBG_OP_CL) {  // a clause after other instructions (the compiler emits none)
+      if (w0 & FBG_HASPAT) {
+        const code_ptr Pp = table + (w0 >> FBG_ARG_SHIFT);
+        uint32_t P[W];
 #pragma unroll
-        for (int i = 0; i < W; i++) acc[i] = __builtin_amdgcn_bitop3_b32(T, acc[i], P[i], kTT_AND_OR);
-        continue;
+        for (int i = 0; i < W; i++) P[i] = Pp[i];
+        lit_op<W>(tt, cur, T, P);
+      } else {
+        lit_op0<W>(tt, cur, T);
       }
-      lit_op<W>(tt, cur, T, P);
       continue;
     }
     const uint32_t r = w0 >> FBG_ARG_SHIFT;
@@ -170,7 +200,7 @@ __device__ __forceinline__ void run_general(code_ptr w, const code_ptr table, ui
         switch (r) {
 #define FBG_ST(k) \
   case k:         \
-    _Pragma("unroll") for (int i = 0; i < W; i++) rv[k][i] = cur[i]; \
+    _Pragma("unroll") for (int i = 0; i < W; i++) st.rv[k][i] = cur[i]; \
     break;
           FBG_ST(0) FBG_ST(1) FBG_ST(2) FBG_ST(3)
 #undef FBG_ST
@@ -180,14 +210,18 @@ __device__ __forceinline__ void run_general(code_ptr w, const code_ptr table, ui
             for (int i = 0; i < W; i++) R[i * 64] = cur[i];
           }
         }
+        if (w0 & FBG_INVOUT) {
+#pragma unroll
+          for (int i = 0; i < W; i++) cur[i] = ~cur[i];
+        }
         break;
       case FBG_OP_OPR:
       case FBG_OP_LDR:
         switch (r) {
-          case 0: reg_op<W>(tt, cur, rv[0]); break;
-          case 1: reg_op<W>(tt, cur, rv[1]); break;
-          case 2: reg_op<W>(tt, cur, rv[2]); break;
-          case 3: reg_op<W>(tt, cur, rv[3]); break;
+          case 0: reg_op<W>(tt, cur, st.rv[0]); break;
+          case 1: reg_op<W>(tt, cur, st.rv[1]); break;
+          case 2: reg_op<W>(tt, cur, st.rv[2]); break;
+          case 3: reg_op<W>(tt, cur, st.rv[3]); break;
           default: {
             const uint32_t *R = regs + (size_t)(r - kVgprRegs) * (W * 64) + lane;
 #pragma unroll
@@ -204,15 +238,17 @@ __device__ __forceinline__ void run_general(code_ptr w, const code_ptr table, ui
 #pragma unroll
           for (int i = 0; i < W; i++) acc[i] &= cur[i];
         }
-        break;
-      default:  // FBG_OP_NOT
+        if (w0 & FBG_INVOUT) {
 #pragma unroll
-        for (int i = 0; i < W; i++) cur[i] = ~cur[i];
+          for (int i = 0; i < W; i++) cur[i] = ~cur[i];
+        }
         break;
-    }
-    if (w0 & FBG_INVOUT) {  // ST / ACC / NOT only: the encoder folds it into the table elsewhere
+      default:  // FBG_OP_NOT; an INVOUT on it (a folded second NOT) cancels it
+        if (!(w0 & FBG_INVOUT)) {
 #pragma unroll
-      for (int i = 0; i < W; i++) cur[i] = ~cur[i];
+          for (int i = 0; i < W; i++) cur[i] = ~cur[i];
+        }
+        break;
     }
   }
 }
@@ -394,13 +430,20 @@ __device__ __forceinline__ void for_tiles(const uint32_t *__restrict__ code, uin
 template <int LOG2W, bool GEN>
 __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g, uint32_t nins, uint64_t U0,
                                             uint32_t lane, uint32_t (&acc)[1 << LOG2W],
-                                            uint32_t *__restrict__ regs) {
+                                            GenState<1 << LOG2W> &st, uint32_t *__restrict__ regs) {
   const code_ptr cb = (code_ptr)code_g;
   const code_ptr ins = cb + cb[0];
-  const code_ptr table = ins + (size_t)nins * FBG_INS_WORDS;
+  const code_ptr table = ins + FBG_TABLE_OFFSET(nins, LOG2W);
   run_clauses<LOG2W>(code_g, table, U0, lane, acc);
   if (!GEN) return;
-  run_general<LOG2W>(ins, table, nins, U0, lane, acc, regs);
+  if constexpr (LOG2W == FBG_J16_LOG2W) {
+    // the jump-table form; LDS registers at this wave's block, 64 bytes a lane
+    const uint32_t lds_lane =
+        (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint32_t *)regs) + lane * 64u;
+    run_general_j16((const uint32_t *)(uintptr_t)ins, (const uint32_t *)(uintptr_t)table, U0, lds_lane, acc);
+  } else {
+    run_general<LOG2W>(ins, table, nins, U0, lane, acc, st, regs);
+  }
 }
 
 // Zero the words of this lane that lie beyond the valuation space.
@@ -571,6 +614,8 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
   const uint64_t wave = (uint64_t)blockIdx.x * wpb + wib;
   const uint64_t nwaves = (uint64_t)gridDim.x * wpb;
   uint64_t total = 0;
+  GenState<W> st;
+  if (VAR & 1) st.clear();
   // dead tiles (uniform cofactor) still write their zeros in DNF and
   // tile-count modes; counting and compaction skip them
   constexpr bool ALL = MODE == MODE_DNF || MODE == MODE_TILECNT;
@@ -581,7 +626,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
     }
     uint32_t acc[W];
     if (alive) {
-      run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, regs);
+      run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, st, regs);
       mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);
     } else {
 #pragma unroll
@@ -659,6 +704,8 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
   // that program, not once per item: same-address device atomics serialize.
   uint64_t total = 0;
   uint32_t cur_slot = ~0u;
+  GenState<W> st;
+  if (VAR & 1) st.clear();
   auto process = [&](uint32_t item) {
     const item_ptr it = (item_ptr)a.items + item;
     const uint64_t t0 = it->t0, t1 = it->t1, step = it->step;
@@ -674,7 +721,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
       if (alive) {
-        run_program<LOG2W, (VAR & 1) != 0>(p->code, p->nins, U0, lane, acc, regs);
+        run_program<LOG2W, (VAR & 1) != 0>(p->code, p->nins, U0, lane, acc, st, regs);
       } else {
 #pragma unroll
         for (int i = 0; i < W; i++) acc[i] = 0u;
@@ -750,7 +797,8 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
     const uint64_t t = g - it->t0;
     const uint64_t U0 = t << LOG2W;
     uint32_t acc[W];
-    run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, nullptr);
+    GenState<W> st;  // unused: clause-only programs
+    run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, st, nullptr);
     const uint32_t c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
     const uint32_t tc = wave_sum_u32(c);
     if (lane == 0) p->tile_counts[t] = tc;

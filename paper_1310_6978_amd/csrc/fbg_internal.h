@@ -52,9 +52,11 @@ int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int
                     const int32_t *subst = nullptr, int n_free = 0);
 
 // Encode for words-per-lane 2^log2w (W <= 32).  Appends the clause block,
-// FBG_INS_WORDS words per instruction after it, then the pattern table (a
-// multiple of 4 words in all); returns the instruction count.
-uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words);
+// FBG_INS_WORDS words per instruction after it (the jump-table form at
+// 16 words per lane, closed by END), then the pattern table (a multiple of 4
+// words in all); returns the instruction count.  *err (if given) is set when
+// the program cannot be encoded.
+uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words, std::string *err = nullptr);
 
 // Number of leading clause (CL) instructions; no CL follows them.
 uint32_t leading_clauses(const Compiled &c);

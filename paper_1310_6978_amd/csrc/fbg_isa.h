@@ -84,7 +84,8 @@
  * Instruction: 8 x uint32.
  *   w0 bits 0..3   opcode
  *      bit 4       XORSET  literal set combines with XOR (else OR)
- *      bit 5       HASLANE lanemask != 0
+ *      bit 5       HASPAT  the literal set has word-index literals: the
+ *                          kernel loads its W pattern words (else P = 0)
  *      bit 6       INV     second operand inverted (literal set / register)
  *      bit 7       INVOUT  invert cur after the operation
  *      bits 8..15  tt      LDL/OPL/LDR/OPR: the 8-bit truth table of the
@@ -111,6 +112,24 @@
  * is all zeros.  An operation reads its W values with scalar loads instead of
  * extracting W bits.  Per-word patterns are ORs of literals over the log2 W
  * word-index bits, so there are at most 3^(log2 W) <= 243 of them.
+ *
+ * Jump-table form (16 words per lane only).  At 16 words per lane the
+ * instructions after the clause block use another encoding, run by an
+ * interpreter that jumps straight to the code of each instruction instead of
+ * deciding among the cases with a chain of compares (kernels: fbg_asm16.h).
+ * Still 8 x uint32 per instruction:
+ *   w0 bits 0..15   byte offset of the instruction's case in the jump table
+ *                   (case number x FBG_J16_SLOT)
+ *      bits 16..31  literal sets with word-index literals: byte offset of
+ *                   their 16 pattern words in the pattern table
+ *   w1           literal sets: mconst; register ops: the register's place,
+ *                r x 16 for VGPR registers (r < 3: a VGPR index offset),
+ *                (r - 3) x 4096 for LDS registers (a byte offset)
+ *   w2..w7       literal sets: lanemask, sel, neg as above
+ * The case fixes the operation and its truth table; the cases are listed
+ * below (FBG_J16_*).  A case END follows the last instruction, and the
+ * pattern table starts after it.  LDS registers hold a lane's 16 words
+ * contiguously (64 bytes per lane, 4096 per register and wave).
  */
 #ifndef FBG_ISA_H
 #define FBG_ISA_H
@@ -127,7 +146,7 @@
 #define FBG_OP_NOT 8u
 
 #define FBG_XORSET (1u << 4)
-#define FBG_HASLANE (1u << 5)
+#define FBG_HASPAT (1u << 5)
 #define FBG_INV (1u << 6)
 #define FBG_INVOUT (1u << 7)
 #define FBG_F_SHIFT 8
@@ -137,12 +156,40 @@
 #define FBG_ARG_SHIFT 16
 
 #define FBG_INS_WORDS 8
+/* Words per lane of the jump-table form, and where the pattern table starts
+   (in words after the first instruction): after the nins instructions, and
+   after the END that closes them in the jump-table form. */
+#define FBG_J16_LOG2W 4
+#define FBG_J16_VGPR_REGS 3   /* registers 0..2 in VGPRs, the rest in LDS */
+#define FBG_TABLE_OFFSET(nins, log2w) (((nins) + ((log2w) == FBG_J16_LOG2W ? 1u : 0u)) * FBG_INS_WORDS)
 #define FBG_CB_HDR 4        /* words of the clause-block header */
 #define FBG_CB_CHUNK 32     /* clauses per chunk */
 #define FBG_CB_CHUNK_HDR 16 /* words of a chunk header */
 #define FBG_LANE_BITS 6  /* 64 lanes per wave */
 #define FBG_SLICE_BITS 5 /* 32 valuations per word */
 #define FBG_TILE_BASE_BIT (FBG_SLICE_BITS + FBG_LANE_BITS) /* 11 */
+
+/* Jump-table form: case numbers; each case's code fills one slot of
+   FBG_J16_SLOT bytes. */
+#define FBG_J16_SLOT 256u
+#define FBG_J16_END 0u          /* leave the interpreter */
+#define FBG_J16_NOT 1u          /* cur = ~cur */
+#define FBG_J16_ACC 2u          /* + (INV ? 1 : 0) + (INVOUT ? 2 : 0): acc &= cur (^ ~0) */
+#define FBG_J16_ST_V 6u         /* + (INVOUT ? 1 : 0): R[r] = cur, r < 4 */
+#define FBG_J16_ST_L 8u         /* + (INVOUT ? 1 : 0): R[r] = cur, r >= 4 */
+#define FBG_J16_REG_V 10u       /* + table index (FBG_J16_REG_TABLES): cur = tt(cur, R[r]) */
+#define FBG_J16_REG_L 22u
+#define FBG_J16_LIT_OR 34u      /* OR-set, no word literal: + index in FBG_J16_NP_TABLES */
+#define FBG_J16_LIT_XOR 46u     /* XOR-set, no word literal: + index in FBG_J16_NP_TABLES */
+#define FBG_J16_LIT_OR_P 58u    /* OR-set with word literals: + index in FBG_J16_OR_TABLES */
+#define FBG_J16_LIT_XOR_P 70u   /* XOR-set with word literals: + index in FBG_J16_XOR_TABLES */
+#define FBG_J16_NCASES 78u
+/* Truth tables of the cases, over (cur = 0xF0, T or R = 0xCC, P = 0xAA).
+   Without word literals P is 0, so only the bits of 0x55 matter. */
+#define FBG_J16_REG_TABLES(X) X(0xC0) X(0x30) X(0xFC) X(0xF3) X(0x3C) X(0xC3) X(0x3F) X(0xCF) X(0x03) X(0x0C) X(0xCC) X(0x33)
+#define FBG_J16_NP_TABLES(X) X(0x44) X(0x11) X(0x40) X(0x10) X(0x15) X(0x45) X(0x54) X(0x51) X(0x01) X(0x04) X(0x14) X(0x41)
+#define FBG_J16_OR_TABLES(X) X(0xEE) X(0x11) X(0xE0) X(0x10) X(0x1F) X(0xEF) X(0xFE) X(0xF1) X(0x01) X(0x0E) X(0x1E) X(0xE1)
+#define FBG_J16_XOR_TABLES(X) X(0x66) X(0x99) X(0x60) X(0x9F) X(0xF6) X(0x09) X(0x96) X(0x69)
 
 /* In-word generator masks: bit j of MASK_k is bit k of j (Section 2.2). */
 static inline uint32_t fbg_inword_mask(int k) {

@@ -6,16 +6,21 @@
 #include <stdint.h>
 
 #include "../../include/fbg.h"
+#include "fbg_isa.h"
 
 namespace fbg {
 
-// Registers of the general part held in VGPRs; the rest live in LDS.
+// Registers of the general part held in VGPRs; the rest live in LDS.  The
+// jump-table interpreter at 16 words per lane keeps three (its fixed register
+// map leaves room for no more without spilling).
 constexpr uint32_t kVgprRegs = 4;
+constexpr uint32_t kJ16VgprRegs = FBG_J16_VGPR_REGS;
+inline uint32_t vgpr_regs_of(int log2w) { return log2w == FBG_J16_LOG2W ? kJ16VgprRegs : kVgprRegs; }
 
 struct EvalArgs {
   const uint32_t *code;   // encoded program: clause block, instructions, pattern table
   uint32_t nins;          // instructions after the clause block
-  uint32_t nregs;         // registers held in LDS (beyond kVgprRegs)
+  uint32_t nregs;         // registers held in LDS (beyond vgpr_regs_of(log2w))
   int32_t n;              // variables
   uint64_t nslices;       // 2^max(n-5, 0) valid 32-bit words
   uint64_t ntiles;        // ceil(nslices / (64 W))
@@ -80,7 +85,7 @@ struct BatchArgs {
   const BatchProg *progs;
   const BatchItem *items;
   uint32_t nitems;
-  uint32_t max_regs;      // LDS registers per wave (beyond kVgprRegs)
+  uint32_t max_regs;      // LDS registers per wave (beyond vgpr_regs_of(log2w))
   uint32_t *head;     // kHeadWords words of queue heads, zeroed before the launch
   uint64_t *counts;   // per slot; the kernel adds to it
   uint32_t run = 1;   // k_batch_direct: consecutive tiles per wave
