@@ -41,6 +41,10 @@ constexpr size_t kMaxLdsPerBlock = 64 * 1024;
 // plan (C1, 16 x 2^32 bits at W = 32: 1.45-1.46 ms at 4, 1.48 at 1, 1.58 at 2
 // and 1.59 at 8).
 constexpr uint32_t kDirectRun = 4;
+// LDS registers a wave of a batch plan keeps at 16 words per lane (4 KiB
+// each): four waves a block then take 32 KiB, so LDS allows the four blocks
+// per CU that the registers of the jump-table interpreter allow.
+constexpr uint32_t kJ16LdsRegs = 2;
 
 int g_cu_count[64];
 std::once_flag g_cu_once[64];
@@ -177,6 +181,10 @@ struct fbg_batch {
     fbg::BatchItem *d_direct = nullptr;
     uint32_t ndirect = 0;
     uint64_t ntiles = 0, max_prog_tiles = 0;
+    // jump-table form (16 words per lane): registers beyond the plan's LDS
+    // registers, gstride words per wave of the grid
+    uint32_t *d_gscratch = nullptr;
+    uint64_t gstride = 0;
   };
   int device = -1;
   int32_t np = 0;
@@ -679,7 +687,16 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   // VGPRs (at every tiling); 2: up to four registers in LDS; 3: more.  The LDS a plan's widest
   // program needs per wave sets the occupancy of the whole plan, so the few
   // register-hungry programs do not slow down the rest.
-  auto group_of = [](const fbg_program *q) {
+  // At 16 words per lane (the jump-table form) a plan keeps at most
+  // kJ16LdsRegs registers of a wave in LDS and the rest in global scratch,
+  // so the register count no longer limits occupancy: when the tuning fixes
+  // that tiling and some program has a general part, every program goes into
+  // one plan, one persistent launch.
+  bool any_general = false;
+  for (int32_t i = 0; i < np; i++) any_general = any_general || ps[i]->general();
+  const bool one_plan = fixed_l == FBG_J16_LOG2W && any_general;
+  auto group_of = [one_plan](const fbg_program *q) {
+    if (one_plan) return 1;
     if (!q->general()) return 0;
     const uint32_t r = lds_regs((uint32_t)q->c.nregs, FBG_J16_LOG2W);
     return r == 0 ? 1 : (r <= 4 ? 2 : 3);
@@ -708,13 +725,25 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
       var |= ps[i]->variant(tune);
     }
-    while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
-    // LDS registers: keep a block of 4 waves within 32 KiB (5 blocks per CU)
-    if (fixed_l < 0)
-      while (l > 0 && lds_per_wave(max_regs, l) * kWavesPerBlock > kMaxLdsPerBlock / 2) l--;
+    if (one_plan) var |= 1;  // clause-only programs run in the general kernel too
+    // registers that stay in LDS, the rest (jump-table form only) in global
+    // scratch, gstride words per wave
+    uint32_t lds_keep = lds_regs(max_regs, l < 0 ? 0 : l);
+    uint64_t gstride = 0;
+    if (l == FBG_J16_LOG2W && lds_keep > kJ16LdsRegs) {
+      gstride = (uint64_t)(lds_keep - kJ16LdsRegs) * (64u << l);
+      lds_keep = kJ16LdsRegs;
+    }
+    if (gstride == 0) {
+      while (l > 0 && lds_per_wave(max_regs, l) > kMaxLdsPerBlock) l--;
+      // LDS registers: keep a block of 4 waves within 32 KiB (5 blocks per CU)
+      if (fixed_l < 0)
+        while (l > 0 && lds_per_wave(max_regs, l) * kWavesPerBlock > kMaxLdsPerBlock / 2) l--;
+      lds_keep = lds_regs(max_regs, l);
+    }
     int wpb;
     size_t lds;
-    if ((st = block_shape(max_regs, l, wpb, lds))) {
+    if ((st = block_shape(lds_keep + fbg::vgpr_regs_of(l), l, wpb, lds))) {
       fbg_batch_free(b);
       return st;
     }
@@ -766,7 +795,8 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     pl.block = 64 * wpb;
     pl.lds = lds;
     pl.nitems = (uint32_t)sorted.size();
-    pl.max_regs = lds_regs(max_regs, l);
+    pl.max_regs = lds_keep;
+    pl.gstride = gstride;
     const uint64_t want = (pl.nitems + wpb - 1) / wpb;
     for (int mode : {fbg::EVAL_COUNT, fbg::EVAL_DNF}) {
       uint64_t maxb = (uint64_t)cus * (uint64_t)fbg::batch_blocks_per_cu(mode, l, var, pl.block, lds);
@@ -795,6 +825,12 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   }
   hipError_t e = hipMalloc((void **)&b->d_progs, (size_t)np * sizeof(fbg::BatchProg));
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_head, 4 * fbg::kHeadWords * sizeof(uint32_t));
+  for (size_t k = 0; k < b->plans.size() && e == hipSuccess; k++) {
+    fbg_batch::Plan &pl = b->plans[k];
+    if (pl.gstride == 0) continue;
+    const uint64_t waves_max = (uint64_t)std::max(pl.grid, pl.grid_dnf) * (uint64_t)(pl.block / 64);
+    e = hipMalloc((void **)&pl.d_gscratch, waves_max * pl.gstride * sizeof(uint32_t));
+  }
   for (size_t k = 0; k < b->plans.size() && e == hipSuccess; k++) {
     e = hipMalloc((void **)&b->plans[k].d_items, plan_items[k].size() * sizeof(fbg::BatchItem));
     if (e == hipSuccess)
@@ -834,6 +870,8 @@ fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, u
     a.max_regs = pl.max_regs;
     a.head = b->d_head + k * fbg::kHeadWords;
     a.counts = d_counts;
+    a.gscratch = pl.d_gscratch;
+    a.gstride = pl.gstride;
     if (mode == fbg::EVAL_DNF && pl.d_direct && b->d_tile_counts) {
       // one wave per tile over the plan's programs in order; counts from the
       // tile counts
@@ -1023,6 +1061,7 @@ void fbg_batch_free(fbg_batch *b) {
   for (auto &pl : b->plans) {
     if (pl.d_items) (void)hipFree(pl.d_items);
     if (pl.d_direct) (void)hipFree(pl.d_direct);
+    if (pl.d_gscratch) (void)hipFree(pl.d_gscratch);
   }
   if (b->d_head) (void)hipFree(b->d_head);
   delete b;

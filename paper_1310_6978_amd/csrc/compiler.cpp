@@ -515,9 +515,14 @@ struct Codegen {
           break;
         }
     }
-    // Stored operands first (cheap register reads), then the others.
-    std::stable_sort(general.begin(), general.end(),
-                     [&](Edge a, Edge b) { return stored.count(a >> 1) > stored.count(b >> 1); });
+    // Stored operands first (cheap register reads), then the others by
+    // decreasing register need, so that the operand needing most registers
+    // is evaluated while no partial result is held (Sethi-Ullman order).
+    std::stable_sort(general.begin(), general.end(), [&](Edge a, Edge b) {
+      const bool sa = stored.count(a >> 1) != 0, sb = stored.count(b >> 1) != 0;
+      if (sa != sb) return sa;
+      return !sa && need(a >> 1) > need(b >> 1);
+    });
 
     bool have_cur = false;
     if (!general.empty()) {
@@ -576,6 +581,32 @@ struct Codegen {
     }
     if (parity) emit_not();
     store_if_shared(v);
+  }
+
+  // Registers the evaluation of node v needs, estimated on the tree view of
+  // the graph (shared nodes counted as computed in place): an operand that is
+  // a literal set needs none; the first general operand is evaluated with no
+  // partial result held, every later one while the partial result of the
+  // node sits in a register, so it needs its own need plus one.
+  std::unordered_map<uint32_t, uint32_t> need_memo;
+  uint32_t need(uint32_t v) {
+    auto it = need_memo.find(v);
+    if (it != need_memo.end()) return it->second;
+    need_memo[v] = 0;  // cycles cannot occur; this guards a revisit during the walk
+    std::vector<Edge> ops;
+    bool parity;
+    operands(v, ops, parity);
+    std::vector<uint32_t> ns;
+    for (Edge e : ops) {
+      LitSet ls;
+      if (is_var(e) || literal_set(e, ls)) continue;
+      ns.push_back(need(e >> 1));
+    }
+    std::sort(ns.begin(), ns.end(), std::greater<uint32_t>());
+    uint32_t r = 0;
+    for (size_t j = 0; j < ns.size(); j++) r = std::max<uint32_t>(r, ns[j] + (j > 0 ? 1u : 0u));
+    need_memo[v] = r;
+    return r;
   }
 
   void store_if_shared(uint32_t v) {

@@ -18,7 +18,8 @@
 //               (read and written through VGPR index mode, M0 = 16 r)
 //   v[80:95]    a register read back from LDS
 //   v[96:111]   acc
-// leaving v[0:13] and v[112:127] to the compiler for what lives across.
+// leaving v[0:13] and v[112:127] to the compiler for what lives across (four
+// waves share a SIMD; two VGPR registers and five waves measured slower).
 //   s[48:55]    the current instruction, s[56:71] its pattern words,
 //   s[72:75]    scratch, s[76:77] the jump table base, s[78:79] the jump
 //               target, s80 the instruction offset, s81 the pattern offset,
@@ -105,8 +106,13 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 #define FBG_J16_C_REGV(TT)                                                                          \
   "s_set_gpr_idx_on s49, gpr_idx(SRC1)\n" FBG_J16_NEXT "s_nop 1\n" FBG_J16_EACH(FBG_J16_REGV_W, #TT) \
   "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
-// register in LDS: four 16-byte reads per lane, then the operation
+// register beyond the VGPRs: in LDS when its offset is inside this wave's
+// LDS block (%[ldsb] bytes), else in the wave's global-memory block (the
+// code of FBG_J16_G_REGL, before the table); four 16-byte reads per lane,
+// then the operation
 #define FBG_J16_C_REGL(TT)                                                                \
+  "s_cmp_lt_u32 s49, %[ldsb]\n"                                                          \
+  "s_cbranch_scc0 LG" #TT "%=\n"                                                          \
   "v_add_u32 v15, s49, %[lb]\n"                                                           \
   "ds_read_b128 v[80:83], v15\n"                                                         \
   "ds_read_b128 v[84:87], v15 offset:16\n"                                               \
@@ -114,18 +120,42 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "ds_read_b128 v[92:95], v15 offset:48\n" FBG_J16_NEXT "s_waitcnt lgkmcnt(0)\n"         \
   FBG_J16_EACH(FBG_J16_REGL_W, #TT) FBG_J16_DISPATCH
 
+// the global-memory half: the same register read from the wave's block at
+// %[gb], lane l at 64 l (%[l64]); earlier stores of this wave are waited for
+#define FBG_J16_G_REGL(TT)                                                                \
+  "LG" #TT "%=:\n"                                                                        \
+  "s_sub_u32 s72, s49, %[ldsb]\n"                                                         \
+  "v_add_u32 v15, s72, %[l64]\n"                                                          \
+  "s_waitcnt vmcnt(0)\n"                                                                  \
+  "global_load_dwordx4 v[80:83], v15, %[gb]\n"                                            \
+  "global_load_dwordx4 v[84:87], v15, %[gb] offset:16\n"                                  \
+  "global_load_dwordx4 v[88:91], v15, %[gb] offset:32\n"                                  \
+  "global_load_dwordx4 v[92:95], v15, %[gb] offset:48\n" FBG_J16_NEXT                     \
+  "s_waitcnt vmcnt(0) lgkmcnt(0)\n" FBG_J16_EACH(FBG_J16_REGL_W, #TT) FBG_J16_DISPATCH
+
 #define FBG_J16_C_ST_V(INVOUT)                                                                  \
   "s_set_gpr_idx_on s49, gpr_idx(DST)\n" FBG_J16_NEXT "s_nop 1\n" FBG_J16_W16(FBG_J16_STV)     \
   "s_set_gpr_idx_off\n" INVOUT FBG_J16_DISPATCH
-#define FBG_J16_C_ST_L(INVOUT)                                                \
+#define FBG_J16_C_ST_L(INVOUT, G)                                             \
+  "s_cmp_lt_u32 s49, %[ldsb]\n"                                              \
+  "s_cbranch_scc0 LGST" #G "%=\n"                                             \
   "v_add_u32 v15, s49, %[lb]\n"                                               \
   "ds_write_b128 v15, v[16:19]\n"                                             \
   "ds_write_b128 v15, v[20:23] offset:16\n"                                   \
   "ds_write_b128 v15, v[24:27] offset:32\n"                                   \
   "ds_write_b128 v15, v[28:31] offset:48\n" FBG_J16_NEXT INVOUT FBG_J16_DISPATCH
+#define FBG_J16_G_ST_L(INVOUT, G)                                             \
+  "LGST" #G "%=:\n"                                                           \
+  "s_sub_u32 s72, s49, %[ldsb]\n"                                            \
+  "v_add_u32 v15, s72, %[l64]\n"                                             \
+  "global_store_dwordx4 v15, v[16:19], %[gb]\n"                              \
+  "global_store_dwordx4 v15, v[20:23], %[gb] offset:16\n"                    \
+  "global_store_dwordx4 v15, v[24:27], %[gb] offset:32\n"                    \
+  "global_store_dwordx4 v15, v[28:31], %[gb] offset:48\n" FBG_J16_NEXT INVOUT FBG_J16_DISPATCH
 // cur inverted after a store: the store has read cur first
 #define FBG_J16_INVOUT_CUR FBG_J16_W16(FBG_J16_NOTCUR)
 #define FBG_J16_INVOUT_AFTER_DS "s_waitcnt lgkmcnt(0)\n" FBG_J16_W16(FBG_J16_NOTCUR)
+#define FBG_J16_INVOUT_AFTER_VM "s_waitcnt vmcnt(0)\n" FBG_J16_W16(FBG_J16_NOTCUR)
 
 // The cases in table order (case k at Lc + 256 k).
 #define FBG_J16_CASES_REG(MAC, BASE)                                                                         \
@@ -158,6 +188,10 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "s_mov_b32 s80, 0\n"                                                                                       \
   "s_load_dwordx8 s[48:55], %[code], s80\n"                                                                  \
   FBG_J16_DISPATCH                                                                                           \
+  FBG_J16_G_REGL(0xC0) FBG_J16_G_REGL(0x30) FBG_J16_G_REGL(0xFC) FBG_J16_G_REGL(0xF3) FBG_J16_G_REGL(0x3C)   \
+  FBG_J16_G_REGL(0xC3) FBG_J16_G_REGL(0x3F) FBG_J16_G_REGL(0xCF) FBG_J16_G_REGL(0x03) FBG_J16_G_REGL(0x0C)   \
+  FBG_J16_G_REGL(0xCC) FBG_J16_G_REGL(0x33)                                                                  \
+  FBG_J16_G_ST_L("", 0) FBG_J16_G_ST_L(FBG_J16_INVOUT_AFTER_VM, 1)                                          \
   ".p2align 8\n"                                                                                             \
   "Lc%=:\n"                                                                                                  \
   FBG_J16_CASE(0)  "s_branch Ld%=\n"                                                                         \
@@ -168,8 +202,8 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASE(5)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_INVOUT_CUR FBG_J16_DISPATCH              \
   FBG_J16_CASE(6)  FBG_J16_C_ST_V("")                                                                        \
   FBG_J16_CASE(7)  FBG_J16_C_ST_V(FBG_J16_INVOUT_CUR)                                                        \
-  FBG_J16_CASE(8)  FBG_J16_C_ST_L("")                                                                        \
-  FBG_J16_CASE(9)  FBG_J16_C_ST_L(FBG_J16_INVOUT_AFTER_DS)                                                   \
+  FBG_J16_CASE(8)  FBG_J16_C_ST_L("", 0)                                                                     \
+  FBG_J16_CASE(9)  FBG_J16_C_ST_L(FBG_J16_INVOUT_AFTER_DS, 1)                                                \
   FBG_J16_CASES_REG(FBG_J16_C_REGV, 10)                                                                      \
   FBG_J16_CASES_REG(FBG_J16_C_REGL, 22)                                                                      \
   FBG_J16_CASES_NP(FBG_J16_C_LITOR, 34)                                                                      \
@@ -186,20 +220,25 @@ static_assert(FBG_J16_NCASES == 78 && FBG_J16_SLOT == 256,
 
 // Run the general part of a program (jump-table form at `code`, its pattern
 // table at `table`) on the 16 words of this lane of tile group U0.  acc comes
-// in as the clause block's value and leaves as the program's.  `lds_lane` is
-// the LDS byte address of this lane's LDS registers (wave base + 64 lane).
+// in as the clause block's value and leaves as the program's.  Registers from
+// 3 on sit at byte offset 4096 (r - 3): below `lds_bytes` in LDS, at
+// `lds_lane` (this wave's LDS block + 64 lane); from `lds_bytes` on in global
+// memory, at `gbase` (this wave's block) + offset - lds_bytes + 64 lane.
 __device__ __forceinline__ void run_general_j16(const uint32_t *code, const uint32_t *table, uint64_t U0,
-                                                uint32_t lds_lane, uint32_t (&acc)[16]) {
+                                                uint32_t lds_lane, uint32_t lds_bytes, uint32_t *gbase,
+                                                uint32_t lane, uint32_t (&acc)[16]) {
   j16_u32x16 a;
 #pragma unroll
   for (int i = 0; i < 16; i++) a[i] = acc[i];
   j16_u32x16 d0, d1, d2, d3, d4;
   j16_u32x2 d6;
-  const uint64_t c = (uint64_t)code, t = (uint64_t)table;
+  const uint64_t c = (uint64_t)code, t = (uint64_t)table, g = (uint64_t)gbase;
+  const uint32_t l64 = lane * 64u;
   asm volatile(FBG_J16_PROGRAM
                : "+{v[96:111]}"(a), "=&{v[16:31]}"(d0), "=&{v[32:47]}"(d1), "=&{v[48:63]}"(d2),
                  "=&{v[64:79]}"(d3), "=&{v[80:95]}"(d4), "=&{v[14:15]}"(d6)
-               : [code] "s"(c), [tab] "s"(t), [u0] "s"(U0), [lb] "v"(lds_lane)
+               : [code] "s"(c), [tab] "s"(t), [u0] "s"(U0), [lb] "v"(lds_lane), [ldsb] "s"(lds_bytes),
+                 [gb] "s"(g), [l64] "v"(l64)
                : "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60", "s61",
                  "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75",
                  "s76", "s77", "s78", "s79", "s80", "s81", "s83", "scc", "memory");

@@ -292,6 +292,11 @@ __device__ __forceinline__ void run_clauses(const uint32_t *__restrict__ cb_g, c
   constexpr int NG = 1 + 2 * LOG2W;
   const code_ptr cb = (code_ptr)cb_g;
   const uint32_t nstat = cb[1], nmulti = cb[2];
+  if (nstat + nmulti == 0) {  // no clause: acc starts all-ones (wave-uniform)
+#pragma unroll
+    for (int i = 0; i < W; i++) acc[i] = ~0u;
+    return;
+  }
   uint32_t G[NG];
 #pragma unroll
   for (int g = 0; g < NG; g++) G[g] = ~0u;
@@ -427,10 +432,14 @@ __device__ __forceinline__ void for_tiles(const uint32_t *__restrict__ code, uin
 
 // Interpret one program over the W words of this lane in tile group U0: the
 // clause block, then (GEN) the instructions after it.
+// regs: this wave's LDS registers; at 16 words per lane the registers from
+// lds_bytes on (byte offsets in the jump-table form) live in global memory at
+// gregs instead (a block per wave).
 template <int LOG2W, bool GEN>
 __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g, uint32_t nins, uint64_t U0,
                                             uint32_t lane, uint32_t (&acc)[1 << LOG2W],
-                                            GenState<1 << LOG2W> &st, uint32_t *__restrict__ regs) {
+                                            GenState<1 << LOG2W> &st, uint32_t *__restrict__ regs,
+                                            uint32_t lds_bytes = 0, uint32_t *gregs = nullptr) {
   const code_ptr cb = (code_ptr)code_g;
   const code_ptr ins = cb + cb[0];
   const code_ptr table = ins + FBG_TABLE_OFFSET(nins, LOG2W);
@@ -440,7 +449,8 @@ __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g,
     // the jump-table form; LDS registers at this wave's block, 64 bytes a lane
     const uint32_t lds_lane =
         (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint32_t *)regs) + lane * 64u;
-    run_general_j16((const uint32_t *)(uintptr_t)ins, (const uint32_t *)(uintptr_t)table, U0, lds_lane, acc);
+    run_general_j16((const uint32_t *)(uintptr_t)ins, (const uint32_t *)(uintptr_t)table, U0, lds_lane, lds_bytes,
+                    gregs, lane, acc);
   } else {
     run_general<LOG2W>(ins, table, nins, U0, lane, acc, st, regs);
   }
@@ -455,9 +465,15 @@ __device__ __forceinline__ void mask_tail(uint32_t (&acc)[1 << LOG2W], uint64_t 
     // valid words of the tile, at most 64 W: 32-bit compares per word
     const uint64_t base = U0 * 64;
     const uint32_t rem = (uint32_t)min(nslices > base ? nslices - base : 0ull, (unsigned long long)W * 64);
+    // words below `full` are whole, word `full` holds the lanes below
+    // `part`; the masks are wave-uniform, so no per-word lane constants
+    const uint32_t full = uni(rem >> 6), part = uni(rem & 63u);
+    const uint64_t partial = __ballot(lane < part);
 #pragma unroll
-    for (int i = 0; i < W; i++)
-      if ((int)lane >= (int)rem - 64 * i) acc[i] = 0u;
+    for (int i = 0; i < W; i++) {
+      const uint64_t keep = (uint32_t)i < full ? ~0ull : ((uint32_t)i == full ? partial : 0ull);
+      acc[i] = __builtin_amdgcn_inverse_ballot_w64(keep) ? acc[i] : 0u;
+    }
     if (n < FBG_SLICE_BITS) acc[0] &= (uint32_t)((1ull << (1u << n)) - 1u);
   }
 }
@@ -626,7 +642,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
     }
     uint32_t acc[W];
     if (alive) {
-      run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, st, regs);
+      run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, st, regs, a.nregs * (W * 256u));
       mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);
     } else {
 #pragma unroll
@@ -698,6 +714,8 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = uni(threadIdx.x) >> 6;
   uint32_t *regs = lds + (size_t)wib * a.max_regs * (W * 64);
+  // registers beyond the LDS block: this wave's block of global scratch
+  uint32_t *gregs = a.gscratch ? a.gscratch + ((size_t)blockIdx.x * (blockDim.x >> 6) + wib) * a.gstride : nullptr;
   typedef const __attribute__((address_space(4))) BatchItem *item_ptr;
   typedef const __attribute__((address_space(4))) BatchProg *prog_ptr;
   // A wave adds its count to a program's slot once per run of items of
@@ -721,7 +739,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
       if (alive) {
-        run_program<LOG2W, (VAR & 1) != 0>(p->code, p->nins, U0, lane, acc, st, regs);
+        run_program<LOG2W, (VAR & 1) != 0>(p->code, p->nins, U0, lane, acc, st, regs, a.max_regs * (W * 256u), gregs);
       } else {
 #pragma unroll
         for (int i = 0; i < W; i++) acc[i] = 0u;

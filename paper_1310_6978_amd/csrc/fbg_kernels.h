@@ -89,6 +89,10 @@ struct BatchArgs {
   uint32_t *head;     // kHeadWords words of queue heads, zeroed before the launch
   uint64_t *counts;   // per slot; the kernel adds to it
   uint32_t run = 1;   // k_batch_direct: consecutive tiles per wave
+  // registers beyond the max_regs LDS registers (jump-table form only):
+  // gstride words of global scratch per wave of the grid, or none
+  uint32_t *gscratch = nullptr;
+  uint64_t gstride = 0;
 };
 
 enum { EVAL_COUNT = 0, EVAL_DNF = 1, EVAL_TILECNT = 2, EVAL_ENUM = 3 };

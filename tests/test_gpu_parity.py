@@ -472,6 +472,23 @@ def test_registers_beyond_the_vgpr_set(F, k):
         assert host(F.count_batch(progs)).tolist() == want
 
 
+@pytest.mark.parametrize("k", [9, 17])
+def test_batch_registers_in_global_scratch(F, k):
+    # at 16 words per lane a batch keeps two registers of a wave in LDS and
+    # the rest in a global scratch block: programs with many registers, next
+    # to clause-only ones and small ones, in one launch, vs the oracle
+    rng = random.Random(5100 + k)
+    texts = [(many_registers(rng, n, k), n) for n in (12, 17, 19)]
+    texts += [workloads.random_3cnf(19, 40, k), ("x0 & ~x3 | x5", 8)]
+    progs = [F.Program(t, n) for t, n in texts]
+    assert max(p.info["n_regs"] for p in progs) >= 6
+    want = [oracle.count(t, n) for t, n in texts]
+    b = F.Batch(progs, words_per_lane=16)
+    assert host(b.count()).tolist() == want
+    assert host(b.count(graph=True)).tolist() == want
+    b.free()
+
+
 def test_batch_enumerate_lists_every_program(F):
     import torch
     rng = random.Random(91)
