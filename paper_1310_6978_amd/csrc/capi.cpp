@@ -231,8 +231,13 @@ namespace {
 int pick_log2w(uint64_t nslices, uint32_t nregs, bool general, int dev) {
   const uint64_t waves = (uint64_t)cu_count(dev) * 32;  // 8 waves per SIMD
   int best = 0;
-  // the general interpreter keeps cur and four registers per word in VGPRs:
-  // beyond 8 words per lane it loses more occupancy than it gains
+  // Programs with a general part: the jump-table interpreter at 16 words per
+  // lane (four waves per SIMD) whenever every compute unit gets a few tiles;
+  // below that the plain interpreter, which beyond 8 words per lane loses
+  // more occupancy than it gains.
+  if (general && lds_per_wave(nregs, FBG_J16_LOG2W) <= kMaxLdsPerBlock &&
+      tiles_of(nslices, FBG_J16_LOG2W) >= (uint64_t)cu_count(dev) * 4)
+    return FBG_J16_LOG2W;
   for (int l = general ? 3 : kMaxLog2W; l >= 0; l--) {
     if (lds_per_wave(nregs, l) > kMaxLdsPerBlock) continue;
     if (tiles_of(nslices, l) >= waves || l == 0) {
@@ -694,6 +699,9 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   // one plan, one persistent launch.
   bool any_general = false;
   for (int32_t i = 0; i < np; i++) any_general = any_general || ps[i]->general();
+  // (the library's own choice for a batch with general programs when the
+  // tuning does not fix the tiling)
+  if (fixed_l < 0 && any_general) fixed_l = FBG_J16_LOG2W;
   const bool one_plan = fixed_l == FBG_J16_LOG2W && any_general;
   auto group_of = [one_plan](const fbg_program *q) {
     if (one_plan) return 1;
