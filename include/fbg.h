@@ -103,7 +103,9 @@ typedef struct {
                               item); 0: as many as stay resident, except for
                               fbg_eval_dnf without the cofactor: one wave per tile */
   int32_t flags;           /* FBG_TUNE_* */
-  int32_t reserved1;
+  int32_t direct_run;      /* fbg_batch_eval_dnf of clause-only programs (one
+                              wave per run of tiles on fresh blocks): tiles
+                              per run, 1..64; 0: the library's choice (4) */
 } fbg_tune;
 
 /* Uniform-cofactor evaluation: the index bits above the lane and word bits

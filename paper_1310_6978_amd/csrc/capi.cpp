@@ -181,6 +181,7 @@ struct fbg_batch {
     fbg::BatchItem *d_direct = nullptr;
     uint32_t ndirect = 0;
     uint64_t ntiles = 0, max_prog_tiles = 0;
+    uint32_t direct_run = kDirectRun;  // tiles per wave of the direct write-out
     // jump-table form (16 words per lane): registers beyond the plan's LDS
     // registers, gstride words per wave of the grid
     uint32_t *d_gscratch = nullptr;
@@ -677,6 +678,8 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
   fbg_status st;
   int fixed_l = -1;
   if (tune && tune->words_per_lane && (st = parse_wpl(tune->words_per_lane, fixed_l))) return st;
+  if (tune && (tune->direct_run < 0 || tune->direct_run > 64))
+    return fail(FBG_E_INVAL, "direct_run must be 0..64 (got %d)", tune->direct_run);
   const int cus = cu_count(dev);
   const uint64_t waves = (uint64_t)cus * 32;
 
@@ -803,6 +806,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     pl.block = 64 * wpb;
     pl.lds = lds;
     pl.nitems = (uint32_t)sorted.size();
+    if (tune && tune->direct_run > 0) pl.direct_run = (uint32_t)tune->direct_run;
     pl.max_regs = lds_keep;
     pl.gstride = gstride;
     const uint64_t want = (pl.nitems + wpb - 1) / wpb;
@@ -885,7 +889,7 @@ fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, u
       // tile counts
       a.items = pl.d_direct;
       a.nitems = pl.ndirect;
-      a.run = kDirectRun;
+      a.run = pl.direct_run;
       const uint64_t wpb = (uint64_t)(pl.block / 64);
       const uint64_t waves = (pl.ntiles + a.run - 1) / a.run;
       const uint64_t grid = (waves + wpb - 1) / wpb;

@@ -801,15 +801,17 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
   const uint64_t g0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + wib) * a.run;
   const item_ptr items = (item_ptr)a.items;
   const uint64_t end = items[a.nitems - 1].t1;
+  if (g0 >= end) return;
+  uint32_t lo = 0, hi = a.nitems;  // the entry with t0 <= g0 < t1, found once
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (items[mid].t0 <= g0)
+      lo = mid;
+    else
+      hi = mid;
+  }
   for (uint64_t g = g0; g < g0 + a.run && g < end; ++g) {  // wave-uniform
-    uint32_t lo = 0, hi = a.nitems;  // the entry with t0 <= g < t1
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (items[mid].t0 <= g)
-        lo = mid;
-      else
-        hi = mid;
-    }
+    while (g >= items[lo].t1) lo++;  // the run crossed into the next program
     const item_ptr it = items + lo;
     const prog_ptr p = (prog_ptr)a.progs + it->prog;
     const uint64_t t = g - it->t0;

@@ -45,7 +45,7 @@ class ProgramInfo(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("words_per_lane", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("direct_run", ctypes.c_int32)]
 
 
 TUNE_COFACTOR = 1
@@ -129,10 +129,11 @@ def _check(st):
         raise FbgError(st, lib.fbg_last_error().decode(errors="replace"), lib.fbg_last_error_offset())
 
 
-def _tune(words_per_lane=0, grid_blocks=0, cofactor=False):
-    if not words_per_lane and not grid_blocks and not cofactor:
+def _tune(words_per_lane=0, grid_blocks=0, cofactor=False, direct_run=0):
+    if not words_per_lane and not grid_blocks and not cofactor and not direct_run:
         return None
-    return ctypes.byref(Tune(int(words_per_lane), int(grid_blocks), TUNE_COFACTOR if cofactor else 0, 0))
+    return ctypes.byref(Tune(int(words_per_lane), int(grid_blocks), TUNE_COFACTOR if cofactor else 0,
+                             int(direct_run)))
 
 
 def _torch_stream(stream):
@@ -410,12 +411,12 @@ class Server:
 class Batch:
     """A work plan for counting many programs in one persistent launch."""
 
-    def __init__(self, progs, words_per_lane=0, grid_blocks=0, cofactor=False):
+    def __init__(self, progs, words_per_lane=0, grid_blocks=0, cofactor=False, direct_run=0):
         self._progs = list(progs)  # keep the programs alive
         arr = (ctypes.c_void_p * len(self._progs))(*[p.handle.value for p in self._progs])
         h = ctypes.c_void_p()
-        _check(lib.fbg_batch_create(arr, len(self._progs), _tune(words_per_lane, grid_blocks, cofactor),
-                                    ctypes.byref(h)))
+        _check(lib.fbg_batch_create(arr, len(self._progs),
+                                    _tune(words_per_lane, grid_blocks, cofactor, direct_run), ctypes.byref(h)))
         self._h = h
         self._streams = {}
         for p in self._progs:
