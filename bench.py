@@ -73,7 +73,7 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # the counters were taken on.  The bench line reports the bytes only while
 # the sources still have that digest, and null otherwise.
 C1_TRAFFIC = {"bytes": None, "kernel_sources_sha1": None}
-KERNEL_SOURCES = ("fbg_device.h", "fbg_isa.h", "fbg_kernels.h", "batch.hip")
+KERNEL_SOURCES = ("fbg_device.h", "fbg_asm16.h", "fbg_isa.h", "fbg_kernels.h", "batch.hip")
 
 
 def kernel_sources_sha1():

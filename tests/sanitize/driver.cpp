@@ -1,0 +1,57 @@
+// Host-only driver of the compiler and encoder for the sanitizer build
+// (tests/test_host_sanitizers.py builds it with -fsanitize=address,undefined
+// from this file and compiler.cpp alone; no HIP).
+//
+// Input on stdin, repeated: a line "n nbytes", then nbytes of formula text.
+// For each case it prints "ERR <status>" when the text does not compile,
+// else one line per words-per-lane setting and evaluation variant:
+//   "<log2w> <cof> <hex words of the emulated DNF vector>"
+// and walks the listing and the VALU count of every encoding.
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <string>
+#include <vector>
+
+#include "fbg_internal.h"
+
+int main() {
+  int n;
+  long len;
+  while (scanf("%d %ld", &n, &len) == 2) {
+    if (getchar() != '\n' || len < 0 || len > (1l << 24)) return 2;
+    std::string text((size_t)len, '\0');
+    if (len && fread(&text[0], 1, (size_t)len, stdin) != (size_t)len) return 2;
+    fbg::Compiled c;
+    std::string msg;
+    int64_t off = -1;
+    const int st = fbg::compile_formula(text.c_str(), n, c, msg, off);
+    if (st != 0) {
+      printf("ERR %d\n", st);
+      continue;
+    }
+    const uint64_t slices = c.n >= 5 ? (1ull << (c.n - 5)) : 1ull;
+    const uint64_t words64 = c.n >= 6 ? (1ull << (c.n - 6)) : 1ull;
+    for (int l = 0; l <= 5; l++) {
+      std::vector<uint32_t> words;
+      std::string err;
+      const uint32_t nins = fbg::encode_program(c, l, words, &err);
+      if (!err.empty()) {
+        printf("ERR encode %s\n", err.c_str());
+        continue;
+      }
+      (void)fbg::disasm_program(words, nins, l);
+      (void)fbg::valu_per_slice(words, nins, l, (uint32_t)c.nregs);
+      for (int cof = 0; cof < 2; cof++) {
+        std::vector<uint32_t> out32((size_t)(slices < 2 ? 2 : slices), 0u);
+        fbg::emulate_program(words, nins, c.nregs, c.n, l, cof != 0, out32.data());
+        printf("%d %d", l, cof);
+        for (uint64_t w = 0; w < words64; w++)
+          printf(" %llx", (unsigned long long)((uint64_t)out32[2 * w] | ((uint64_t)out32[2 * w + 1] << 32)));
+        printf("\n");
+      }
+    }
+  }
+  return 0;
+}
