@@ -292,11 +292,6 @@ __device__ __forceinline__ void run_clauses(const uint32_t *__restrict__ cb_g, c
   constexpr int NG = 1 + 2 * LOG2W;
   const code_ptr cb = (code_ptr)cb_g;
   const uint32_t nstat = cb[1], nmulti = cb[2];
-  if (nstat + nmulti == 0) {  // no clause: acc starts all-ones (wave-uniform)
-#pragma unroll
-    for (int i = 0; i < W; i++) acc[i] = ~0u;
-    return;
-  }
   uint32_t G[NG];
 #pragma unroll
   for (int g = 0; g < NG; g++) G[g] = ~0u;
@@ -443,7 +438,20 @@ __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g,
   const code_ptr cb = (code_ptr)code_g;
   const code_ptr ins = cb + cb[0];
   const code_ptr table = ins + FBG_TABLE_OFFSET(nins, LOG2W);
-  run_clauses<LOG2W>(code_g, table, U0, lane, acc);
+  if constexpr (GEN && LOG2W == FBG_J16_LOG2W) {
+    // programs without clauses (most general programs) skip the block and
+    // its product tree: acc starts all-ones (wave-uniform test); only here,
+    // where the register map is fixed anyway, so the other kernels keep
+    // their register allocation
+    if (cb[1] + cb[2] == 0) {
+#pragma unroll
+      for (int i = 0; i < (1 << LOG2W); i++) acc[i] = ~0u;
+    } else {
+      run_clauses<LOG2W>(code_g, table, U0, lane, acc);
+    }
+  } else {
+    run_clauses<LOG2W>(code_g, table, U0, lane, acc);
+  }
   if (!GEN) return;
   if constexpr (LOG2W == FBG_J16_LOG2W) {
     // the jump-table form; LDS registers at this wave's block, 64 bytes a lane
@@ -465,15 +473,12 @@ __device__ __forceinline__ void mask_tail(uint32_t (&acc)[1 << LOG2W], uint64_t 
     // valid words of the tile, at most 64 W: 32-bit compares per word
     const uint64_t base = U0 * 64;
     const uint32_t rem = (uint32_t)min(nslices > base ? nslices - base : 0ull, (unsigned long long)W * 64);
-    // words below `full` are whole, word `full` holds the lanes below
-    // `part`; the masks are wave-uniform, so no per-word lane constants
-    const uint32_t full = uni(rem >> 6), part = uni(rem & 63u);
-    const uint64_t partial = __ballot(lane < part);
+    // word i of this lane is valid when 64 i + lane < rem, i.e. when
+    // d = rem - lane exceeds 64 i: one VGPR and an immediate per word, no
+    // per-word lane constants kept across the tile loop
+    const int d = (int)rem - (int)lane;
 #pragma unroll
-    for (int i = 0; i < W; i++) {
-      const uint64_t keep = (uint32_t)i < full ? ~0ull : ((uint32_t)i == full ? partial : 0ull);
-      acc[i] = __builtin_amdgcn_inverse_ballot_w64(keep) ? acc[i] : 0u;
-    }
+    for (int i = 0; i < W; i++) acc[i] = d > 64 * i ? acc[i] : 0u;
     if (n < FBG_SLICE_BITS) acc[0] &= (uint32_t)((1ull << (1u << n)) - 1u);
   }
 }
