@@ -513,7 +513,9 @@ fbg_status fbg_program_info(const fbg_program *p, struct fbg_program_info *out) 
   out->n_vars = p->c.n;
   out->const_value = p->c.const_value;
   out->l2in = p->c.l2in;
-  out->n_instr = (int32_t)(p->ncl + p->nins[p->auto_log2w]);  // clauses + instructions after them
+  // clauses + instructions after them, in the plain form (one word per lane
+  // is never the jump-table form, which adds the ends of chains)
+  out->n_instr = (int32_t)(p->ncl + p->nins[0]);
   out->n_regs = p->c.nregs;
   out->n_clause_instr = (int32_t)p->ncl;
   out->words_per_lane = 1 << p->auto_log2w;
@@ -762,7 +764,9 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     for (int32_t i : members) {
       fbg::BatchProg &q = b->host_progs[(size_t)i];
       q = batch_prog(ps[i], l);
-      total_cost += (double)q.ntiles * (q.nins + 4);
+      // per tile about one step per instruction (counted in the plain form:
+      // one word per lane never takes the jump-table form) and a few more
+      total_cost += (double)q.ntiles * (ps[i]->nins[0] + 4.0);
       b->plan_of[(size_t)i] = (int)b->plans.size();
     }
     // about four items per wave; never split below one tile.  A program's
@@ -774,7 +778,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     std::vector<double> cost;
     for (int32_t i : members) {
       const fbg::BatchProg &q = b->host_progs[(size_t)i];
-      const double per_tile = q.nins + 4.0;
+      const double per_tile = ps[i]->nins[0] + 4.0;
       const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
       const uint64_t K = (q.ntiles + chunk - 1) / chunk;
       for (uint64_t k = 0; k < K; k++) {

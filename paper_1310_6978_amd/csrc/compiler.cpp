@@ -1008,19 +1008,20 @@ int table_index(const uint32_t (&list)[N], uint32_t tt) {
 }
 
 // Rewrite the nins instructions at words[at..] into the jump-table form
-// (fbg_isa.h) and close them with END; returns the instructions kept (a NOT
-// with INVOUT, which changes nothing, is dropped).  *err is set when an
-// instruction has no case (the code generator emits none such).
+// (fbg_isa.h) and close them with END; returns the length of that form in
+// units of FBG_J16_UNIT words, END included (a NOT with INVOUT, which changes
+// nothing, is dropped; runs of literal sets become chains).  *err is set
+// when an instruction has no case (the code generator emits none such).
 uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, std::string *err) {
-  std::vector<uint32_t> out;
-  out.reserve((size_t)(nins + 1) * FBG_INS_WORDS);
+  std::vector<std::array<uint32_t, FBG_INS_WORDS>> out;
+  out.reserve(nins);
   auto missing = [&](const char *what, uint32_t tt) {
     if (err && err->empty()) *err = std::string("internal: no jump-table case for ") + what + " table " +
                                     std::to_string(tt);
   };
   for (uint32_t k = 0; k < nins; k++) {
     const uint32_t *g = &words[at + (size_t)k * FBG_INS_WORDS];
-    uint32_t w[FBG_INS_WORDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::array<uint32_t, FBG_INS_WORDS> w{};
     const uint32_t op = g[0] & 15u, tt = (g[0] >> FBG_F_SHIFT) & 0xFFu, arg = g[0] >> FBG_ARG_SHIFT;
     const uint32_t invout = (g[0] & FBG_INVOUT) ? 1u : 0u;
     uint32_t cs = 0;
@@ -1054,23 +1055,59 @@ uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, s
       missing("opcode", op);
     }
     w[0] |= cs * FBG_J16_SLOT;
-    out.insert(out.end(), w, w + FBG_INS_WORDS);
+    out.push_back(w);
   }
-  const uint32_t kept = (uint32_t)(out.size() / FBG_INS_WORDS);
-  out.resize(out.size() + FBG_INS_WORDS, 0u);  // END
+  // Runs of kMinChain or more literal sets without word literals become
+  // chains: XYF, XYM ..., XYM, XYL (fbg_isa.h, Chains).
+  constexpr size_t kMinChain = 2;
+  auto case_of = [&](size_t k) { return (out[k][0] & 0xFFFFu) / FBG_J16_SLOT; };
+  auto chainable = [&](size_t k) { return case_of(k) >= FBG_J16_LIT_OR && case_of(k) < FBG_J16_LIT_OR_P; };
+  for (size_t k = 0; k < out.size();) {
+    size_t e = k;
+    while (e < out.size() && chainable(e)) e++;
+    if (e - k >= kMinChain) {
+      for (size_t j = k; j < e; j++) {
+        const uint32_t cs = case_of(j);
+        const bool x = cs >= FBG_J16_LIT_XOR;
+        const uint32_t idx = cs - (x ? FBG_J16_LIT_XOR : FBG_J16_LIT_OR);
+        const uint32_t first = x ? FBG_J16_XYF_XOR : FBG_J16_XYF_OR, further = x ? FBG_J16_XYM_XOR : FBG_J16_XYM_OR,
+                       last = x ? FBG_J16_XYL_XOR : FBG_J16_XYL_OR;
+        const uint32_t ncs = (j == k ? first : j + 1 == e ? last : further) + idx;
+        out[j][0] = (out[j][0] & ~0xFFFFu) | ncs * FBG_J16_SLOT;
+      }
+    }
+    k = e > k ? e : k + 1;
+  }
+  // lay out: literal sets (and chain members) in full, the others short
+  std::vector<uint32_t> flat;
+  flat.reserve(out.size() * FBG_INS_WORDS + FBG_INS_WORDS);
+  for (const auto &w : out) {
+    const uint32_t cs = (w[0] & 0xFFFFu) / FBG_J16_SLOT;
+    const uint32_t len = cs >= FBG_J16_LIT_OR ? FBG_INS_WORDS : FBG_J16_SHORT_WORDS;
+    flat.insert(flat.end(), w.begin(), w.begin() + len);
+  }
+  flat.resize(flat.size() + FBG_INS_WORDS, 0u);  // END, full length
   words.resize(at);
-  words.insert(words.end(), out.begin(), out.end());
-  return kept;
+  words.insert(words.end(), flat.begin(), flat.end());
+  return (uint32_t)(flat.size() / FBG_J16_UNIT);
 }
 
 }  // namespace
 
 // One jump-table instruction back in the plain form (the same semantics: an
-// LDL is an OPL whose table ignores cur).  Returns false for END.
-bool from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
+// LDL is an OPL whose table ignores cur; chain members keep their chain
+// opcodes).  Returns the instruction's length in words, 0 for END.
+static uint32_t from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
   for (int j = 0; j < FBG_INS_WORDS; j++) g[j] = 0;
   const uint32_t cs = (w[0] & 0xFFFFu) / FBG_J16_SLOT;
-  if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) return false;
+  if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) return 0;
+  if (cs >= FBG_J16_XYF_OR) {
+    const uint32_t k = cs - FBG_J16_XYF_OR;  // 12 cases per (first / further / last, OR / XOR)
+    const uint32_t ops[3] = {FBG_OP_XYF, FBG_OP_XYM, FBG_OP_XYL};
+    g[0] = ops[k / 24] | ((k / 12) % 2 ? FBG_XORSET : 0u) | (kJ16Np[k % 12] << FBG_F_SHIFT);
+    for (int j = 1; j < FBG_INS_WORDS; j++) g[j] = w[j];
+    return FBG_INS_WORDS;
+  }
   if (cs >= FBG_J16_LIT_OR) {
     uint32_t tt, flags = 0, arg = 0;
     if (cs >= FBG_J16_LIT_XOR_P) {
@@ -1085,7 +1122,9 @@ bool from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
     if (flags & FBG_HASPAT) arg = (w[0] >> 16) / 4u;
     g[0] = FBG_OP_OPL | flags | (tt << FBG_F_SHIFT) | (arg << FBG_ARG_SHIFT);
     for (int j = 1; j < FBG_INS_WORDS; j++) g[j] = w[j];
-  } else if (cs >= FBG_J16_REG_V) {
+    return FBG_INS_WORDS;
+  }
+  if (cs >= FBG_J16_REG_V) {
     const bool lds = cs >= FBG_J16_REG_L;
     const uint32_t tt = kJ16Reg[cs - (lds ? FBG_J16_REG_L : FBG_J16_REG_V)];
     const uint32_t r = lds ? kJ16V + w[1] / 4096u : w[1] / 16u;
@@ -1100,7 +1139,7 @@ bool from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
   } else {
     g[0] = FBG_OP_NOT;
   }
-  return true;
+  return FBG_J16_SHORT_WORDS;
 }
 
 uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &words, std::string *err) {
@@ -1257,9 +1296,16 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
   const uint32_t *ins = cb + cb[0];
   if (log2w == FBG_J16_LOG2W) {
     // jump-table form: per instruction its case's VALU work
-    for (uint32_t pc = 0; pc < nins; pc++) {
-      const uint32_t cs = (ins[(size_t)pc * FBG_INS_WORDS] & 0xFFFFu) / FBG_J16_SLOT;
-      if (cs >= FBG_J16_LIT_OR) {
+    const size_t end = (size_t)nins * FBG_J16_UNIT;
+    for (size_t at = 0; at < end;) {
+      const uint32_t cs = (ins[at] & 0xFFFFu) / FBG_J16_SLOT;
+      if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) break;
+      at += cs >= FBG_J16_LIT_OR ? FBG_INS_WORDS : FBG_J16_SHORT_WORDS;
+      if (cs >= FBG_J16_XYL_OR) {
+        per_tile += 4 + W;  // the lane value, X and Y, then one v_bitop3 per word
+      } else if (cs >= FBG_J16_XYF_OR) {
+        per_tile += 4;  // the lane value, then X and Y
+      } else if (cs >= FBG_J16_LIT_OR) {
         per_tile += 2 + W;  // the lane value, one v_bitop3 per word
       } else if (cs >= FBG_J16_REG_V) {
         per_tile += W + (cs >= FBG_J16_REG_L ? 1 : 0);
@@ -1300,7 +1346,7 @@ uint32_t leading_clauses(const Compiled &c) {
 }
 
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
-  static const char *ops[] = {"?", "CL", "LDL", "OPL", "ST", "OPR", "ACC", "LDR", "NOT"};
+  static const char *ops[] = {"?", "CL", "LDL", "OPL", "ST", "OPR", "ACC", "LDR", "NOT", "XYF", "XYM", "XYL"};
   const int W = 1 << log2w;
   const uint32_t *cb = words.data();
   const uint32_t *ins = cb + cb[0];
@@ -1351,17 +1397,25 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
     ch += ch[1];
   }
   if (log2w == FBG_J16_LOG2W) out += "; jump-table form (listed in the plain form's terms)\n";
-  for (size_t pc = 0; pc < (size_t)nins * FBG_INS_WORDS; pc += FBG_INS_WORDS) {
+  const bool j16 = log2w == FBG_J16_LOG2W;
+  const size_t end = (size_t)nins * (j16 ? FBG_J16_UNIT : FBG_INS_WORDS);
+  size_t pc = 0;
+  for (size_t at = 0; at < end; pc++) {
     uint32_t gw[FBG_INS_WORDS];
-    const uint32_t *w = &ins[pc];
-    if (log2w == FBG_J16_LOG2W) {
-      if (!from_jump_table(w, gw)) break;
+    const uint32_t *w = &ins[at];
+    if (j16) {
+      const uint32_t len = from_jump_table(w, gw);
+      if (!len) break;
+      at += len;
       w = gw;
+    } else {
+      at += FBG_INS_WORDS;
     }
     uint32_t op = w[0] & 15u;
     uint32_t arg = w[0] >> FBG_ARG_SHIFT;
-    const char *name = op <= 8 ? ops[op] : "?";
-    if (op == FBG_OP_CL || op == FBG_OP_LDL || op == FBG_OP_OPL) {
+    const char *name = op <= FBG_OP_XYL ? ops[op] : "?";
+    if (op == FBG_OP_CL || op == FBG_OP_LDL || op == FBG_OP_OPL || op == FBG_OP_XYF || op == FBG_OP_XYM ||
+        op == FBG_OP_XYL) {
       uint32_t pat = 0;
       for (int i = 0; i < W; i++)
         if (table[arg + i]) pat |= 1u << i;
@@ -1369,13 +1423,12 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
       if (op != FBG_OP_CL) snprintf(tt, sizeof tt, "tt=%02x ", (w[0] >> FBG_F_SHIFT) & 0xFFu);
       snprintf(buf, sizeof buf,
                "%4zu %-3s %sset=%s mconst=%08x lane=%08x%08x pat=%08x sel=%08x%08x neg=%08x%08x\n",
-               pc / FBG_INS_WORDS, name, tt, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], pat, w[5],
+               pc, name, tt, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], pat, w[5],
                w[4], w[7], w[6]);
     } else if (op == FBG_OP_OPR || op == FBG_OP_LDR) {
-      snprintf(buf, sizeof buf, "%4zu %-3s tt=%02x r%u\n", pc / FBG_INS_WORDS, name, (w[0] >> FBG_F_SHIFT) & 0xFFu,
-               arg);
+      snprintf(buf, sizeof buf, "%4zu %-3s tt=%02x r%u\n", pc, name, (w[0] >> FBG_F_SHIFT) & 0xFFu, arg);
     } else {
-      snprintf(buf, sizeof buf, "%4zu %-3s r%u%s%s\n", pc / FBG_INS_WORDS, name, arg, (w[0] & FBG_INV) ? " inv" : "",
+      snprintf(buf, sizeof buf, "%4zu %-3s r%u%s%s\n", pc, name, arg, (w[0] & FBG_INV) ? " inv" : "",
                (w[0] & FBG_INVOUT) ? " invout" : "");
     }
     out += buf;
@@ -1387,8 +1440,6 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
 
 namespace {
 
-// A literal set at (lane, word index i, tile group U0), read the way the
-// kernels read it: P(i) from the pattern table.
 // The lane value T of a literal set at (lane, tile group U0), formed the way
 // the kernels form it: every literal but the per-word ones.
 inline uint32_t set_lane_value(const uint32_t *w, uint32_t lane, uint64_t U0) {
@@ -1475,8 +1526,13 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
   std::vector<uint32_t> plain;
   if (log2w == FBG_J16_LOG2W) {
     uint32_t g[FBG_INS_WORDS];
-    for (uint32_t pc = 0; pc < nins && from_jump_table(&ins[(size_t)pc * FBG_INS_WORDS], g); pc++)
+    const size_t end = (size_t)nins * FBG_J16_UNIT;
+    for (size_t at = 0; at < end;) {
+      const uint32_t len = from_jump_table(&ins[at], g);
+      if (!len) break;
+      at += len;
       plain.insert(plain.end(), g, g + FBG_INS_WORDS);
+    }
     ins = plain.data();
     nins = (uint32_t)(plain.size() / FBG_INS_WORDS);
   }
@@ -1485,7 +1541,7 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
     uint64_t U = s >> FBG_LANE_BITS;
     uint32_t i = (uint32_t)(U & (W - 1));
     uint64_t U0 = U - i;
-    uint32_t acc = clause_block_value(cb, table, log2w, lane, i, U0, cof), cur = 0;
+    uint32_t acc = clause_block_value(cb, table, log2w, lane, i, U0, cof), cur = 0, X = 0, Y = 0;
     for (size_t pc = 0; pc < nins; pc++) {
       const uint32_t *w = &ins[pc * FBG_INS_WORDS];
       uint32_t op = w[0] & 15u;
@@ -1501,6 +1557,19 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
         case FBG_OP_LDR: cur = bitop3(tt, cur, R[arg], 0u); break;
         case FBG_OP_ACC: acc &= cur ^ inv; break;
         case FBG_OP_NOT: cur = ~cur; break;
+        case FBG_OP_XYF:
+          X = bitop3(tt, ~0u, set_lane_value(w, lane, U0), 0u);
+          Y = bitop3(tt, 0u, set_lane_value(w, lane, U0), 0u);
+          break;
+        case FBG_OP_XYM:
+          X = bitop3(tt, X, set_lane_value(w, lane, U0), 0u);
+          Y = bitop3(tt, Y, set_lane_value(w, lane, U0), 0u);
+          break;
+        case FBG_OP_XYL:
+          X = bitop3(tt, X, set_lane_value(w, lane, U0), 0u);
+          Y = bitop3(tt, Y, set_lane_value(w, lane, U0), 0u);
+          cur = (cur & X) | (~cur & Y);
+          break;
       }
       if (w[0] & FBG_INVOUT) cur = ~cur;
     }

@@ -16,7 +16,8 @@
 //   v[16:31]    cur, word i in v[16+i]
 //   v[32:79]    registers 0..2 in VGPRs, register r word i in v[32+16r+i]
 //               (read and written through VGPR index mode, M0 = 16 r)
-//   v[80:95]    a register read back from LDS
+//   v[80:95]    a register read back from LDS; inside a chain of literal
+//               sets (fbg_isa.h) v80 = X and v81 = Y instead
 //   v[96:111]   acc
 // leaving v[0:13] and v[112:127] to the compiler for what lives across (four
 // waves share a SIMD; two VGPR registers and five waves measured slower).
@@ -42,15 +43,19 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 #define FBG_J16_STR(x) FBG_J16_STR2(x)
 #define FBG_J16_W16(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
-// Fetch the next instruction (32 bytes further) into s[48:55].
-#define FBG_J16_NEXT "s_add_u32 s80, s80, 32\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
+// Fetch the next instruction into s[48:55]: 32 bytes further after a
+// literal-set instruction (NEXT_L), 8 after the others (NEXT_S).  The load
+// reads 32 bytes either way; the END that closes the program is 32 bytes
+// long, so it never reads past the program.
+#define FBG_J16_NEXT_L "s_add_u32 s80, s80, 32\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
+#define FBG_J16_NEXT_S "s_add_u32 s80, s80, 8\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
 // Wait for it and jump to its case.  The offset is cut to a whole slot and
 // clamped to the slot past the last case, where the interpreter exits: no
 // instruction word can send the jump outside the table.
 #define FBG_J16_DISPATCH                \
   "s_waitcnt lgkmcnt(0)\n"              \
   "s_and_b32 s78, s48, 0xff00\n"        \
-  "s_min_u32 s78, s78, 0x4e00\n"        \
+  "s_min_u32 s78, s78, 0x9600\n"        \
   "s_add_u32 s78, s76, s78\n"           \
   "s_addc_u32 s79, s77, 0\n"            \
   "s_setpc_b64 s[78:79]\n"
@@ -95,16 +100,16 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   M(11, TT) M(12, TT) M(13, TT) M(14, TT) M(15, TT)
 
 // literal set without word literals: T, fetch, 16 x v_bitop3(cur, T, 0)
-#define FBG_J16_C_LITOR(TT) FBG_J16_T_OR FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
-#define FBG_J16_C_LITXOR(TT) FBG_J16_T_XOR FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
+#define FBG_J16_C_LITOR(TT) FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
+#define FBG_J16_C_LITXOR(TT) FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
 // with word literals: the pattern words come in with the next instruction
 #define FBG_J16_C_LITORP(TT) \
-  FBG_J16_PLOAD FBG_J16_T_OR "s_waitcnt lgkmcnt(0)\n" FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITP_W, #TT) FBG_J16_DISPATCH
+  FBG_J16_PLOAD FBG_J16_T_OR "s_waitcnt lgkmcnt(0)\n" FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITP_W, #TT) FBG_J16_DISPATCH
 #define FBG_J16_C_LITXORP(TT) \
-  FBG_J16_PLOAD FBG_J16_T_XOR "s_waitcnt lgkmcnt(0)\n" FBG_J16_NEXT FBG_J16_EACH(FBG_J16_LITP_W, #TT) FBG_J16_DISPATCH
+  FBG_J16_PLOAD FBG_J16_T_XOR "s_waitcnt lgkmcnt(0)\n" FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITP_W, #TT) FBG_J16_DISPATCH
 // register in VGPRs: index mode offsets the register operand by 16 r
 #define FBG_J16_C_REGV(TT)                                                                          \
-  "s_set_gpr_idx_on s49, gpr_idx(SRC1)\n" FBG_J16_NEXT "s_nop 1\n" FBG_J16_EACH(FBG_J16_REGV_W, #TT) \
+  "s_set_gpr_idx_on s49, gpr_idx(SRC1)\n" FBG_J16_NEXT_S "s_nop 1\n" FBG_J16_EACH(FBG_J16_REGV_W, #TT) \
   "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
 // register beyond the VGPRs: in LDS when its offset is inside this wave's
 // LDS block (%[ldsb] bytes), else in the wave's global-memory block (the
@@ -117,7 +122,7 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "ds_read_b128 v[80:83], v15\n"                                                         \
   "ds_read_b128 v[84:87], v15 offset:16\n"                                               \
   "ds_read_b128 v[88:91], v15 offset:32\n"                                               \
-  "ds_read_b128 v[92:95], v15 offset:48\n" FBG_J16_NEXT "s_waitcnt lgkmcnt(0)\n"         \
+  "ds_read_b128 v[92:95], v15 offset:48\n" FBG_J16_NEXT_S "s_waitcnt lgkmcnt(0)\n"         \
   FBG_J16_EACH(FBG_J16_REGL_W, #TT) FBG_J16_DISPATCH
 
 // the global-memory half: the same register read from the wave's block at
@@ -130,11 +135,26 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "global_load_dwordx4 v[80:83], v15, %[gb]\n"                                            \
   "global_load_dwordx4 v[84:87], v15, %[gb] offset:16\n"                                  \
   "global_load_dwordx4 v[88:91], v15, %[gb] offset:32\n"                                  \
-  "global_load_dwordx4 v[92:95], v15, %[gb] offset:48\n" FBG_J16_NEXT                     \
+  "global_load_dwordx4 v[92:95], v15, %[gb] offset:48\n" FBG_J16_NEXT_S                   \
   "s_waitcnt vmcnt(0) lgkmcnt(0)\n" FBG_J16_EACH(FBG_J16_REGL_W, #TT) FBG_J16_DISPATCH
 
+// chains (fbg_isa.h): the first set sets X and Y from cur = all-ones and cur
+// = zero, each further set updates them, and the last one then applies them
+// to the words: cur = (cur & X) | (~cur & Y)
+#define FBG_J16_XYF(TT) "v_bitop3_b32 v80, -1, v14, 0 bitop3:" TT "\n" "v_bitop3_b32 v81, 0, v14, 0 bitop3:" TT "\n"
+#define FBG_J16_XYM(TT) "v_bitop3_b32 v80, v80, v14, 0 bitop3:" TT "\n" "v_bitop3_b32 v81, v81, v14, 0 bitop3:" TT "\n"
+#define FBG_J16_C_XYF_OR(TT) FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_XYF(#TT) FBG_J16_DISPATCH
+#define FBG_J16_C_XYF_XOR(TT) FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_XYF(#TT) FBG_J16_DISPATCH
+#define FBG_J16_C_XYM_OR(TT) FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_DISPATCH
+#define FBG_J16_C_XYM_XOR(TT) FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_DISPATCH
+#define FBG_J16_XYAPPLY(i) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v80, v81 bitop3:0xca\n"
+#define FBG_J16_C_XYL_OR(TT) \
+  FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_W16(FBG_J16_XYAPPLY) FBG_J16_DISPATCH
+#define FBG_J16_C_XYL_XOR(TT) \
+  FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_W16(FBG_J16_XYAPPLY) FBG_J16_DISPATCH
+
 #define FBG_J16_C_ST_V(INVOUT)                                                                  \
-  "s_set_gpr_idx_on s49, gpr_idx(DST)\n" FBG_J16_NEXT "s_nop 1\n" FBG_J16_W16(FBG_J16_STV)     \
+  "s_set_gpr_idx_on s49, gpr_idx(DST)\n" FBG_J16_NEXT_S "s_nop 1\n" FBG_J16_W16(FBG_J16_STV)     \
   "s_set_gpr_idx_off\n" INVOUT FBG_J16_DISPATCH
 #define FBG_J16_C_ST_L(INVOUT, G)                                             \
   "s_cmp_lt_u32 s49, %[ldsb]\n"                                              \
@@ -143,7 +163,7 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "ds_write_b128 v15, v[16:19]\n"                                             \
   "ds_write_b128 v15, v[20:23] offset:16\n"                                   \
   "ds_write_b128 v15, v[24:27] offset:32\n"                                   \
-  "ds_write_b128 v15, v[28:31] offset:48\n" FBG_J16_NEXT INVOUT FBG_J16_DISPATCH
+  "ds_write_b128 v15, v[28:31] offset:48\n" FBG_J16_NEXT_S INVOUT FBG_J16_DISPATCH
 #define FBG_J16_G_ST_L(INVOUT, G)                                             \
   "LGST" #G "%=:\n"                                                           \
   "s_sub_u32 s72, s49, %[ldsb]\n"                                            \
@@ -151,7 +171,7 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "global_store_dwordx4 v15, v[16:19], %[gb]\n"                              \
   "global_store_dwordx4 v15, v[20:23], %[gb] offset:16\n"                    \
   "global_store_dwordx4 v15, v[24:27], %[gb] offset:32\n"                    \
-  "global_store_dwordx4 v15, v[28:31], %[gb] offset:48\n" FBG_J16_NEXT INVOUT FBG_J16_DISPATCH
+  "global_store_dwordx4 v15, v[28:31], %[gb] offset:48\n" FBG_J16_NEXT_S INVOUT FBG_J16_DISPATCH
 // cur inverted after a store: the store has read cur first
 #define FBG_J16_INVOUT_CUR FBG_J16_W16(FBG_J16_NOTCUR)
 #define FBG_J16_INVOUT_AFTER_DS "s_waitcnt lgkmcnt(0)\n" FBG_J16_W16(FBG_J16_NOTCUR)
@@ -195,11 +215,11 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   ".p2align 8\n"                                                                                             \
   "Lc%=:\n"                                                                                                  \
   FBG_J16_CASE(0)  "s_branch Ld%=\n"                                                                         \
-  FBG_J16_CASE(1)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_NOTCUR) FBG_J16_DISPATCH                                  \
-  FBG_J16_CASE(2)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCAND) FBG_J16_DISPATCH                                  \
-  FBG_J16_CASE(3)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_DISPATCH                                 \
-  FBG_J16_CASE(4)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCAND) FBG_J16_INVOUT_CUR FBG_J16_DISPATCH               \
-  FBG_J16_CASE(5)  FBG_J16_NEXT FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_INVOUT_CUR FBG_J16_DISPATCH              \
+  FBG_J16_CASE(1)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_NOTCUR) FBG_J16_DISPATCH                                \
+  FBG_J16_CASE(2)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_ACCAND) FBG_J16_DISPATCH                                \
+  FBG_J16_CASE(3)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_DISPATCH                               \
+  FBG_J16_CASE(4)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_ACCAND) FBG_J16_INVOUT_CUR FBG_J16_DISPATCH             \
+  FBG_J16_CASE(5)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_INVOUT_CUR FBG_J16_DISPATCH            \
   FBG_J16_CASE(6)  FBG_J16_C_ST_V("")                                                                        \
   FBG_J16_CASE(7)  FBG_J16_C_ST_V(FBG_J16_INVOUT_CUR)                                                        \
   FBG_J16_CASE(8)  FBG_J16_C_ST_L("", 0)                                                                     \
@@ -210,13 +230,20 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASES_NP(FBG_J16_C_LITXOR, 46)                                                                     \
   FBG_J16_CASES_ORP(FBG_J16_C_LITORP, 58)                                                                    \
   FBG_J16_CASES_XORP(FBG_J16_C_LITXORP, 70)                                                                  \
-  FBG_J16_CASE(78)                                                                                           \
+  FBG_J16_CASES_NP(FBG_J16_C_XYF_OR, 78)                                                                     \
+  FBG_J16_CASES_NP(FBG_J16_C_XYF_XOR, 90)                                                                    \
+  FBG_J16_CASES_NP(FBG_J16_C_XYM_OR, 102)                                                                    \
+  FBG_J16_CASES_NP(FBG_J16_C_XYM_XOR, 114)                                                                   \
+  FBG_J16_CASES_NP(FBG_J16_C_XYL_OR, 126)                                                                    \
+  FBG_J16_CASES_NP(FBG_J16_C_XYL_XOR, 138)                                                                   \
+  FBG_J16_CASE(150)                                                                                          \
   "Ld%=:\n"                                                                                                  \
   "s_mov_b32 m0, s83\n"
 // clang-format on
 
-static_assert(FBG_J16_NCASES == 78 && FBG_J16_SLOT == 256,
-              "the case list of FBG_J16_PROGRAM and the clamp 0x4e00 = 78 x 256 of FBG_J16_DISPATCH");
+static_assert(FBG_J16_NCASES == 150 && FBG_J16_SLOT == 256 && FBG_J16_XYF_OR == 78 && FBG_J16_XYF_XOR == 90 &&
+                  FBG_J16_XYM_OR == 102 && FBG_J16_XYM_XOR == 114 && FBG_J16_XYL_OR == 126 && FBG_J16_XYL_XOR == 138,
+              "the case list of FBG_J16_PROGRAM and the clamp 0x9600 = 150 x 256 of FBG_J16_DISPATCH");
 
 // Run the general part of a program (jump-table form at `code`, its pattern
 // table at `table`) on the 16 words of this lane of tile group U0.  acc comes

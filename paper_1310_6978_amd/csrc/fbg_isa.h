@@ -117,19 +117,37 @@
  * instructions after the clause block use another encoding, run by an
  * interpreter that jumps straight to the code of each instruction instead of
  * deciding among the cases with a chain of compares (kernels: fbg_asm16.h).
- * Still 8 x uint32 per instruction:
+ * Literal-set instructions take 8 x uint32, all others 2:
  *   w0 bits 0..15   byte offset of the instruction's case in the jump table
  *                   (case number x FBG_J16_SLOT)
  *      bits 16..31  literal sets with word-index literals: byte offset of
  *                   their 16 pattern words in the pattern table
  *   w1           literal sets: mconst; register ops: the register's place,
  *                r x 16 for VGPR registers (r < 3: a VGPR index offset),
- *                (r - 3) x 4096 for LDS registers (a byte offset)
- *   w2..w7       literal sets: lanemask, sel, neg as above
- * The case fixes the operation and its truth table; the cases are listed
- * below (FBG_J16_*).  A case END follows the last instruction, and the
- * pattern table starts after it.  LDS registers hold a lane's 16 words
+ *                (r - 3) x 4096 for LDS registers (a byte offset); unused
+ *                by ACC and NOT
+ *   w2..w7       literal sets only: lanemask, sel, neg as above
+ * The case fixes the operation, its truth table and the instruction's length
+ * (the case fetches the next instruction that far on); the cases are listed
+ * below (FBG_J16_*).  A case END, padded to 8 words, follows the last
+ * instruction, and the pattern table starts after it; the number of
+ * instructions given for this form counts its length in units of 2 words,
+ * END included.  The short forms halve the program bytes the scalar cache
+ * streams through per tile.  LDS registers hold a lane's 16 words
  * contiguously (64 bytes per lane, 4096 per register and wave).
+ *
+ * Chains.  Two or more literal-set operations in a row, none with word
+ * literals, act on cur through per-lane values only: bit by bit the chain
+ * maps cur to (cur & X) | (~cur & Y), where X is what the chain makes of an
+ * all-ones cur and Y what it makes of zero.  The jump-table form runs such a
+ * run as XYF (X = f(~0, T), Y = f(0, T) for its first operation), XYM (X =
+ * f(X, T), Y = f(Y, T) for each further one but the last) and XYL (the last:
+ * X and Y updated, then per word one v_bitop3 over (cur, X, Y)): per lane two
+ * operations per set instead of one per word, and one pass over the words
+ * for the whole run.  X and Y live only inside a chain (an XYF always starts
+ * one, an XYL always ends it).  In the plain form's terms (the disassembly
+ * and the emulator) they are the opcodes XYF, XYM and XYL, which the plain
+ * encoding never contains.
  */
 #ifndef FBG_ISA_H
 #define FBG_ISA_H
@@ -144,6 +162,10 @@
 #define FBG_OP_ACC 6u
 #define FBG_OP_LDR 7u
 #define FBG_OP_NOT 8u
+/* chain operations: only as the decoded jump-table form (see Chains) */
+#define FBG_OP_XYF 9u
+#define FBG_OP_XYM 10u
+#define FBG_OP_XYL 11u
 
 #define FBG_XORSET (1u << 4)
 #define FBG_HASPAT (1u << 5)
@@ -157,11 +179,14 @@
 
 #define FBG_INS_WORDS 8
 /* Words per lane of the jump-table form, and where the pattern table starts
-   (in words after the first instruction): after the nins instructions, and
-   after the END that closes them in the jump-table form. */
+   (in words after the first instruction): after the nins instructions, or
+   in the jump-table form after nins units of FBG_J16_UNIT words (END
+   included). */
 #define FBG_J16_LOG2W 4
 #define FBG_J16_VGPR_REGS 3   /* registers 0..2 in VGPRs, the rest in LDS */
-#define FBG_TABLE_OFFSET(nins, log2w) (((nins) + ((log2w) == FBG_J16_LOG2W ? 1u : 0u)) * FBG_INS_WORDS)
+#define FBG_TABLE_OFFSET(nins, log2w) ((log2w) == FBG_J16_LOG2W ? (nins) * FBG_J16_UNIT : (nins) * FBG_INS_WORDS)
+#define FBG_J16_UNIT 2u       /* words per length unit of the jump-table form */
+#define FBG_J16_SHORT_WORDS 2u /* register, ACC and NOT instructions */
 #define FBG_CB_HDR 4        /* words of the clause-block header */
 #define FBG_CB_CHUNK 32     /* clauses per chunk */
 #define FBG_CB_CHUNK_HDR 16 /* words of a chunk header */
@@ -183,7 +208,13 @@
 #define FBG_J16_LIT_XOR 46u     /* XOR-set, no word literal: + index in FBG_J16_NP_TABLES */
 #define FBG_J16_LIT_OR_P 58u    /* OR-set with word literals: + index in FBG_J16_OR_TABLES */
 #define FBG_J16_LIT_XOR_P 70u   /* XOR-set with word literals: + index in FBG_J16_XOR_TABLES */
-#define FBG_J16_NCASES 78u
+#define FBG_J16_XYF_OR 78u      /* first set of a chain, OR-set: + index in FBG_J16_NP_TABLES */
+#define FBG_J16_XYF_XOR 90u     /* first set of a chain, XOR-set */
+#define FBG_J16_XYM_OR 102u     /* further set of a chain, OR-set */
+#define FBG_J16_XYM_XOR 114u    /* further set of a chain, XOR-set */
+#define FBG_J16_XYL_OR 126u     /* last set of a chain, then cur = (cur & X) | (~cur & Y) */
+#define FBG_J16_XYL_XOR 138u
+#define FBG_J16_NCASES 150u
 /* Truth tables of the cases, over (cur = 0xF0, T or R = 0xCC, P = 0xAA).
    Without word literals P is 0, so only the bits of 0x55 matter. */
 #define FBG_J16_REG_TABLES(X) X(0xC0) X(0x30) X(0xFC) X(0xF3) X(0x3C) X(0xC3) X(0x3F) X(0xCF) X(0x03) X(0x0C) X(0xCC) X(0x33)

@@ -19,7 +19,7 @@ inline uint32_t vgpr_regs_of(int log2w) { return log2w == FBG_J16_LOG2W ? kJ16Vg
 
 struct EvalArgs {
   const uint32_t *code;   // encoded program: clause block, instructions, pattern table
-  uint32_t nins;          // instructions after the clause block
+  uint32_t nins;          // instructions after the clause block (16 words per lane: 2-word units)
   uint32_t nregs;         // registers held in LDS (beyond vgpr_regs_of(log2w))
   int32_t n;              // variables
   uint64_t nslices;       // 2^max(n-5, 0) valid 32-bit words

@@ -269,3 +269,49 @@ def test_registers_beyond_the_vgpr_set(k):
     text = many_registers(rng, 14, k)
     p = check(text, 14, wpl=[1, 4, 8])
     assert p.info["n_regs"] >= min(k, 5) - 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_chains_of_literal_sets(seed):
+    """At 16 words per lane, two or more literal sets in a row without
+    word-index literals (x11..x14) run as a chain: XYF, XYM ..., XYL, and the
+    emulated chain (X and Y per lane, then one pass over the words) equals
+    the oracle.  Runs of every length from 1 to 6, OR- and XOR-sets, with lane,
+    in-word and tile literals (x15..)."""
+    rng = random.Random(5100 + seed)
+    n = 19
+    pool = [v for v in range(n) if not 11 <= v <= 14]
+    parts = []
+    for _ in range(4):
+        e = "x%d" % rng.choice(pool)
+        for _ in range(rng.randrange(1, 7)):
+            lit = ("~" if rng.random() < 0.3 else "") + "x%d" % rng.choice(pool)
+            e = "(%s %s %s)" % (e, rng.choice("&|^"), lit)
+        parts.append(e)
+    text = "(%s ^ %s) | (%s & ~%s)" % tuple(parts)
+    p = check(text, n, wpl=[16, 1, 32])
+    ops = [op for _, op in instructions(p.disasm(16))]
+    # every chain opens with XYF, continues with XYM and closes with XYL
+    i = 0
+    while i < len(ops):
+        if ops[i] == "XYF":
+            j = i + 1
+            while ops[j] == "XYM":
+                j += 1
+            assert ops[j] == "XYL", ops
+            i = j + 1
+        else:
+            assert ops[i] not in ("XYM", "XYL"), ops
+            i += 1
+    assert "XYF" not in [op for _, op in instructions(p.disasm(8))]
+    # the plain form and the jump-table form hold the same instructions
+    assert len(ops) == len(instructions(p.disasm(8)))
+
+
+def test_run_of_four_literal_sets_is_one_chain():
+    """Four literal sets in a row (lane, in-word and tile literals) become
+    XYF, XYM, XYM, XYL; the clause x9 stays in the clause block."""
+    text = "((((x0 ^ x6) & x7) | x16) ^ x2) & x9"
+    p = fbg.Program(text, 18)
+    assert [op for _, op in instructions(p.disasm(16))][:4] == ["XYF", "XYM", "XYM", "XYL"]
+    check(text, 18, wpl=[16])
