@@ -150,6 +150,11 @@ struct fbg_program {
   std::vector<uint32_t> words[kMaxLog2W + 1];
   uint64_t dev_off[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
   uint32_t nins[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
+  // programs of clauses alone with n >= kXcdMinVars: the 32-words-per-lane
+  // encoding with variables exchanged for the XCD-local DNF write-out
+  std::vector<uint32_t> words_xcd;
+  uint64_t dev_off_xcd = 0;
+  bool has_xcd = false;
   uint32_t ncl = 0;  // leading clause instructions
   int auto_log2w = 0;
   uint64_t nslices = 1;
@@ -199,6 +204,7 @@ struct fbg_batch {
   std::vector<int> plan_of;               // plan index of every program
   uint64_t total_tiles = 0;
   uint32_t *d_tile_counts = nullptr;
+  uint32_t *d_chunk_counts = nullptr;     // XCD-local write-out: counts per 4 KiB piece
   uint64_t *d_offsets = nullptr;
   uint64_t *d_scan_blk = nullptr;
   uint32_t *d_tile_list = nullptr;        // tiles holding models, then their number
@@ -327,6 +333,7 @@ fbg::BatchProg batch_prog(const fbg_program *p, int l) {
   b.n = p->c.n;
   b.nslices = p->nslices;
   b.ntiles = tiles_of(p->nslices, l);
+  if (l == 5 && p->has_xcd && p->d_code) b.xcd_code = p->d_code + p->dev_off_xcd;
   return b;
 }
 
@@ -414,6 +421,14 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
     p->dev_off[l] = total;
     total += p->words[l].size();
   }
+  if (!p->general() && p->c.n >= fbg::kXcdMinVars) {
+    const fbg::Compiled x = fbg::exchange_variables(p->c, fbg::kXcdSwapA, fbg::kXcdSwapB, fbg::kXcdSwapLen);
+    const uint32_t nx = fbg::encode_program(x, 5, p->words_xcd, &enc_err);
+    if (nx != p->nins[5] && enc_err.empty()) enc_err = "internal: exchanged encoding differs in length";
+    p->dev_off_xcd = total;
+    total += p->words_xcd.size();
+    p->has_xcd = true;
+  }
   if (!enc_err.empty()) {
     delete p;
     return fail(FBG_E_RANGE, "%s", enc_err.c_str());
@@ -430,6 +445,7 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
     std::vector<uint32_t> all;
     all.reserve(total + 64);
     for (int l = 0; l <= kMaxLog2W; l++) all.insert(all.end(), p->words[l].begin(), p->words[l].end());
+    all.insert(all.end(), p->words_xcd.begin(), p->words_xcd.end());
     all.resize(all.size() + 64, 0);  // padding: scalar loads never run past the allocation
     e = CodeArena::of(dev).alloc(all.size() * sizeof(uint32_t), (void **)&p->d_code, p->code_class);
     p->code_bytes = p->code_class >= 0 ? (1ull << p->code_class) : all.size() * sizeof(uint32_t);
@@ -821,8 +837,16 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     }
     std::vector<fbg::BatchItem> direct;
     if (var == 0 && !(tune && tune->grid_blocks > 0)) {
+      bool any_xcd = false;
       for (int32_t i : members) {
         const fbg::BatchProg &q = b->host_progs[(size_t)i];
+        if (q.xcd_code) {
+          // the XCD-local layout: the program starts at a multiple of 32
+          // tiles, so that block k of its waves runs on XCD k mod 8 (the
+          // tiles in between belong to no program and are skipped)
+          pl.ntiles = (pl.ntiles + 31) & ~(uint64_t)31;
+          any_xcd = true;
+        }
         fbg::BatchItem it;
         it.prog = (uint32_t)i;
         it.slot = (uint32_t)i;
@@ -834,6 +858,9 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
         pl.max_prog_tiles = std::max<uint64_t>(pl.max_prog_tiles, q.ntiles);
       }
       pl.ndirect = (uint32_t)direct.size();
+      // one tile per wave, four waves per block: a block's tiles share bits
+      // 2..4 of their tile index, i.e. one residue class of 4 KiB pieces
+      if (any_xcd && !(tune && tune->direct_run > 0)) pl.direct_run = 1;
     }
     b->plans.push_back(pl);
     plan_items.push_back(std::move(sorted));
@@ -938,7 +965,10 @@ fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, cons
                   (unsigned long long)need);
     q.out32 = (uint32_t *)d_outs[i];
     q.out_slices = 2 * need;
-    if (!b->host_dnf.empty()) q.tile_counts = b->host_dnf[(size_t)i].tile_counts;
+    if (!b->host_dnf.empty()) {
+      q.tile_counts = b->host_dnf[(size_t)i].tile_counts;
+      q.chunk_counts = b->host_dnf[(size_t)i].chunk_counts;
+    }
   }
   hipError_t e = hipSuccess;
   if (!b->d_progs_dnf) e = hipMalloc((void **)&b->d_progs_dnf, t.size() * sizeof(fbg::BatchProg));
@@ -957,10 +987,18 @@ fbg_status fbg_batch_set_enum_outputs(fbg_batch *b, uint64_t *const *d_idx, cons
   for (int32_t i = 0; i < b->np; i++)
     if (capacity[i] > 0 && !d_idx[i]) return fail(FBG_E_INVAL, "d_idx[%d] is NULL with capacity %llu", i,
                                                   (unsigned long long)capacity[i]);
+  // programs whose DNF write-out takes the XCD-local layout: two piece
+  // counts per tile
+  auto xcd_direct = [&](int32_t i) {
+    return b->host_progs[(size_t)i].xcd_code && b->plans[(size_t)b->plan_of[(size_t)i]].d_direct;
+  };
   hipError_t e = hipSuccess;
   if (!b->d_tile_counts) {
-    uint64_t total = 0;
-    for (const auto &q : b->host_progs) total += q.ntiles;
+    uint64_t total = 0, chunks = 0;
+    for (int32_t i = 0; i < b->np; i++) {
+      total += b->host_progs[(size_t)i].ntiles;
+      if (xcd_direct(i)) chunks += 2 * b->host_progs[(size_t)i].ntiles;
+    }
     if (total >= (1ull << 32)) return fail(FBG_E_RANGE, "%llu tiles: batched enumeration lists tiles in 32 bits",
                                            (unsigned long long)total);
     b->total_tiles = total;
@@ -970,13 +1008,19 @@ fbg_status fbg_batch_set_enum_outputs(fbg_batch *b, uint64_t *const *d_idx, cons
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_scan_blk, (nb + 2) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_enum, (size_t)b->np * sizeof(fbg::EnumProg));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_tile_list, (std::max<uint64_t>(total, 1) + 64) * sizeof(uint32_t));
+    if (e == hipSuccess && chunks) e = hipMalloc((void **)&b->d_chunk_counts, chunks * sizeof(uint32_t));
     if (e != hipSuccess) return fail(FBG_E_NOMEM, "enumeration buffers: %s", hipGetErrorString(e));
   }
   std::vector<fbg::EnumProg> ep((size_t)b->np);
-  uint64_t tile0 = 0;
+  uint64_t tile0 = 0, chunk0 = 0;
   for (int32_t i = 0; i < b->np; i++) {
     fbg::BatchProg &q = b->host_dnf[(size_t)i];
     q.tile_counts = b->d_tile_counts + tile0;
+    q.chunk_counts = nullptr;
+    if (xcd_direct(i)) {
+      q.chunk_counts = b->d_chunk_counts + chunk0;
+      chunk0 += 2 * q.ntiles;
+    }
     fbg::EnumProg &x = ep[(size_t)i];
     memset(&x, 0, sizeof x);
     x.dnf = q.out32;
@@ -1070,6 +1114,7 @@ void fbg_batch_free(fbg_batch *b) {
   if (b->d_progs) (void)hipFree(b->d_progs);
   if (b->d_progs_dnf) (void)hipFree(b->d_progs_dnf);
   if (b->d_tile_counts) (void)hipFree(b->d_tile_counts);
+  if (b->d_chunk_counts) (void)hipFree(b->d_chunk_counts);
   if (b->d_offsets) (void)hipFree(b->d_offsets);
   if (b->d_scan_blk) (void)hipFree(b->d_scan_blk);
   if (b->d_enum) (void)hipFree(b->d_enum);

@@ -1338,6 +1338,18 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
   return per_tile / W;
 }
 
+Compiled exchange_variables(const Compiled &c, int a, int b, int len) {
+  Compiled r = c;
+  for (HIns &h : r.code)
+    for (Lit &l : h.ls.lits) {
+      if (l.k >= a && l.k < a + len)
+        l.k += b - a;
+      else if (l.k >= b && l.k < b + len)
+        l.k -= b - a;
+    }
+  return r;
+}
+
 uint32_t leading_clauses(const Compiled &c) {
   // the code generator emits every clause before any other instruction
   uint32_t k = 0;

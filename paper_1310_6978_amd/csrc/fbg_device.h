@@ -818,28 +818,64 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
   for (uint64_t g = g0; g < g0 + a.run && g < end; ++g) {  // wave-uniform
     while (g >= items[lo].t1) lo++;  // the run crossed into the next program
     const item_ptr it = items + lo;
+    if (g < it->t0) continue;  // padding in front of a program of the XCD-local layout
     const prog_ptr p = (prog_ptr)a.progs + it->prog;
     const uint64_t t = g - it->t0;
     const uint64_t U0 = t << LOG2W;
     uint32_t acc[W];
     GenState<W> st;  // unused: clause-only programs
-    run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, st, nullptr);
-    const uint32_t c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
-    const uint32_t tc = wave_sum_u32(c);
-    if (lane == 0) p->tile_counts[t] = tc;
+    if (LOG2W == 5 && p->xcd_code && p->chunk_counts) {
+      // XCD-local layout (fbg_kernels.h): the exchanged program's tile t is
+      // the pieces x + 8 h + 16 (t & 3) + 64 (t >> 5) of the vector, h = 0, 1
+      // (words 0..15 and 16..31 of each lane), x = bits 2..4 of t; full tiles
+      // only (n >= 21)
+      run_program<LOG2W, false>(p->xcd_code, p->nins, U0, lane, acc, st, nullptr);
+      const uint64_t piece = ((t >> 2) & 7) + 16 * (t & 3) + 64 * (t >> 5);
+      uint32_t *dst = p->out32 + piece * 1024 + lane;
+      uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+      for (int i = 0; i < W; i++) {
+        __builtin_nontemporal_store(acc[i], dst + (i >> 4) * 8192 + (i & 15) * 64);
+        if (i < 16)
+          c0 += __popc(acc[i]);
+        else
+          c1 += __popc(acc[i]);
+      }
+      c0 = wave_sum_u32(c0);
+      c1 = wave_sum_u32(c1);
+      if (lane == 0) {
+        p->chunk_counts[piece] = c0;
+        p->chunk_counts[piece + 8] = c1;
+      }
+    } else {
+      run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, st, nullptr);
+      const uint32_t c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
+      const uint32_t tc = wave_sum_u32(c);
+      if (lane == 0) p->tile_counts[t] = tc;
+    }
   }
 }
 
 #ifdef FBG_DEVICE_BATCH_KERNELS  // defined once, in batch.hip
 // Counts after k_batch_direct: block (m, y) adds its share of the tile counts
-// of entry m's program into that program's count slot (zeroed before).
+// of entry m's program into that program's count slot (zeroed before).  For a
+// program of the XCD-local layout it first forms each tile count from the
+// counts of the tile's two 4 KiB pieces.
 __global__ __launch_bounds__(256) void k_sum_tile_counts(BatchArgs a) {
   __shared__ uint64_t part[4];
   const BatchItem &it = a.items[blockIdx.x];
   const BatchProg &p = a.progs[it.prog];
   uint64_t s = 0;
-  for (uint64_t t = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; t < p.ntiles; t += (uint64_t)gridDim.y * blockDim.x)
-    s += p.tile_counts[t];
+  const bool xcd = p.xcd_code && p.chunk_counts;
+  for (uint64_t t = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; t < p.ntiles; t += (uint64_t)gridDim.y * blockDim.x) {
+    if (xcd) {
+      const uint32_t v = p.chunk_counts[2 * t] + p.chunk_counts[2 * t + 1];
+      p.tile_counts[t] = v;
+      s += v;
+    } else {
+      s += p.tile_counts[t];
+    }
+  }
   s = wave_sum_u64(s);
   if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();

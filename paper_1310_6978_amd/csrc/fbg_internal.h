@@ -61,6 +61,11 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
 // Number of leading clause (CL) instructions; no CL follows them.
 uint32_t leading_clauses(const Compiled &c);
 
+// The same program with variables a .. a+len-1 and b .. b+len-1 exchanged
+// (the two ranges disjoint): evaluated at index k it gives the original's
+// value at k with those two bit fields exchanged.
+Compiled exchange_variables(const Compiled &c, int a, int b, int len);
+
 // VALU instructions per 32-bit slice the evaluator issues for an encoded
 // program (a static count per tile, divided by the words per lane; the
 // popcount and store epilogue excluded).

@@ -33,6 +33,23 @@ struct EvalArgs {
   uint64_t capacity;      // MODE_ENUM
 };
 
+// The XCD-local layout of the batched DNF write-out (32 words per lane, a
+// program made of clauses alone, n >= kXcdMinVars).  The write-out kernel
+// evaluates a second encoding of the program whose variables 15..17 and
+// 18..20 are exchanged, so its tile t (64 lanes x 32 words) holds the words
+// of the DNF vector whose word index has bits 10..12 equal to bits 2..4 of t
+// (bits 13..15: word bit 4 and bits 0..1 of t; 0..9: lane and word bits 0..3;
+// 16 and up: bits 5 and up of t).  Such a tile is two whole 4 KiB pieces
+// of the vector, 8 KiB apart, whose piece index is congruent to bits 2..4 of
+// t modulo 8: with one tile per wave and four waves per block, every block
+// (blocks go to the eight XCDs in turn) writes the pieces of one residue
+// class, which HBM absorbs faster than the same bytes in plain order.  A
+// piece's model count goes to chunk_counts (one per 4 KiB piece, in vector
+// order); k_sum_tile_counts adds the two pieces of each 8 KiB tile into the
+// tile counts the batched enumeration reads.
+constexpr int kXcdSwapA = 15, kXcdSwapB = 18, kXcdSwapLen = 3;
+constexpr int kXcdMinVars = 21;
+
 struct BatchProg {
   const uint32_t *code;
   uint32_t nins;
@@ -43,6 +60,10 @@ struct BatchProg {
   uint32_t *out32;      // MODE_DNF: the program's DNF vector
   uint64_t out_slices;  // MODE_DNF: 32-bit words of out32
   uint32_t *tile_counts;  // MODE_DNF: per-tile model counts (or null)
+  // the batched DNF write-out in the XCD-local layout (or null): the program
+  // with variables exchanged, and the per-piece model counts it writes
+  const uint32_t *xcd_code;
+  uint32_t *chunk_counts;
 };
 
 // One program of a batched enumeration over stored DNF vectors.

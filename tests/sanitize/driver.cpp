@@ -6,7 +6,11 @@
 // For each case it prints "ERR <status>" when the text does not compile,
 // else one line per words-per-lane setting and evaluation variant:
 //   "<log2w> <cof> <hex words of the emulated DNF vector>"
-// and walks the listing and the VALU count of every encoding.
+// and walks the listing and the VALU count of every encoding.  For n >= 21
+// it also prints "X <hex words>": the 32-words-per-lane encoding of the
+// program with variables 15..17 and 18..20 exchanged, emulated, and each
+// emulated word put back at the index with word-index bits 10..12 and 13..15
+// exchanged (the layout of the XCD-local DNF write-out).
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -51,6 +55,22 @@ int main() {
           printf(" %llx", (unsigned long long)((uint64_t)out32[2 * w] | ((uint64_t)out32[2 * w + 1] << 32)));
         printf("\n");
       }
+    }
+    if (c.n >= 21) {
+      const fbg::Compiled x = fbg::exchange_variables(c, 15, 18, 3);
+      std::vector<uint32_t> words;
+      std::string err;
+      const uint32_t nins = fbg::encode_program(x, 5, words, &err);
+      std::vector<uint32_t> em((size_t)slices, 0u), out32((size_t)slices, 0u);
+      fbg::emulate_program(words, nins, x.nregs, x.n, 5, false, em.data());
+      for (uint64_t s = 0; s < slices; s++) {
+        const uint64_t lo = (s >> 10) & 7, hi = (s >> 13) & 7;
+        out32[(size_t)((s & ~(uint64_t)(63u << 10)) | (lo << 13) | (hi << 10))] = em[(size_t)s];
+      }
+      printf("X");
+      for (uint64_t w = 0; w < words64; w++)
+        printf(" %llx", (unsigned long long)((uint64_t)out32[2 * w] | ((uint64_t)out32[2 * w + 1] << 32)));
+      printf("\n");
     }
   }
   return 0;

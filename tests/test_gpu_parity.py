@@ -549,6 +549,42 @@ def test_batch_dnf_with_tile_counts(F):
         b.free()
 
 
+@pytest.mark.parametrize("run", [0, 1, 4])
+def test_batch_dnf_xcd_local_layout(F, run):
+    """Programs of clauses alone with n >= 21 are written out by the batched
+    write-out in the XCD-local layout (an encoding with variables 15..17 and
+    18..20 exchanged; piece counts summed into tile counts): DNF vectors,
+    counts and the batched enumeration equal the oracle, next to smaller
+    programs in the same plan (whose tiles pad the XCD-aligned starts), at the
+    default one tile per wave and at explicit runs of tiles."""
+    import torch
+    texts = [workloads.random_3cnf(12, 51, 1), workloads.random_3cnf(21, 89, 2), ("x3 & ~x11", 14),
+             workloads.random_3cnf(22, 94, 3), workloads.random_3cnf(19, 81, 4), ("~x20 | x16 & x17", 21),
+             workloads.random_3cnf(24, 102, 5), ("x15 & x18 & ~x19", 22)]
+    progs = [F.Program(t, n) for t, n in texts]
+    wants = [oracle.dnf(t, n) for t, n in texts]
+    cap = 3000
+    models = [oracle.models(t, n, cap=cap) for t, n in texts]   # (first cap models, total)
+    b = F.Batch(progs, words_per_lane=32, direct_run=run)
+    dnfs = [torch.full((F.dnf_words(n) + 1,), -1, dtype=torch.int64, device="cuda") for _, n in texts]
+    idx = [torch.full((cap,), -1, dtype=torch.int64, device="cuda") for _ in texts]
+    b.set_dnf_outputs(dnfs)
+    b.set_enum_outputs(idx)
+    for rep in range(2):
+        for o in dnfs:
+            o.fill_(-1)
+        print("xcd layout: run %d, repeat %d" % (run, rep), flush=True)
+        counts = host(b.eval_dnf())
+        b.enumerate()
+        for (t, n), w, (m, total), o, ii, c in zip(texts, wants, models, dnfs, idx, counts):
+            got = host(o)
+            assert np.array_equal(got[:len(w)], w), (run, n, rep)
+            assert got[len(w)] == np.uint64(2**64 - 1)
+            assert int(c) == total, (run, n, rep)
+            assert np.array_equal(host(ii)[:len(m)], m), (run, n, rep)
+    b.free()
+
+
 def test_batch_enumerate_needs_outputs(F):
     import torch
     p = F.Program("x1 & x5", 9)

@@ -74,6 +74,23 @@ def test_random_formulas_under_sanitizers(driver):
             assert np.array_equal(got, want), (f[:2], text[:200])
 
 
+def test_exchanged_variables_give_the_xcd_local_layout(driver):
+    """The second encoding of the batched DNF write-out: the program with
+    variables 15..17 and 18..20 exchanged, emulated at 32 words per lane, puts
+    at word index s the DNF word whose index is s with bits 10..12 and 13..15
+    exchanged.  Clause-only formulas (the write-out's programs) and general
+    ones, n = 21 and 22."""
+    rng = random.Random(2101)
+    cases = [workloads.random_3cnf(21, 89, 4), workloads.random_3cnf(22, 94, 5),
+             (random_cnf(rng, 22, 60), 22), (random_program(rng, 21)[1], 21)]
+    lines = run(driver, cases)
+    xs = [l for l in lines if l.startswith("X")]
+    assert len(xs) == len(cases)
+    for (text, n), line in zip(cases, xs):
+        got = np.array([int(x, 16) for x in line.split()[1:]], dtype=np.uint64)
+        assert np.array_equal(got, oracle.dnf(text, n)), text[:200]
+
+
 def test_parser_fuzz_under_sanitizers(driver):
     rng = random.Random(5)
     alphabet = "x0123456789 ~&^|()=\n;#abt_"
