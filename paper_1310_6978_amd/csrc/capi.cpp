@@ -603,6 +603,8 @@ fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t ou
   fbg::EvalArgs a = base_args(p, g.log2w);
   a.out32 = (uint32_t *)d_out;
   a.out_slices = 2 * need;
+  // the XCD-local layout (fbg_kernels.h) on the grid of one tile per wave
+  if (g.log2w == 5 && p->has_xcd && p->variant(tune) == 0) a.xcd_code = p->d_code + p->dev_off_xcd;
   hipError_t e =
       fbg::launch_eval(fbg::EVAL_DNF, g.log2w, p->variant(tune), a, g.grid, g.block, g.lds, (hipStream_t)stream);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the DNF kernel");

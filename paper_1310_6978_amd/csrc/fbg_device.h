@@ -646,6 +646,14 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
       if (a.tile_counts[t] == 0u) return;  // no model in this tile
     }
     uint32_t acc[W];
+    if (LOG2W == 5 && VAR == 0 && MODE == MODE_DNF && a.xcd_code) {
+      // XCD-local layout (fbg_kernels.h): full tiles only (n >= 21)
+      run_program<LOG2W, false>(a.xcd_code, a.nins, U0, lane, acc, st, regs);
+      uint32_t *dst = a.out32 + (((t >> 2) & 7) + 16 * (t & 3) + 64 * (t >> 5)) * 1024 + lane;
+#pragma unroll
+      for (int i = 0; i < W; i++) __builtin_nontemporal_store(acc[i], dst + (i >> 4) * 8192 + (i & 15) * 64);
+      return;
+    }
     if (alive) {
       run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, st, regs, a.nregs * (W * 256u));
       mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);

@@ -27,6 +27,7 @@ struct EvalArgs {
   uint64_t *out_count;    // MODE_COUNT
   uint32_t *out32;        // MODE_DNF (written); stored-DNF scans (read)
   uint64_t out_slices;    // MODE_DNF: words written (>= nslices, >= 2)
+  const uint32_t *xcd_code;  // MODE_DNF at 32 words per lane: the XCD-local encoding, or null
   uint32_t *tile_counts;  // MODE_TILECNT (out), MODE_ENUM (in)
   const uint64_t *tile_offsets;  // MODE_ENUM
   uint64_t *out_idx;      // MODE_ENUM

@@ -585,6 +585,27 @@ def test_batch_dnf_xcd_local_layout(F, run):
     b.free()
 
 
+@pytest.mark.parametrize("grid", [0, 96])
+def test_single_dnf_xcd_local_layout(F, grid):
+    """fbg_eval_dnf of a program of clauses alone with n >= 21 at 32 words
+    per lane writes through the XCD-local encoding: the vector equals the
+    oracle's, on the default grid of one tile per wave and on an explicit
+    smaller grid whose waves stride over the tiles; the word after the
+    vector is untouched."""
+    import torch
+    for t, n in (workloads.random_3cnf(21, 89, 7), ("x15 & ~x18 | x20", 22), workloads.random_3cnf(23, 98, 8),
+                 ("~x16 & (x19 | x2)", 21)):
+        p = F.Program(t, n)
+        out = torch.full((F.dnf_words(n) + 1,), -1, dtype=torch.int64, device="cuda")
+        print("single xcd: n %d grid %d" % (n, grid), flush=True)
+        F.eval_dnf(p, out=out, words_per_lane=32, grid_blocks=grid)
+        got = host(out)
+        want = oracle.dnf(t, n)
+        assert np.array_equal(got[:len(want)], want), (n, grid)
+        assert got[len(want)] == np.uint64(2**64 - 1)
+        p.free()
+
+
 def test_batch_enumerate_needs_outputs(F):
     import torch
     p = F.Program("x1 & x5", 9)
