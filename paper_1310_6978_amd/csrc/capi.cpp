@@ -926,7 +926,8 @@ fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, u
       const uint64_t wpb = (uint64_t)(pl.block / 64);
       const uint64_t waves = (pl.ntiles + a.run - 1) / a.run;
       const uint64_t grid = (waves + wpb - 1) / wpb;
-      const int sum_blocks = (int)std::min<uint64_t>(64, std::max<uint64_t>(1, pl.max_prog_tiles / 4096));
+      // about 1024 tiles per block of the count sums (C1: 64 per program)
+      const int sum_blocks = (int)std::min<uint64_t>(256, std::max<uint64_t>(1, pl.max_prog_tiles / 1024));
       e = fbg::launch_batch_direct(pl.log2w, a, (int)grid, pl.block, sum_blocks, s);
       if (e != hipSuccess) return hip_fail(e, "launch of the batch kernel");
       continue;

@@ -851,10 +851,9 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
       }
       c0 = wave_sum_u32(c0);
       c1 = wave_sum_u32(c1);
-      if (lane == 0) {
-        p->chunk_counts[piece] = c0;
-        p->chunk_counts[piece + 8] = c1;
-      }
+      // the two piece counts side by side, in tile order: the four waves of a
+      // block fill 32 contiguous bytes
+      if (lane == 0) *(uint2 *)(p->chunk_counts + 2 * t) = make_uint2(c0, c1);
     } else {
       run_program<LOG2W, false>(p->code, p->nins, U0, lane, acc, st, nullptr);
       const uint32_t c = store_count_tile<LOG2W>(acc, U0, lane, p->nslices, p->n, p->out32, p->out_slices);
@@ -877,7 +876,14 @@ __global__ __launch_bounds__(256) void k_sum_tile_counts(BatchArgs a) {
   const bool xcd = p.xcd_code && p.chunk_counts;
   for (uint64_t t = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; t < p.ntiles; t += (uint64_t)gridDim.y * blockDim.x) {
     if (xcd) {
-      const uint32_t v = p.chunk_counts[2 * t] + p.chunk_counts[2 * t + 1];
+      // tile t of the vector is pieces 2t and 2t + 1; piece c came from
+      // tile (c & 7) << 2 | (c >> 4 & 3) | (c >> 6) << 5 of the exchanged
+      // program, its half c >> 3 & 1
+      uint32_t v = 0;
+      for (uint64_t c = 2 * t; c < 2 * t + 2; c++) {
+        const uint64_t k = ((c & 7) << 2) | ((c >> 4) & 3) | ((c >> 6) << 5);
+        v += p.chunk_counts[2 * k + ((c >> 3) & 1)];
+      }
       p.tile_counts[t] = v;
       s += v;
     } else {

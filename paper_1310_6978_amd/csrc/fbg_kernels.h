@@ -44,10 +44,10 @@ struct EvalArgs {
 // of the vector, 8 KiB apart, whose piece index is congruent to bits 2..4 of
 // t modulo 8: with one tile per wave and four waves per block, every block
 // (blocks go to the eight XCDs in turn) writes the pieces of one residue
-// class, which HBM absorbs faster than the same bytes in plain order.  A
-// piece's model count goes to chunk_counts (one per 4 KiB piece, in vector
-// order); k_sum_tile_counts adds the two pieces of each 8 KiB tile into the
-// tile counts the batched enumeration reads.
+// class, which HBM absorbs faster than the same bytes in plain order.  The
+// model counts of a tile's two pieces go to chunk_counts[2t], [2t + 1];
+// k_sum_tile_counts adds the two pieces of each 8 KiB tile of the vector
+// into the tile counts the batched enumeration reads.
 constexpr int kXcdSwapA = 15, kXcdSwapB = 18, kXcdSwapLen = 3;
 constexpr int kXcdMinVars = 21;
 
