@@ -1007,6 +1007,12 @@ int table_index(const uint32_t (&list)[N], uint32_t tt) {
   return -1;
 }
 
+// Words of a jump-table instruction of case cs: literal sets (chains
+// included) take 8, register, ACC and NOT instructions 2.
+uint32_t j16_words(uint32_t cs) {
+  return (cs >= FBG_J16_LIT_OR && cs < FBG_J16_ORS) || cs >= FBG_J16_XYS_OR ? FBG_INS_WORDS : FBG_J16_SHORT_WORDS;
+}
+
 // Rewrite the nins instructions at words[at..] into the jump-table form
 // (fbg_isa.h) and close them with END; returns the length of that form in
 // units of FBG_J16_UNIT words, END included (a NOT with INVOUT, which changes
@@ -1014,7 +1020,9 @@ int table_index(const uint32_t (&list)[N], uint32_t tt) {
 // when an instruction has no case (the code generator emits none such).
 uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, std::string *err) {
   std::vector<std::array<uint32_t, FBG_INS_WORDS>> out;
+  std::vector<uint32_t> pop;  // the plain opcode of each entry of out
   out.reserve(nins);
+  pop.reserve(nins);
   auto missing = [&](const char *what, uint32_t tt) {
     if (err && err->empty()) *err = std::string("internal: no jump-table case for ") + what + " table " +
                                     std::to_string(tt);
@@ -1056,6 +1064,7 @@ uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, s
     }
     w[0] |= cs * FBG_J16_SLOT;
     out.push_back(w);
+    pop.push_back(op);
   }
   // Runs of kMinChain or more literal sets without word literals become
   // chains: XYF, XYM ..., XYM, XYL (fbg_isa.h, Chains).
@@ -1078,12 +1087,53 @@ uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, s
     }
     k = e > k ? e : k + 1;
   }
+  // A store into a VGPR register after which cur is dead (the next
+  // instruction loads cur without reading it, or the program ends) merges
+  // into the instruction before it when that one can write the register
+  // itself: the last set of a chain (XYS) or an operation with that same
+  // register (ORS, both operands then addressed with the register's index).
+  auto st_v = [&](size_t k) {
+    const uint32_t cs = case_of(k);
+    return cs == FBG_J16_ST_V || cs == FBG_J16_ST_V + 1;
+  };
+  auto dead_after = [&](size_t k) {
+    return k + 1 >= out.size() || pop[k + 1] == FBG_OP_LDL || pop[k + 1] == FBG_OP_LDR;
+  };
+  {
+    std::vector<std::array<uint32_t, FBG_INS_WORDS>> merged;
+    std::vector<uint32_t> mpop;
+    merged.reserve(out.size());
+    for (size_t k = 0; k < out.size(); k++) {
+      const uint32_t cs = case_of(k);
+      if (k + 1 < out.size() && st_v(k + 1) && dead_after(k + 1)) {
+        if (cs >= FBG_J16_XYL_OR && cs < FBG_J16_XYL_OR + 24) {
+          std::array<uint32_t, FBG_INS_WORDS> w = out[k];
+          w[0] = ((out[k + 1][1] & 0xFFFFu) << 16) | (FBG_J16_XYS_OR + (cs - FBG_J16_XYL_OR)) * FBG_J16_SLOT;
+          merged.push_back(w);
+          mpop.push_back(FBG_OP_ST);
+          k++;
+          continue;
+        }
+        if (cs >= FBG_J16_REG_V && cs < FBG_J16_REG_L && out[k][1] == out[k + 1][1]) {
+          std::array<uint32_t, FBG_INS_WORDS> w = out[k];
+          w[0] = (FBG_J16_ORS + (cs - FBG_J16_REG_V)) * FBG_J16_SLOT;
+          merged.push_back(w);
+          mpop.push_back(FBG_OP_ST);
+          k++;
+          continue;
+        }
+      }
+      merged.push_back(out[k]);
+      mpop.push_back(pop[k]);
+    }
+    out.swap(merged);
+    pop.swap(mpop);
+  }
   // lay out: literal sets (and chain members) in full, the others short
   std::vector<uint32_t> flat;
   flat.reserve(out.size() * FBG_INS_WORDS + FBG_INS_WORDS);
   for (const auto &w : out) {
-    const uint32_t cs = (w[0] & 0xFFFFu) / FBG_J16_SLOT;
-    const uint32_t len = cs >= FBG_J16_LIT_OR ? FBG_INS_WORDS : FBG_J16_SHORT_WORDS;
+    const uint32_t len = j16_words((w[0] & 0xFFFFu) / FBG_J16_SLOT);
     flat.insert(flat.end(), w.begin(), w.begin() + len);
   }
   flat.resize(flat.size() + FBG_INS_WORDS, 0u);  // END, full length
@@ -1101,6 +1151,17 @@ static uint32_t from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
   for (int j = 0; j < FBG_INS_WORDS; j++) g[j] = 0;
   const uint32_t cs = (w[0] & 0xFFFFu) / FBG_J16_SLOT;
   if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) return 0;
+  if (cs >= FBG_J16_XYS_OR) {  // a chain's last set into R[r]
+    const uint32_t k = cs - FBG_J16_XYS_OR;
+    const uint32_t r = (w[0] >> 16) / 16u;
+    g[0] = FBG_OP_XYS | (k >= 12 ? FBG_XORSET : 0u) | (kJ16Np[k % 12] << FBG_F_SHIFT) | (r << FBG_ARG_SHIFT);
+    for (int j = 1; j < FBG_INS_WORDS; j++) g[j] = w[j];
+    return FBG_INS_WORDS;
+  }
+  if (cs >= FBG_J16_ORS) {  // R[r] = tt(cur, R[r])
+    g[0] = FBG_OP_ORS | (kJ16Reg[cs - FBG_J16_ORS] << FBG_F_SHIFT) | ((w[1] / 16u) << FBG_ARG_SHIFT);
+    return FBG_J16_SHORT_WORDS;
+  }
   if (cs >= FBG_J16_XYF_OR) {
     const uint32_t k = cs - FBG_J16_XYF_OR;  // 12 cases per (first / further / last, OR / XOR)
     const uint32_t ops[3] = {FBG_OP_XYF, FBG_OP_XYM, FBG_OP_XYL};
@@ -1300,8 +1361,12 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
     for (size_t at = 0; at < end;) {
       const uint32_t cs = (ins[at] & 0xFFFFu) / FBG_J16_SLOT;
       if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) break;
-      at += cs >= FBG_J16_LIT_OR ? FBG_INS_WORDS : FBG_J16_SHORT_WORDS;
-      if (cs >= FBG_J16_XYL_OR) {
+      at += j16_words(cs);
+      if (cs >= FBG_J16_XYS_OR) {
+        per_tile += 4 + W;  // the lane value, X and Y, then one v_bitop3 per word
+      } else if (cs >= FBG_J16_ORS) {
+        per_tile += W;  // one v_bitop3 per word into the register
+      } else if (cs >= FBG_J16_XYL_OR) {
         per_tile += 4 + W;  // the lane value, X and Y, then one v_bitop3 per word
       } else if (cs >= FBG_J16_XYF_OR) {
         per_tile += 4;  // the lane value, then X and Y
@@ -1358,7 +1423,8 @@ uint32_t leading_clauses(const Compiled &c) {
 }
 
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
-  static const char *ops[] = {"?", "CL", "LDL", "OPL", "ST", "OPR", "ACC", "LDR", "NOT", "XYF", "XYM", "XYL"};
+  static const char *ops[] = {"?",   "CL",  "LDL", "OPL", "ST",  "OPR", "ACC",
+                              "LDR", "NOT", "XYF", "XYM", "XYL", "XYS", "ORS"};
   const int W = 1 << log2w;
   const uint32_t *cb = words.data();
   const uint32_t *ins = cb + cb[0];
@@ -1425,8 +1491,13 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
     }
     uint32_t op = w[0] & 15u;
     uint32_t arg = w[0] >> FBG_ARG_SHIFT;
-    const char *name = op <= FBG_OP_XYL ? ops[op] : "?";
-    if (op == FBG_OP_CL || op == FBG_OP_LDL || op == FBG_OP_OPL || op == FBG_OP_XYF || op == FBG_OP_XYM ||
+    const char *name = op <= FBG_OP_ORS ? ops[op] : "?";
+    if (op == FBG_OP_XYS) {
+      snprintf(buf, sizeof buf,
+               "%4zu %-3s tt=%02x set=%s mconst=%08x lane=%08x%08x sel=%08x%08x neg=%08x%08x into r%u\n", pc, name,
+               (w[0] >> FBG_F_SHIFT) & 0xFFu, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], w[5], w[4], w[7],
+               w[6], arg);
+    } else if (op == FBG_OP_CL || op == FBG_OP_LDL || op == FBG_OP_OPL || op == FBG_OP_XYF || op == FBG_OP_XYM ||
         op == FBG_OP_XYL) {
       uint32_t pat = 0;
       for (int i = 0; i < W; i++)
@@ -1437,7 +1508,7 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
                "%4zu %-3s %sset=%s mconst=%08x lane=%08x%08x pat=%08x sel=%08x%08x neg=%08x%08x\n",
                pc, name, tt, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], pat, w[5],
                w[4], w[7], w[6]);
-    } else if (op == FBG_OP_OPR || op == FBG_OP_LDR) {
+    } else if (op == FBG_OP_OPR || op == FBG_OP_LDR || op == FBG_OP_ORS) {
       snprintf(buf, sizeof buf, "%4zu %-3s tt=%02x r%u\n", pc, name, (w[0] >> FBG_F_SHIFT) & 0xFFu, arg);
     } else {
       snprintf(buf, sizeof buf, "%4zu %-3s r%u%s%s\n", pc, name, arg, (w[0] & FBG_INV) ? " inv" : "",
@@ -1582,6 +1653,12 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
           Y = bitop3(tt, Y, set_lane_value(w, lane, U0), 0u);
           cur = (cur & X) | (~cur & Y);
           break;
+        case FBG_OP_XYS:  // cur keeps its value
+          X = bitop3(tt, X, set_lane_value(w, lane, U0), 0u);
+          Y = bitop3(tt, Y, set_lane_value(w, lane, U0), 0u);
+          R[arg] = (cur & X) | (~cur & Y);
+          break;
+        case FBG_OP_ORS: R[arg] = bitop3(tt, cur, R[arg], 0u); break;  // cur keeps its value
       }
       if (w[0] & FBG_INVOUT) cur = ~cur;
     }

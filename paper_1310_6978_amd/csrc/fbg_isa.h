@@ -148,6 +148,14 @@
  * one, an XYL always ends it).  In the plain form's terms (the disassembly
  * and the emulator) they are the opcodes XYF, XYM and XYL, which the plain
  * encoding never contains.
+ *
+ * Merged stores.  A store of cur into a VGPR register after which cur is dead
+ * (the next instruction loads cur without reading it, or the program ends)
+ * merges into the instruction before it when that one can write the register
+ * itself: the last set of a chain (XYS: the chain's result goes to R[r], r x
+ * 16 in bits 16..31 of w0) or an operation on that same register (ORS: R[r] =
+ * f(cur, R[r])).  cur keeps its old value; nothing reads it.  In the plain
+ * form's terms they are the opcodes XYS and ORS.
  */
 #ifndef FBG_ISA_H
 #define FBG_ISA_H
@@ -166,6 +174,10 @@
 #define FBG_OP_XYF 9u
 #define FBG_OP_XYM 10u
 #define FBG_OP_XYL 11u
+/* a store merged into the instruction before it (see Merged stores): only
+   as the decoded jump-table form */
+#define FBG_OP_XYS 12u
+#define FBG_OP_ORS 13u
 
 #define FBG_XORSET (1u << 4)
 #define FBG_HASPAT (1u << 5)
@@ -214,7 +226,10 @@
 #define FBG_J16_XYM_XOR 114u    /* further set of a chain, XOR-set */
 #define FBG_J16_XYL_OR 126u     /* last set of a chain, then cur = (cur & X) | (~cur & Y) */
 #define FBG_J16_XYL_XOR 138u
-#define FBG_J16_NCASES 150u
+#define FBG_J16_ORS 150u        /* + table index: R[r] = tt(cur, R[r]), cur left as it was (VGPR registers) */
+#define FBG_J16_XYS_OR 162u     /* last set of a chain, the result into R[r] instead of cur: + table index */
+#define FBG_J16_XYS_XOR 174u
+#define FBG_J16_NCASES 186u
 /* Truth tables of the cases, over (cur = 0xF0, T or R = 0xCC, P = 0xAA).
    Without word literals P is 0, so only the bits of 0x55 matter. */
 #define FBG_J16_REG_TABLES(X) X(0xC0) X(0x30) X(0xFC) X(0xF3) X(0x3C) X(0xC3) X(0x3F) X(0xCF) X(0x03) X(0x0C) X(0xCC) X(0x33)

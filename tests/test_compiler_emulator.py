@@ -54,7 +54,9 @@ def assert_clause_block(p, w):
     assert ncl <= p.info["n_clause_instr"]
     chunks = [int(l.split()[3].split("=")[1]) for l in lst.splitlines() if l.startswith("chunk ")]
     assert sum(chunks) == ncl and all(1 <= c <= 32 for c in chunks)
-    assert p.info["n_instr"] == p.info["n_clause_instr"] + len(instructions(lst))
+    # a merged store (XYS, ORS at 16 words per lane) is two instructions
+    ops = [op for _, op in instructions(lst)]
+    assert p.info["n_instr"] == p.info["n_clause_instr"] + len(ops) + sum(op in ("XYS", "ORS") for op in ops)
 
 
 @pytest.mark.parametrize("seed", range(60))
@@ -291,21 +293,41 @@ def test_chains_of_literal_sets(seed):
     text = "(%s ^ %s) | (%s & ~%s)" % tuple(parts)
     p = check(text, n, wpl=[16, 1, 32])
     ops = [op for _, op in instructions(p.disasm(16))]
-    # every chain opens with XYF, continues with XYM and closes with XYL
+    # every chain opens with XYF, continues with XYM and closes with XYL (or
+    # XYS, its result stored into a register)
     i = 0
     while i < len(ops):
         if ops[i] == "XYF":
             j = i + 1
             while ops[j] == "XYM":
                 j += 1
-            assert ops[j] == "XYL", ops
+            assert ops[j] in ("XYL", "XYS"), ops
             i = j + 1
         else:
-            assert ops[i] not in ("XYM", "XYL"), ops
+            assert ops[i] not in ("XYM", "XYL", "XYS"), ops
             i += 1
     assert "XYF" not in [op for _, op in instructions(p.disasm(8))]
-    # the plain form and the jump-table form hold the same instructions
-    assert len(ops) == len(instructions(p.disasm(8)))
+    # the plain form and the jump-table form hold the same instructions (a
+    # merged store counts twice)
+    assert len(ops) + sum(op in ("XYS", "ORS") for op in ops) == len(instructions(p.disasm(8)))
+
+
+def test_merged_stores():
+    """At 16 words per lane a store into a VGPR register after which cur is
+    dead merges into the instruction before it: the last set of a chain
+    (XYS) or an operation on the same register (ORS).  Where cur is still
+    read after the store (here by ACC), the store stays.  The emulator runs
+    the merged forms as the kernel does (cur left stale), so a merge where cur
+    is live would show as a wrong vector."""
+    # (a ^ b) & (c | d) with chained literal sets on both sides
+    text = "t1 = ((x0 ^ x6) & x7 | x16) ^ x2\nt2 = ((x1 | x9) ^ x17) & x4\nt1 & t2 | (t1 ^ x3) & ~t2"
+    p = check(text, 18, wpl=[16, 8])
+    ops = [op for _, op in instructions(p.disasm(16))]
+    assert "XYS" in ops or "ORS" in ops, ops
+    rng = random.Random(5300)
+    for _ in range(12):
+        t = many_registers(rng, 17, rng.choice([3, 5, 8]))
+        check(t, 17, wpl=[16])
 
 
 def test_run_of_four_literal_sets_is_one_chain():
