@@ -1090,8 +1090,9 @@ uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, s
   // A store into a VGPR register after which cur is dead (the next
   // instruction loads cur without reading it, or the program ends) merges
   // into the instruction before it when that one can write the register
-  // itself: the last set of a chain (XYS) or an operation with that same
-  // register (ORS, both operands then addressed with the register's index).
+  // itself: the last set of a chain (XYS), a literal set without word
+  // literals (LIS) or an operation with that same register (ORS, both
+  // operands then addressed with the register's index).
   auto st_v = [&](size_t k) {
     const uint32_t cs = case_of(k);
     return cs == FBG_J16_ST_V || cs == FBG_J16_ST_V + 1;
@@ -1109,6 +1110,14 @@ uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, s
         if (cs >= FBG_J16_XYL_OR && cs < FBG_J16_XYL_OR + 24) {
           std::array<uint32_t, FBG_INS_WORDS> w = out[k];
           w[0] = ((out[k + 1][1] & 0xFFFFu) << 16) | (FBG_J16_XYS_OR + (cs - FBG_J16_XYL_OR)) * FBG_J16_SLOT;
+          merged.push_back(w);
+          mpop.push_back(FBG_OP_ST);
+          k++;
+          continue;
+        }
+        if (cs >= FBG_J16_LIT_OR && cs < FBG_J16_LIT_OR_P) {
+          std::array<uint32_t, FBG_INS_WORDS> w = out[k];
+          w[0] = ((out[k + 1][1] & 0xFFFFu) << 16) | (FBG_J16_LIS_OR + (cs - FBG_J16_LIT_OR)) * FBG_J16_SLOT;
           merged.push_back(w);
           mpop.push_back(FBG_OP_ST);
           k++;
@@ -1151,10 +1160,10 @@ static uint32_t from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
   for (int j = 0; j < FBG_INS_WORDS; j++) g[j] = 0;
   const uint32_t cs = (w[0] & 0xFFFFu) / FBG_J16_SLOT;
   if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) return 0;
-  if (cs >= FBG_J16_XYS_OR) {  // a chain's last set into R[r]
-    const uint32_t k = cs - FBG_J16_XYS_OR;
+  if (cs >= FBG_J16_XYS_OR) {  // a chain's last set, or a literal set, into R[r]
+    const uint32_t k = (cs - FBG_J16_XYS_OR) % 24, op = cs >= FBG_J16_LIS_OR ? FBG_OP_LIS : FBG_OP_XYS;
     const uint32_t r = (w[0] >> 16) / 16u;
-    g[0] = FBG_OP_XYS | (k >= 12 ? FBG_XORSET : 0u) | (kJ16Np[k % 12] << FBG_F_SHIFT) | (r << FBG_ARG_SHIFT);
+    g[0] = op | (k >= 12 ? FBG_XORSET : 0u) | (kJ16Np[k % 12] << FBG_F_SHIFT) | (r << FBG_ARG_SHIFT);
     for (int j = 1; j < FBG_INS_WORDS; j++) g[j] = w[j];
     return FBG_INS_WORDS;
   }
@@ -1362,7 +1371,9 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
       const uint32_t cs = (ins[at] & 0xFFFFu) / FBG_J16_SLOT;
       if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) break;
       at += j16_words(cs);
-      if (cs >= FBG_J16_XYS_OR) {
+      if (cs >= FBG_J16_LIS_OR) {
+        per_tile += 2 + W;  // the lane value, one v_bitop3 per word into the register
+      } else if (cs >= FBG_J16_XYS_OR) {
         per_tile += 4 + W;  // the lane value, X and Y, then one v_bitop3 per word
       } else if (cs >= FBG_J16_ORS) {
         per_tile += W;  // one v_bitop3 per word into the register
@@ -1423,8 +1434,8 @@ uint32_t leading_clauses(const Compiled &c) {
 }
 
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
-  static const char *ops[] = {"?",   "CL",  "LDL", "OPL", "ST",  "OPR", "ACC",
-                              "LDR", "NOT", "XYF", "XYM", "XYL", "XYS", "ORS"};
+  static const char *ops[] = {"?",   "CL",  "LDL", "OPL", "ST",  "OPR", "ACC", "LDR",
+                              "NOT", "XYF", "XYM", "XYL", "XYS", "ORS", "LIS"};
   const int W = 1 << log2w;
   const uint32_t *cb = words.data();
   const uint32_t *ins = cb + cb[0];
@@ -1491,8 +1502,8 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
     }
     uint32_t op = w[0] & 15u;
     uint32_t arg = w[0] >> FBG_ARG_SHIFT;
-    const char *name = op <= FBG_OP_ORS ? ops[op] : "?";
-    if (op == FBG_OP_XYS) {
+    const char *name = op <= FBG_OP_LIS ? ops[op] : "?";
+    if (op == FBG_OP_XYS || op == FBG_OP_LIS) {
       snprintf(buf, sizeof buf,
                "%4zu %-3s tt=%02x set=%s mconst=%08x lane=%08x%08x sel=%08x%08x neg=%08x%08x into r%u\n", pc, name,
                (w[0] >> FBG_F_SHIFT) & 0xFFu, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], w[5], w[4], w[7],
@@ -1659,6 +1670,7 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
           R[arg] = (cur & X) | (~cur & Y);
           break;
         case FBG_OP_ORS: R[arg] = bitop3(tt, cur, R[arg], 0u); break;  // cur keeps its value
+        case FBG_OP_LIS: R[arg] = bitop3(tt, cur, set_lane_value(w, lane, U0), 0u); break;  // cur too
       }
       if (w[0] & FBG_INVOUT) cur = ~cur;
     }

@@ -55,7 +55,7 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 #define FBG_J16_DISPATCH                \
   "s_waitcnt lgkmcnt(0)\n"              \
   "s_and_b32 s78, s48, 0xff00\n"        \
-  "s_min_u32 s78, s78, 0xba00\n"        \
+  "s_min_u32 s78, s78, 0xd200\n"        \
   "s_add_u32 s78, s76, s78\n"           \
   "s_addc_u32 s79, s77, 0\n"            \
   "s_setpc_b64 s[78:79]\n"
@@ -167,6 +167,14 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "s_nop 1\n" FBG_J16_W16(FBG_J16_XYSTORE) "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
 #define FBG_J16_C_XYS_OR(TT) FBG_J16_T_OR FBG_J16_XYS_TAIL(#TT)
 #define FBG_J16_C_XYS_XOR(TT) FBG_J16_T_XOR FBG_J16_XYS_TAIL(#TT)
+// LIS: a literal set's operation, its result into R[r] (index mode on the
+// destination)
+#define FBG_J16_LIS_W(i, TT) "v_bitop3_b32 v[32+" #i "], v[16+" #i "], v14, 0 bitop3:" TT "\n"
+#define FBG_J16_LIS_TAIL(TT)                                                                          \
+  "s_lshr_b32 s72, s48, 16\n" "s_set_gpr_idx_on s72, gpr_idx(DST)\n" FBG_J16_NEXT_L "s_nop 1\n" \
+  FBG_J16_EACH(FBG_J16_LIS_W, TT) "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
+#define FBG_J16_C_LIS_OR(TT) FBG_J16_T_OR FBG_J16_LIS_TAIL(#TT)
+#define FBG_J16_C_LIS_XOR(TT) FBG_J16_T_XOR FBG_J16_LIS_TAIL(#TT)
 
 #define FBG_J16_C_ST_V(INVOUT)                                                                  \
   "s_set_gpr_idx_on s49, gpr_idx(DST)\n" FBG_J16_NEXT_S "s_nop 1\n" FBG_J16_W16(FBG_J16_STV)     \
@@ -254,15 +262,18 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASES_REG(FBG_J16_C_ORS, 150)                                                                      \
   FBG_J16_CASES_NP(FBG_J16_C_XYS_OR, 162)                                                                    \
   FBG_J16_CASES_NP(FBG_J16_C_XYS_XOR, 174)                                                                   \
-  FBG_J16_CASE(186)                                                                                          \
+  FBG_J16_CASES_NP(FBG_J16_C_LIS_OR, 186)                                                                    \
+  FBG_J16_CASES_NP(FBG_J16_C_LIS_XOR, 198)                                                                   \
+  FBG_J16_CASE(210)                                                                                          \
   "Ld%=:\n"                                                                                                  \
   "s_mov_b32 m0, s83\n"
 // clang-format on
 
-static_assert(FBG_J16_NCASES == 186 && FBG_J16_SLOT == 256 && FBG_J16_XYF_OR == 78 && FBG_J16_XYF_XOR == 90 &&
+static_assert(FBG_J16_NCASES == 210 && FBG_J16_SLOT == 256 && FBG_J16_XYF_OR == 78 && FBG_J16_XYF_XOR == 90 &&
                   FBG_J16_XYM_OR == 102 && FBG_J16_XYM_XOR == 114 && FBG_J16_XYL_OR == 126 &&
-                  FBG_J16_XYL_XOR == 138 && FBG_J16_ORS == 150 && FBG_J16_XYS_OR == 162 && FBG_J16_XYS_XOR == 174,
-              "the case list of FBG_J16_PROGRAM and the clamp 0xba00 = 186 x 256 of FBG_J16_DISPATCH");
+                  FBG_J16_XYL_XOR == 138 && FBG_J16_ORS == 150 && FBG_J16_XYS_OR == 162 && FBG_J16_XYS_XOR == 174 &&
+                  FBG_J16_LIS_OR == 186 && FBG_J16_LIS_XOR == 198,
+              "the case list of FBG_J16_PROGRAM and the clamp 0xd200 = 210 x 256 of FBG_J16_DISPATCH");
 
 // Run the general part of a program (jump-table form at `code`, its pattern
 // table at `table`) on the 16 words of this lane of tile group U0.  acc comes

@@ -153,9 +153,10 @@
  * (the next instruction loads cur without reading it, or the program ends)
  * merges into the instruction before it when that one can write the register
  * itself: the last set of a chain (XYS: the chain's result goes to R[r], r x
- * 16 in bits 16..31 of w0) or an operation on that same register (ORS: R[r] =
+ * 16 in bits 16..31 of w0), a literal set without word literals (LIS, r x 16
+ * in the same place) or an operation on that same register (ORS: R[r] =
  * f(cur, R[r])).  cur keeps its old value; nothing reads it.  In the plain
- * form's terms they are the opcodes XYS and ORS.
+ * form's terms they are the opcodes XYS, LIS and ORS.
  */
 #ifndef FBG_ISA_H
 #define FBG_ISA_H
@@ -178,6 +179,7 @@
    as the decoded jump-table form */
 #define FBG_OP_XYS 12u
 #define FBG_OP_ORS 13u
+#define FBG_OP_LIS 14u
 
 #define FBG_XORSET (1u << 4)
 #define FBG_HASPAT (1u << 5)
@@ -229,7 +231,9 @@
 #define FBG_J16_ORS 150u        /* + table index: R[r] = tt(cur, R[r]), cur left as it was (VGPR registers) */
 #define FBG_J16_XYS_OR 162u     /* last set of a chain, the result into R[r] instead of cur: + table index */
 #define FBG_J16_XYS_XOR 174u
-#define FBG_J16_NCASES 186u
+#define FBG_J16_LIS_OR 186u     /* literal set without word literals, the result into R[r]: + table index */
+#define FBG_J16_LIS_XOR 198u
+#define FBG_J16_NCASES 210u
 /* Truth tables of the cases, over (cur = 0xF0, T or R = 0xCC, P = 0xAA).
    Without word literals P is 0, so only the bits of 0x55 matter. */
 #define FBG_J16_REG_TABLES(X) X(0xC0) X(0x30) X(0xFC) X(0xF3) X(0x3C) X(0xC3) X(0x3F) X(0xCF) X(0x03) X(0x0C) X(0xCC) X(0x33)

@@ -33,6 +33,9 @@ def check(text, n, wpl=WPL):
     return p
 
 
+MERGED = ("XYS", "LIS", "ORS")   # jump-table instructions that hold a store as well
+
+
 def instructions(listing):
     """(pc, opcode) of the instruction lines of a listing."""
     out = []
@@ -54,9 +57,9 @@ def assert_clause_block(p, w):
     assert ncl <= p.info["n_clause_instr"]
     chunks = [int(l.split()[3].split("=")[1]) for l in lst.splitlines() if l.startswith("chunk ")]
     assert sum(chunks) == ncl and all(1 <= c <= 32 for c in chunks)
-    # a merged store (XYS, ORS at 16 words per lane) is two instructions
+    # a merged store (XYS, LIS, ORS at 16 words per lane) is two instructions
     ops = [op for _, op in instructions(lst)]
-    assert p.info["n_instr"] == p.info["n_clause_instr"] + len(ops) + sum(op in ("XYS", "ORS") for op in ops)
+    assert p.info["n_instr"] == p.info["n_clause_instr"] + len(ops) + sum(op in MERGED for op in ops)
 
 
 @pytest.mark.parametrize("seed", range(60))
@@ -309,13 +312,13 @@ def test_chains_of_literal_sets(seed):
     assert "XYF" not in [op for _, op in instructions(p.disasm(8))]
     # the plain form and the jump-table form hold the same instructions (a
     # merged store counts twice)
-    assert len(ops) + sum(op in ("XYS", "ORS") for op in ops) == len(instructions(p.disasm(8)))
+    assert len(ops) + sum(op in MERGED for op in ops) == len(instructions(p.disasm(8)))
 
 
 def test_merged_stores():
     """At 16 words per lane a store into a VGPR register after which cur is
     dead merges into the instruction before it: the last set of a chain
-    (XYS) or an operation on the same register (ORS).  Where cur is still
+    (XYS), a literal set (LIS) or an operation on the same register (ORS).  Where cur is still
     read after the store (here by ACC), the store stays.  The emulator runs
     the merged forms as the kernel does (cur left stale), so a merge where cur
     is live would show as a wrong vector."""
@@ -323,7 +326,7 @@ def test_merged_stores():
     text = "t1 = ((x0 ^ x6) & x7 | x16) ^ x2\nt2 = ((x1 | x9) ^ x17) & x4\nt1 & t2 | (t1 ^ x3) & ~t2"
     p = check(text, 18, wpl=[16, 8])
     ops = [op for _, op in instructions(p.disasm(16))]
-    assert "XYS" in ops or "ORS" in ops, ops
+    assert any(op in MERGED for op in ops), ops
     rng = random.Random(5300)
     for _ in range(12):
         t = many_registers(rng, 17, rng.choice([3, 5, 8]))
