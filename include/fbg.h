@@ -105,7 +105,8 @@ typedef struct {
   int32_t flags;           /* FBG_TUNE_* */
   int32_t direct_run;      /* fbg_batch_eval_dnf of clause-only programs (one
                               wave per run of tiles on fresh blocks): tiles
-                              per run, 1..64; 0: the library's choice (4) */
+                              per run, 1..64; 0: the library's choice (1 when
+                              a program takes the XCD-local layout, else 4) */
 } fbg_tune;
 
 /* Uniform-cofactor evaluation: the index bits above the lane and word bits
@@ -199,7 +200,11 @@ fbg_status fbg_program_set_tuning(fbg_program *p, const fbg_tune *tune);
  * d_out[0 .. max(1, 2^(n-6))), layout above.
  *   d_out      device pointer, caller-owned, 8-byte aligned.
  *   out_words  capacity of d_out in words; must be >= max(1, 2^(n-6)).
- * n <= FBG_MAX_DNF_VARS.
+ * n <= FBG_MAX_DNF_VARS.  A program made only of clauses with n >= 21, at 32
+ * words per lane without the cofactor, is evaluated in a second encoding
+ * whose tiles are pairs of 4 KiB pieces of d, each block of waves writing the
+ * pieces of one residue class modulo 8 (one per XCD); the result is the same
+ * vector, and it is written fastest when d_out is 32 KiB aligned.
  */
 fbg_status fbg_eval_dnf(const fbg_program *p, uint64_t *d_out, uint64_t out_words, void *stream);
 
@@ -268,10 +273,12 @@ fbg_status fbg_batch_count_graph(fbg_batch *b, uint64_t *d_counts, void *stream)
  *   (layout as fbg_eval_dnf) and d_counts[i] = its number of models
  *   (overwritten), computing each word once: one launch per plan.  Once the
  *   tile counts exist (fbg_batch_set_enum_outputs), a plan of clause-only
- *   programs without the cofactor runs four consecutive tiles per wave on a
- *   grid of fresh blocks and its counts are summed from the tile counts by a
- *   second small launch; other plans run persistent waves over work queues.
- *   FBG_E_INVAL if no outputs were set.  Allocates nothing.
+ *   programs without the cofactor runs on a grid of fresh blocks, one run of
+ *   tiles per wave (programs with n >= 21 in the XCD-local layout described
+ *   at fbg_eval_dnf, one tile per wave), and its counts are summed from the
+ *   tile counts by a second small launch; other plans run persistent waves
+ *   over work queues.  FBG_E_INVAL if no outputs were set.  Allocates
+ *   nothing.
  */
 fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, const uint64_t *out_words);
 fbg_status fbg_batch_eval_dnf(fbg_batch *b, uint64_t *d_counts, void *stream);
@@ -286,8 +293,9 @@ fbg_status fbg_batch_eval_dnf(fbg_batch *b, uint64_t *d_counts, void *stream);
  *             receives at most capacity[i] uint64 indices; NULL allowed
  *             when capacity[i] = 0.
  *   capacity  host array of np capacities.
- * Synchronous (allocates the tile-count and offset buffers once and uploads
- * a table); must not run while a launch of this batch is pending.
+ * Synchronous (allocates the tile-count, offset and piece-count buffers once
+ * and uploads a table); must not run while a launch of this batch is
+ * pending.
  * fbg_batch_enumerate -- after fbg_batch_eval_dnf on the same stream: the
  *   first min(count_i, capacity_i) models of every program i, ascending,
  *   into d_idx[i] (count_i is d_counts[i] of that call).  One scan over the
