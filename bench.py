@@ -364,6 +364,23 @@ def c3_block(args, torch, fbg):
     gen_ms = timed(lambda: gb.count(out=gout, stream=stream), reps)
     gen_rate = gen_l2in / (gen_ms / 1e3)
     gb.free()
+    # the small and the large formulas apart: each set as a batch of its own
+    # and as plain launches
+    by_n = {}
+    for name, sel in (("n<=20", lambda n: n <= 20), ("n>=28", lambda n: n >= 28)):
+        part = [p for p in progs if sel(p.n)]
+        pb = fbg.Batch(part, words_per_lane=wpl)
+        pout = torch.empty(len(part), dtype=torch.int64, device="cuda")
+        p_ms = timed(lambda: pb.count(out=pout, stream=stream), reps)
+        pb.free()
+
+        def plain_part():
+            for i, p in enumerate(part):
+                fbg.count(p, out=pout[i:i + 1], stream=stream)
+        pp_ms = timed(plain_part, 1)
+        pv = float(sum(1 << p.n for p in part))
+        by_n[name] = {"formulas": len(part), "batched_ms": p_ms, "plain_ms": pp_ms,
+                      "batched_valuations_per_s": pv / (p_ms / 1e3), "plain_valuations_per_s": pv / (pp_ms / 1e3)}
     b.free()
     l2in = sum(p.info["l2in"] * 2.0 ** p.n for p in progs)
     return {
@@ -376,6 +393,7 @@ def c3_block(args, torch, fbg):
         "general_plans": {"programs": len(gen), "sum_l2in_2n": gen_l2in, "ms": gen_ms,
                           "algorithmic_rate_T": gen_rate / 1e12,
                           "frac_of_valu_bitwise_peak": gen_rate / VALU_BITWISE_PEAK},
+        "by_n": by_n,
         "counts_equal_oracle": exact, "batched_equals_plain": same,
     }
 
@@ -404,8 +422,9 @@ def bench_c4(args, torch, fbg):
     equivalence, 5x5 permutation and k=8 triangle-free workloads), continuous
     batching.  First the saturation rate is measured with every request
     arriving at once; then one timed run per load level, arrivals at that
-    fraction of the saturation rate."""
-    import oracle
+    fraction of the saturation rate.  Results are checked against the
+    theories' closed forms and against the stored oracle counts of the
+    stream's 3-CNF requests with n <= 20 (tests/golden/c4_requests.json)."""
     from paper_1310_6978_amd.serve import ServeLoop
     from workloads.serving import request_stream
 
@@ -419,6 +438,8 @@ def bench_c4(args, torch, fbg):
     sat = loop.run(request_stream(args.sat_requests, 0.0, seed=1), realtime=False, log=log)
     rate = sat["requests_per_s"]
     closed = {"equivalence_k9": 21147, "permutations_k5": 120, "triangle_free_k8": 4682270}
+    with open(os.path.join(ROOT, "tests", "golden", "c4_requests.json")) as f:
+        stored = json.load(f)["counts"]
     runs = []
     ok = True
     checked = 0
@@ -434,8 +455,9 @@ def bench_c4(args, torch, fbg):
             if r["kind"] in closed:
                 ok = ok and c == closed[r["kind"]]
                 checked += 1
-            elif r["n"] <= 20 and n_ok < 400:
-                ok = ok and c == oracle.count(r["text"], r["n"])
+            elif str(r["id"]) in stored and n_ok < 400:
+                rec = stored[str(r["id"])]
+                ok = ok and rec["n"] == r["n"] and c == rec["count"]
                 checked += 1
                 n_ok += 1
         runs.append({"load": load, "qps": qps, "latency_p50_ms": res["latency_p50_ms"],
@@ -511,7 +533,7 @@ def bench_theories(args, torch, fbg):
              ("equivalence relations k=6", workloads.equivalence_relations(6), 203)]
     stream = torch.cuda.current_stream()
     out = torch.empty(1, dtype=torch.int64, device="cuda")
-    rows, ok, vals, best_total = [], True, 0.0, 0.0
+    rows, enum_rows, ok, vals, best_total = [], [], True, 0.0, 0.0
     for name, (text, n), want in cases:
         p = fbg.Program(text, n)
         best = None
@@ -535,11 +557,70 @@ def bench_theories(args, torch, fbg):
                     best = ms
         vals += 2.0 ** n
         best_total += best
+        # every model listed (two passes: tile counts and scan, then the
+        # compaction of the tiles that hold models), at the library's tiling
+        cap = want
+        idx, tot = fbg.enumerate_models(p, cap, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fbg.enumerate_models(p, cap, out=idx, total=tot, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ok = ok and int(tot.cpu().numpy().view("uint64")[0]) == want
+        enum_rows.append({"theory": name, "models": want, "ms": a.elapsed_time(b) / args.steps,
+                          "list_bytes": 8 * want})
     return {"metric": "valuations/s of one full-evaluation count per theory (best tiling)",
             "value": vals / (best_total / 1e3), "unit": "valuations/s", "ms_per_step": best_total, "dtype": "u32",
             "config": {"workload": "propositional theories: equivalence k=9 and k=6, triangle-free k=8, "
                                    "5x5 permutations; one count each"},
-            "counts_match_closed_forms": ok, "runs": rows}
+            "counts_match_closed_forms": ok, "runs": rows, "enumerate": enum_rows}
+
+
+def bench_c0(args, torch, fbg):
+    """Equivalence relations on 6 elements (n = 15, 60 clauses): a launch-
+    bound size, so what is reported is the latency of one call from the
+    host, synchronised, for the count, the DNF vector and the enumeration,
+    each against the stored oracle values (tests/golden/c0_equivalence_k6.json)
+    and the closed form B_6 = 203."""
+    import numpy as np
+    import workloads
+    text, n = workloads.equivalence_relations(6)
+    p = fbg.Program(text, n)
+    stream = torch.cuda.current_stream()
+    out = torch.empty(1, dtype=torch.int64, device="cuda")
+    dnf = torch.empty(fbg.dnf_words(n), dtype=torch.int64, device="cuda")
+    idx = torch.empty(256, dtype=torch.int64, device="cuda")
+    tot = torch.empty(1, dtype=torch.int64, device="cuda")
+    calls = {"count": lambda: fbg.count(p, out=out, stream=stream),
+             "dnf": lambda: fbg.eval_dnf(p, out=dnf, stream=stream),
+             "enumerate": lambda: fbg.enumerate_models(p, 256, out=idx, total=tot, stream=stream)}
+    reps = max(args.steps, 1) * 40
+    lat = {}
+    for name, fn in calls.items():
+        for _ in range(max(args.warmup, 1) * 10):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+            torch.cuda.synchronize()
+        lat[name] = (time.perf_counter() - t0) * 1e6 / reps
+    with open(os.path.join(ROOT, "tests", "golden", "c0_equivalence_k6.json")) as f:
+        g = json.load(f)
+    want_dnf = np.array([int(x, 16) for x in g["dnf_words_hex"]], dtype=np.uint64)
+    models = np.array(g["models"], dtype=np.uint64)
+    ok = (g["count"] == 203 and int(out.cpu().numpy().view("uint64")[0]) == 203
+          and np.array_equal(dnf.cpu().numpy().view(np.uint64), want_dnf)
+          and int(tot.cpu().numpy().view("uint64")[0]) == 203
+          and np.array_equal(idx.cpu().numpy().view(np.uint64)[:203], models))
+    return {"metric": "latency of one call (us, host to result, synchronised)", "value": lat["count"],
+            "unit": "us", "ms_per_step": lat["count"] / 1e3, "dtype": "u32",
+            "config": {"workload": "equivalence relations k=6: n=15, 60 clauses; count, DNF (512 words), "
+                                   "enumeration (203 models)", "n": n},
+            "higher_is_better": False, "latency_us": lat, "bit_exact_vs_oracle": ok}
 
 
 def bench_unlabeled(args, torch, fbg):
@@ -655,7 +736,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1",
-                    choices=["c1", "c3", "c4", "posets", "theories", "unlabeled", "copy", "valu"])
+                    choices=["c0", "c1", "c3", "c4", "posets", "theories", "unlabeled", "copy", "valu"])
     ap.add_argument("--posets-n", type=int, default=11, help="posets: bounded posets on n elements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="c1: leave out the 4096-formula batch block")
@@ -679,6 +760,8 @@ def main():
         res = bench_c1(args, torch, fbg)
         if not args.no_c3:
             res["c3"] = c3_block(args, torch, fbg)
+    elif args.workload == "c0":
+        res = bench_c0(args, torch, fbg)
     elif args.workload == "c3":
         res = bench_c3(args, torch, fbg)
     elif args.workload == "c4":
@@ -695,7 +778,8 @@ def main():
         res = bench_copy(args, torch)
     out = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"),
+           "higher_is_better": res.pop("higher_is_better", True), "scaling": "weak", "vs_baseline": None,
+           "dtype": res.pop("dtype"),
            "data": "synthetic (seeded SplitMix64 formulas)", "config": res.pop("config")}
     out.update(res)
     print(json.dumps(out))

@@ -13,6 +13,9 @@ Files written (JSON):
                            k=8: counts, model lists (or a SHA-256 of the
                            little-endian uint64 model array when large)
   c3_dag_batch.json        per formula of the 4096-DAG batch: n and count
+  c4_requests.json         the serving stream (seed 0, any arrival rate > 0):
+                           the count of every random 3-CNF request with
+                           n <= 20 among the first 20,000
 """
 
 import hashlib
@@ -34,6 +37,7 @@ from workloads.formulas import random_dag_batch  # noqa: E402
 C1_SEEDS = list(range(16))
 C3_SEED = 0
 C3_COUNT = 4096
+C4_REQUESTS = 20000
 
 
 def models_sha256(arr):
@@ -106,6 +110,19 @@ def c3():
         if i % 256 == 255:
             print("c3", i + 1, "%.1fs" % (time.time() - t0), flush=True)
     write("c3_dag_batch.json", out)
+
+
+def c4():
+    from workloads.serving import request_stream
+    reqs = request_stream(C4_REQUESTS, 1.0, seed=0)  # the texts do not depend on the rate
+    out = {"workload": "serving stream, seed 0, first %d requests: 3-CNF requests with n <= 20" % C4_REQUESTS,
+           "requests": C4_REQUESTS, "counts": {}}
+    t0 = time.time()
+    for r in reqs:
+        if r["kind"] == "3cnf" and r["n"] <= 20:
+            out["counts"][str(r["id"])] = {"n": r["n"], "count": int(oracle.count(r["text"], r["n"]))}
+    print("c4", len(out["counts"]), "requests %.1fs" % (time.time() - t0), flush=True)
+    write("c4_requests.json", out)
 
 
 if __name__ == "__main__":

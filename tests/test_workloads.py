@@ -44,3 +44,24 @@ def test_dag_batch_ranges():
         assert 10 <= n <= 30
         size = len(text.strip().split("\n")) - 1
         assert 50 <= size <= 2000
+
+
+def test_serving_golden_matches_the_stream():
+    """tests/golden/c4_requests.json (written by make_golden.py from the
+    oracle) still describes the stream: a sample of its entries regenerated
+    here has the same n and the oracle's count."""
+    import json
+    import os
+    import random
+    import oracle
+    from workloads.serving import request_stream
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c4_requests.json")) as f:
+        g = json.load(f)
+    reqs = request_stream(g["requests"], 1.0, seed=0)
+    ids = sorted(g["counts"], key=int)
+    assert len(ids) > 6000
+    assert {str(r["id"]) for r in reqs if r["kind"] == "3cnf" and r["n"] <= 20} == set(ids)
+    for i in random.Random(4).sample(ids, 12):
+        r = reqs[int(i)]
+        assert r["n"] == g["counts"][i]["n"]
+        assert oracle.count(r["text"], r["n"]) == g["counts"][i]["count"]
