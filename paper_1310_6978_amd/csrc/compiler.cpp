@@ -998,6 +998,8 @@ const uint32_t kJ16Reg[] = {FBG_J16_REG_TABLES(FBG_LIST)};
 const uint32_t kJ16Np[] = {FBG_J16_NP_TABLES(FBG_LIST)};
 const uint32_t kJ16Or[] = {FBG_J16_OR_TABLES(FBG_LIST)};
 const uint32_t kJ16Xor[] = {FBG_J16_XOR_TABLES(FBG_LIST)};
+const uint32_t kJ16Ora[] = {FBG_J16_ORA_TABLES(FBG_LIST)};
+const uint32_t kJ16Lia[] = {FBG_J16_LIA_TABLES(FBG_LIST)};
 #undef FBG_LIST
 
 template <size_t N>
@@ -1010,7 +1012,9 @@ int table_index(const uint32_t (&list)[N], uint32_t tt) {
 // Words of a jump-table instruction of case cs: literal sets (chains
 // included) take 8, register, ACC and NOT instructions 2.
 uint32_t j16_words(uint32_t cs) {
-  return (cs >= FBG_J16_LIT_OR && cs < FBG_J16_ORS) || cs >= FBG_J16_XYS_OR ? FBG_INS_WORDS : FBG_J16_SHORT_WORDS;
+  const bool lit = (cs >= FBG_J16_LIT_OR && cs < FBG_J16_ORS) || (cs >= FBG_J16_XYS_OR && cs < FBG_J16_ORA) ||
+                   cs >= FBG_J16_LIA_OR;
+  return lit ? FBG_INS_WORDS : FBG_J16_SHORT_WORDS;
 }
 
 // Rewrite the nins instructions at words[at..] into the jump-table form
@@ -1138,6 +1142,47 @@ uint32_t to_jump_table(std::vector<uint32_t> &words, size_t at, uint32_t nins, s
     out.swap(merged);
     pop.swap(mpop);
   }
+  // An ACC after which cur is dead merges into the operation before it: an
+  // operation on a VGPR register (ORA) or a literal set without word literals
+  // (LIA) then ANDs its result into acc directly (ACC's inversion folded into
+  // the operation's table).
+  {
+    std::vector<std::array<uint32_t, FBG_INS_WORDS>> merged;
+    std::vector<uint32_t> mpop;
+    merged.reserve(out.size());
+    for (size_t k = 0; k < out.size(); k++) {
+      const uint32_t cs = case_of(k);
+      if (k + 1 < out.size() && case_of(k + 1) >= FBG_J16_ACC && case_of(k + 1) < FBG_J16_ACC + 4 &&
+          dead_after(k + 1)) {
+        const bool inv = ((case_of(k + 1) - FBG_J16_ACC) & 1u) != 0;  // acc &= ~cur
+        if (cs >= FBG_J16_REG_V && cs < FBG_J16_REG_L) {
+          const uint32_t t = kJ16Reg[cs - FBG_J16_REG_V];
+          const int idx = table_index(kJ16Reg, inv ? ~t & 0xFFu : t);
+          std::array<uint32_t, FBG_INS_WORDS> w = out[k];
+          w[0] = (FBG_J16_ORA + (uint32_t)idx) * FBG_J16_SLOT;
+          merged.push_back(w);
+          mpop.push_back(FBG_OP_ACC);
+          k++;
+          continue;
+        }
+        if (cs >= FBG_J16_LIT_OR && cs < FBG_J16_LIT_OR_P) {
+          const bool x = cs >= FBG_J16_LIT_XOR;
+          const uint32_t t = kJ16Np[cs - (x ? FBG_J16_LIT_XOR : FBG_J16_LIT_OR)];
+          const int idx = table_index(kJ16Np, inv ? ~t & 0x55u : t);
+          std::array<uint32_t, FBG_INS_WORDS> w = out[k];
+          w[0] = ((x ? FBG_J16_LIA_XOR : FBG_J16_LIA_OR) + (uint32_t)idx) * FBG_J16_SLOT;
+          merged.push_back(w);
+          mpop.push_back(FBG_OP_ACC);
+          k++;
+          continue;
+        }
+      }
+      merged.push_back(out[k]);
+      mpop.push_back(pop[k]);
+    }
+    out.swap(merged);
+    pop.swap(mpop);
+  }
   // lay out: literal sets (and chain members) in full, the others short
   std::vector<uint32_t> flat;
   flat.reserve(out.size() * FBG_INS_WORDS + FBG_INS_WORDS);
@@ -1160,6 +1205,16 @@ static uint32_t from_jump_table(const uint32_t *w, uint32_t g[FBG_INS_WORDS]) {
   for (int j = 0; j < FBG_INS_WORDS; j++) g[j] = 0;
   const uint32_t cs = (w[0] & 0xFFFFu) / FBG_J16_SLOT;
   if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) return 0;
+  if (cs >= FBG_J16_ORA) {  // acc = tt(acc, cur, R[r] or T)
+    if (cs < FBG_J16_LIA_OR) {
+      g[0] = FBG_OP_ACM | FBG_HASPAT | (kJ16Ora[cs - FBG_J16_ORA] << FBG_F_SHIFT) | ((w[1] / 16u) << FBG_ARG_SHIFT);
+      return FBG_J16_SHORT_WORDS;
+    }
+    const uint32_t k = cs - FBG_J16_LIA_OR;
+    g[0] = FBG_OP_ACM | (k >= 12 ? FBG_XORSET : 0u) | (kJ16Lia[k % 12] << FBG_F_SHIFT);
+    for (int j = 1; j < FBG_INS_WORDS; j++) g[j] = w[j];
+    return FBG_INS_WORDS;
+  }
   if (cs >= FBG_J16_XYS_OR) {  // a chain's last set, or a literal set, into R[r]
     const uint32_t k = (cs - FBG_J16_XYS_OR) % 24, op = cs >= FBG_J16_LIS_OR ? FBG_OP_LIS : FBG_OP_XYS;
     const uint32_t r = (w[0] >> 16) / 16u;
@@ -1371,7 +1426,11 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
       const uint32_t cs = (ins[at] & 0xFFFFu) / FBG_J16_SLOT;
       if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) break;
       at += j16_words(cs);
-      if (cs >= FBG_J16_LIS_OR) {
+      if (cs >= FBG_J16_LIA_OR) {
+        per_tile += 2 + W;  // the lane value, one v_bitop3 per word into acc
+      } else if (cs >= FBG_J16_ORA) {
+        per_tile += W;  // one v_bitop3 per word into acc
+      } else if (cs >= FBG_J16_LIS_OR) {
         per_tile += 2 + W;  // the lane value, one v_bitop3 per word into the register
       } else if (cs >= FBG_J16_XYS_OR) {
         per_tile += 4 + W;  // the lane value, X and Y, then one v_bitop3 per word
@@ -1435,7 +1494,7 @@ uint32_t leading_clauses(const Compiled &c) {
 
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w) {
   static const char *ops[] = {"?",   "CL",  "LDL", "OPL", "ST",  "OPR", "ACC", "LDR",
-                              "NOT", "XYF", "XYM", "XYL", "XYS", "ORS", "LIS"};
+                              "NOT", "XYF", "XYM", "XYL", "XYS", "ORS", "LIS", "ACM"};
   const int W = 1 << log2w;
   const uint32_t *cb = words.data();
   const uint32_t *ins = cb + cb[0];
@@ -1502,8 +1561,14 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
     }
     uint32_t op = w[0] & 15u;
     uint32_t arg = w[0] >> FBG_ARG_SHIFT;
-    const char *name = op <= FBG_OP_LIS ? ops[op] : "?";
-    if (op == FBG_OP_XYS || op == FBG_OP_LIS) {
+    const char *name = ops[op];
+    if (op == FBG_OP_ACM && (w[0] & FBG_HASPAT)) {
+      snprintf(buf, sizeof buf, "%4zu %-3s tt=%02x r%u\n", pc, name, (w[0] >> FBG_F_SHIFT) & 0xFFu, arg);
+    } else if (op == FBG_OP_ACM) {
+      snprintf(buf, sizeof buf, "%4zu %-3s tt=%02x set=%s mconst=%08x lane=%08x%08x sel=%08x%08x neg=%08x%08x\n", pc,
+               name, (w[0] >> FBG_F_SHIFT) & 0xFFu, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], w[5], w[4],
+               w[7], w[6]);
+    } else if (op == FBG_OP_XYS || op == FBG_OP_LIS) {
       snprintf(buf, sizeof buf,
                "%4zu %-3s tt=%02x set=%s mconst=%08x lane=%08x%08x sel=%08x%08x neg=%08x%08x into r%u\n", pc, name,
                (w[0] >> FBG_F_SHIFT) & 0xFFu, (w[0] & FBG_XORSET) ? "xor" : "or", w[1], w[3], w[2], w[5], w[4], w[7],
@@ -1671,6 +1736,9 @@ void emulate_program(const std::vector<uint32_t> &words, uint32_t nins, int nreg
           break;
         case FBG_OP_ORS: R[arg] = bitop3(tt, cur, R[arg], 0u); break;  // cur keeps its value
         case FBG_OP_LIS: R[arg] = bitop3(tt, cur, set_lane_value(w, lane, U0), 0u); break;  // cur too
+        case FBG_OP_ACM:  // cur keeps its value
+          acc = bitop3(tt, acc, cur, (w[0] & FBG_HASPAT) ? R[arg] : set_lane_value(w, lane, U0));
+          break;
       }
       if (w[0] & FBG_INVOUT) cur = ~cur;
     }

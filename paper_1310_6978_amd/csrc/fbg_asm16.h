@@ -55,7 +55,7 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 #define FBG_J16_DISPATCH                \
   "s_waitcnt lgkmcnt(0)\n"              \
   "s_and_b32 s78, s48, 0xff00\n"        \
-  "s_min_u32 s78, s78, 0xd200\n"        \
+  "s_min_u32 s78, s78, 0xf600\n"        \
   "s_add_u32 s78, s76, s78\n"           \
   "s_addc_u32 s79, s77, 0\n"            \
   "s_setpc_b64 s[78:79]\n"
@@ -175,6 +175,15 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_EACH(FBG_J16_LIS_W, TT) "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
 #define FBG_J16_C_LIS_OR(TT) FBG_J16_T_OR FBG_J16_LIS_TAIL(#TT)
 #define FBG_J16_C_LIS_XOR(TT) FBG_J16_T_XOR FBG_J16_LIS_TAIL(#TT)
+// merged ACC (fbg_isa.h): acc = tt(acc, cur, R[r]) with index mode on the
+// third source, or acc = tt(acc, cur, T)
+#define FBG_J16_ORA_W(i, TT) "v_bitop3_b32 v[96+" #i "], v[96+" #i "], v[16+" #i "], v[32+" #i "] bitop3:" TT "\n"
+#define FBG_J16_C_ORA(TT)                                                                             \
+  "s_set_gpr_idx_on s49, gpr_idx(SRC2)\n" FBG_J16_NEXT_S "s_nop 1\n" FBG_J16_EACH(FBG_J16_ORA_W, #TT) \
+  "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
+#define FBG_J16_LIA_W(i, TT) "v_bitop3_b32 v[96+" #i "], v[96+" #i "], v[16+" #i "], v14 bitop3:" TT "\n"
+#define FBG_J16_C_LIA_OR(TT) FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LIA_W, #TT) FBG_J16_DISPATCH
+#define FBG_J16_C_LIA_XOR(TT) FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LIA_W, #TT) FBG_J16_DISPATCH
 
 #define FBG_J16_C_ST_V(INVOUT)                                                                  \
   "s_set_gpr_idx_on s49, gpr_idx(DST)\n" FBG_J16_NEXT_S "s_nop 1\n" FBG_J16_W16(FBG_J16_STV)     \
@@ -216,6 +225,16 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASE(BASE + 3) MAC(0x10) FBG_J16_CASE(BASE + 4) MAC(0x1F) FBG_J16_CASE(BASE + 5) MAC(0xEF)        \
   FBG_J16_CASE(BASE + 6) MAC(0xFE) FBG_J16_CASE(BASE + 7) MAC(0xF1) FBG_J16_CASE(BASE + 8) MAC(0x01)        \
   FBG_J16_CASE(BASE + 9) MAC(0x0E) FBG_J16_CASE(BASE + 10) MAC(0x1E) FBG_J16_CASE(BASE + 11) MAC(0xE1)
+#define FBG_J16_CASES_ORA(MAC, BASE)                                                                         \
+  FBG_J16_CASE(BASE + 0) MAC(0x80) FBG_J16_CASE(BASE + 1) MAC(0x40) FBG_J16_CASE(BASE + 2) MAC(0xE0)        \
+  FBG_J16_CASE(BASE + 3) MAC(0xD0) FBG_J16_CASE(BASE + 4) MAC(0x60) FBG_J16_CASE(BASE + 5) MAC(0x90)        \
+  FBG_J16_CASE(BASE + 6) MAC(0x70) FBG_J16_CASE(BASE + 7) MAC(0xB0) FBG_J16_CASE(BASE + 8) MAC(0x10)        \
+  FBG_J16_CASE(BASE + 9) MAC(0x20) FBG_J16_CASE(BASE + 10) MAC(0xA0) FBG_J16_CASE(BASE + 11) MAC(0x50)
+#define FBG_J16_CASES_LIA(MAC, BASE)                                                                         \
+  FBG_J16_CASE(BASE + 0) MAC(0xA0) FBG_J16_CASE(BASE + 1) MAC(0x50) FBG_J16_CASE(BASE + 2) MAC(0x80)        \
+  FBG_J16_CASE(BASE + 3) MAC(0x40) FBG_J16_CASE(BASE + 4) MAC(0x70) FBG_J16_CASE(BASE + 5) MAC(0xB0)        \
+  FBG_J16_CASE(BASE + 6) MAC(0xE0) FBG_J16_CASE(BASE + 7) MAC(0xD0) FBG_J16_CASE(BASE + 8) MAC(0x10)        \
+  FBG_J16_CASE(BASE + 9) MAC(0x20) FBG_J16_CASE(BASE + 10) MAC(0x60) FBG_J16_CASE(BASE + 11) MAC(0x90)
 #define FBG_J16_CASES_XORP(MAC, BASE)                                                                        \
   FBG_J16_CASE(BASE + 0) MAC(0x66) FBG_J16_CASE(BASE + 1) MAC(0x99) FBG_J16_CASE(BASE + 2) MAC(0x60)        \
   FBG_J16_CASE(BASE + 3) MAC(0x9F) FBG_J16_CASE(BASE + 4) MAC(0xF6) FBG_J16_CASE(BASE + 5) MAC(0x09)        \
@@ -264,16 +283,20 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASES_NP(FBG_J16_C_XYS_XOR, 174)                                                                   \
   FBG_J16_CASES_NP(FBG_J16_C_LIS_OR, 186)                                                                    \
   FBG_J16_CASES_NP(FBG_J16_C_LIS_XOR, 198)                                                                   \
-  FBG_J16_CASE(210)                                                                                          \
+  FBG_J16_CASES_ORA(FBG_J16_C_ORA, 210)                                                                      \
+  FBG_J16_CASES_LIA(FBG_J16_C_LIA_OR, 222)                                                                   \
+  FBG_J16_CASES_LIA(FBG_J16_C_LIA_XOR, 234)                                                                  \
+  FBG_J16_CASE(246)                                                                                          \
   "Ld%=:\n"                                                                                                  \
   "s_mov_b32 m0, s83\n"
 // clang-format on
 
-static_assert(FBG_J16_NCASES == 210 && FBG_J16_SLOT == 256 && FBG_J16_XYF_OR == 78 && FBG_J16_XYF_XOR == 90 &&
+static_assert(FBG_J16_NCASES == 246 && FBG_J16_SLOT == 256 && FBG_J16_XYF_OR == 78 && FBG_J16_XYF_XOR == 90 &&
                   FBG_J16_XYM_OR == 102 && FBG_J16_XYM_XOR == 114 && FBG_J16_XYL_OR == 126 &&
                   FBG_J16_XYL_XOR == 138 && FBG_J16_ORS == 150 && FBG_J16_XYS_OR == 162 && FBG_J16_XYS_XOR == 174 &&
-                  FBG_J16_LIS_OR == 186 && FBG_J16_LIS_XOR == 198,
-              "the case list of FBG_J16_PROGRAM and the clamp 0xd200 = 210 x 256 of FBG_J16_DISPATCH");
+                  FBG_J16_LIS_OR == 186 && FBG_J16_LIS_XOR == 198 && FBG_J16_ORA == 210 && FBG_J16_LIA_OR == 222 &&
+                  FBG_J16_LIA_XOR == 234,
+              "the case list of FBG_J16_PROGRAM and the clamp 0xf600 = 246 x 256 of FBG_J16_DISPATCH");
 
 // Run the general part of a program (jump-table form at `code`, its pattern
 // table at `table`) on the 16 words of this lane of tile group U0.  acc comes

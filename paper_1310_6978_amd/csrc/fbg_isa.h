@@ -157,6 +157,12 @@
  * in the same place) or an operation on that same register (ORS: R[r] =
  * f(cur, R[r])).  cur keeps its old value; nothing reads it.  In the plain
  * form's terms they are the opcodes XYS, LIS and ORS.
+ *
+ * Merged ACC.  Likewise an ACC (acc &= cur, or acc &= ~cur) after which cur
+ * is dead merges into the operation before it when that is an operation on
+ * a VGPR register (ORA) or a literal set without word literals (LIA): one
+ * v_bitop3 per word over (acc, cur, R[r] or T) computes acc AND the
+ * operation's result.  In the plain form's terms: the opcode ACM.
  */
 #ifndef FBG_ISA_H
 #define FBG_ISA_H
@@ -180,6 +186,9 @@
 #define FBG_OP_XYS 12u
 #define FBG_OP_ORS 13u
 #define FBG_OP_LIS 14u
+/* an ACC merged into the operation before it (see Merged ACC): only as the
+   decoded jump-table form; FBG_HASPAT marks the register form */
+#define FBG_OP_ACM 15u
 
 #define FBG_XORSET (1u << 4)
 #define FBG_HASPAT (1u << 5)
@@ -233,13 +242,20 @@
 #define FBG_J16_XYS_XOR 174u
 #define FBG_J16_LIS_OR 186u     /* literal set without word literals, the result into R[r]: + table index */
 #define FBG_J16_LIS_XOR 198u
-#define FBG_J16_NCASES 210u
+#define FBG_J16_ORA 210u        /* + table index: acc = tt(acc, cur, R[r]), cur left (an operation and ACC) */
+#define FBG_J16_LIA_OR 222u     /* + table index: acc = tt(acc, cur, T), cur left (a literal set and ACC) */
+#define FBG_J16_LIA_XOR 234u
+#define FBG_J16_NCASES 246u
 /* Truth tables of the cases, over (cur = 0xF0, T or R = 0xCC, P = 0xAA).
    Without word literals P is 0, so only the bits of 0x55 matter. */
 #define FBG_J16_REG_TABLES(X) X(0xC0) X(0x30) X(0xFC) X(0xF3) X(0x3C) X(0xC3) X(0x3F) X(0xCF) X(0x03) X(0x0C) X(0xCC) X(0x33)
 #define FBG_J16_NP_TABLES(X) X(0x44) X(0x11) X(0x40) X(0x10) X(0x15) X(0x45) X(0x54) X(0x51) X(0x01) X(0x04) X(0x14) X(0x41)
 #define FBG_J16_OR_TABLES(X) X(0xEE) X(0x11) X(0xE0) X(0x10) X(0x1F) X(0xEF) X(0xFE) X(0xF1) X(0x01) X(0x0E) X(0x1E) X(0xE1)
 #define FBG_J16_XOR_TABLES(X) X(0x66) X(0x99) X(0x60) X(0x9F) X(0xF6) X(0x09) X(0x96) X(0x69)
+/* Merged ACC, over (acc = 0xF0, cur = 0xCC, R or T = 0xAA): acc AND the
+   operation of the register table (or the literal table) of the same index */
+#define FBG_J16_ORA_TABLES(X) X(0x80) X(0x40) X(0xE0) X(0xD0) X(0x60) X(0x90) X(0x70) X(0xB0) X(0x10) X(0x20) X(0xA0) X(0x50)
+#define FBG_J16_LIA_TABLES(X) X(0xA0) X(0x50) X(0x80) X(0x40) X(0x70) X(0xB0) X(0xE0) X(0xD0) X(0x10) X(0x20) X(0x60) X(0x90)
 
 /* In-word generator masks: bit j of MASK_k is bit k of j (Section 2.2). */
 static inline uint32_t fbg_inword_mask(int k) {

@@ -33,7 +33,7 @@ def check(text, n, wpl=WPL):
     return p
 
 
-MERGED = ("XYS", "LIS", "ORS")   # jump-table instructions that hold a store as well
+MERGED = ("XYS", "LIS", "ORS", "ACM")   # jump-table instructions that hold a store or an ACC as well
 
 
 def instructions(listing):
