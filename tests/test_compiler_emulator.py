@@ -333,6 +333,19 @@ def test_merged_stores():
         check(t, 17, wpl=[16])
 
 
+@pytest.mark.parametrize("text", ["t = x0 ^ x7 | x16\nt & (t | x3 & x9) & (t ^ x17)",
+                                  "t = (x0 ^ x7) & x16\nu = t | x4\nt & u & (u ^ x2)",
+                                  "t = x1 & ~x12\nu = t ^ x5\n(u | x17) & ~(t & x3) & (u | t)"])
+def test_merged_acc(text):
+    """An ACC after which cur is dead merges into the register operation or
+    literal set before it (ACM: acc = f(acc, cur, operand), ACC's inversion
+    folded in); where cur is read after the ACC, or the instruction before
+    it is a store, the ACC stays.  Emulated with cur left stale."""
+    p = check(text, 18, wpl=[16, 8, 32])
+    ops = [op for _, op in instructions(p.disasm(16))]
+    assert "ACM" in ops, ops
+
+
 def test_run_of_four_literal_sets_is_one_chain():
     """Four literal sets in a row (lane, in-word and tile literals) become
     XYF, XYM, XYM, XYL; the clause x9 stays in the clause block."""
