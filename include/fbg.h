@@ -115,6 +115,17 @@ typedef struct {
    data-dependent (usually much smaller) work. */
 #define FBG_TUNE_COFACTOR 1
 
+/* Compile flags: the tilings to encode.  A program is encoded once per
+   tiling (1, 2, 4, 8, 16 and 32 words per lane), which is most of a short
+   program's compile time; a caller that only ever runs it at known tilings
+   (a server at a fixed tiling) asks for those alone.  flags = 0 encodes
+   every tiling.  A call at a tiling the program was not encoded for
+   (words_per_lane of fbg_tune, a batch, a server, fbg_program_emulate,
+   fbg_program_disasm) fails with FBG_E_INVAL; the library's own default
+   tiling is always one that was encoded. */
+#define FBG_COMPILE_WPL(words_per_lane_log2) (1u << (words_per_lane_log2))
+#define FBG_COMPILE_WPL_MASK 0x3Fu
+
 /*
  * fbg_compile -- turn formula text into a straight-line bitwise program and
  * upload it to the current HIP device (Section 4.1: the engine builds a
@@ -122,7 +133,8 @@ typedef struct {
  *   src     NUL-terminated formula text (format above).
  *   n_vars  n, 0 <= n <= FBG_MAX_VARS; every variable used must be < n.
  *           Variables below n that do not occur still index valuations.
- *   flags   0 (reserved).
+ *   flags   0, or an OR of FBG_COMPILE_WPL(k): encode only those tilings.
+ *           Other bits: FBG_E_INVAL.
  *   out     receives the program; free it with fbg_program_free.
  * Errors: FBG_E_PARSE (with offset), FBG_E_RANGE, FBG_E_INVAL, FBG_E_NOMEM,
  * FBG_E_DEVICE.  Synchronous.
@@ -140,7 +152,7 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
  *   assume  host array of n_vars entries (caller-owned, read during the
  *           call): 0 or 1 kills xk to that constant, -1 leaves it free.  May
  *           be NULL only when n_vars = 0.
- *   flags   0 (reserved).
+ *   flags   as fbg_compile.
  *   out     the program over the f free variables, renumbered in increasing
  *           order: bit j of a valuation index is the j-th free variable.
  * FBG_E_INVAL for an entry outside {-1, 0, 1}, FBG_E_RANGE if f exceeds
@@ -167,7 +179,7 @@ fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *ass
  *           may map to one j).  May be NULL only when n_vars = 0.
  *   n_free  the program's variables, 0 <= n_free <= FBG_MAX_VARS; a j that
  *           no letter maps to still indexes valuations (and doubles counts).
- *   flags   0 (reserved).
+ *   flags   as fbg_compile.
  * FBG_E_INVAL for an entry outside [-2, n_free); otherwise as fbg_compile.
  * Synchronous.
  */

@@ -150,6 +150,8 @@ struct fbg_program {
   std::vector<uint32_t> words[kMaxLog2W + 1];
   uint64_t dev_off[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
   uint32_t nins[kMaxLog2W + 1] = {0, 0, 0, 0, 0, 0};
+  uint32_t tilings = FBG_COMPILE_WPL_MASK;  // bit l: encoded for 2^l words per lane
+  bool has_tiling(int l) const { return (tilings >> l) & 1u; }
   // programs of clauses alone with n >= kXcdMinVars: the 32-words-per-lane
   // encoding with variables exchanged for the XCD-local DNF write-out
   std::vector<uint32_t> words_xcd;
@@ -275,10 +277,17 @@ fbg_status block_shape(uint32_t nregs, int l, int &wpb, size_t &lds) {
 // Launch shape of an evaluator kernel: a persistent grid of exactly the
 // blocks that can be resident at once (more would only queue behind them and
 // finish in a tail), each wave striding over the tiles.
+fbg_status check_tiling(const fbg_program *p, int l) {
+  if (!p->has_tiling(l))
+    return fail(FBG_E_INVAL, "the program was compiled without %d words per lane (FBG_COMPILE_WPL)", 1 << l);
+  return FBG_OK;
+}
+
 fbg_status geometry(const fbg_program *p, const fbg_tune *tune, int mode, Geometry &g) {
   int l = p->auto_log2w;
   fbg_status st;
   if (tune && tune->words_per_lane && (st = parse_wpl(tune->words_per_lane, l))) return st;
+  if ((st = check_tiling(p, l))) return st;
   int wpb;
   if ((st = block_shape((uint32_t)p->c.nregs, l, wpb, g.lds))) return st;
   const uint64_t ntiles = tiles_of(p->nslices, l);
@@ -398,10 +407,27 @@ int64_t fbg_last_error_offset(void) { return g_err_off; }
 
 namespace {
 
-fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst, int32_t n_free,
+// The tiling that pick_log2w prefers, or the nearest one the program is
+// encoded for (the larger of two equally near).
+int nearest_tiling(uint32_t tilings, int l) {
+  for (int d = 0; d <= kMaxLog2W; d++) {
+    if (l + d <= kMaxLog2W && ((tilings >> (l + d)) & 1u)) return l + d;
+    if (l - d >= 0 && ((tilings >> (l - d)) & 1u)) return l - d;
+  }
+  return l;
+}
+
+fbg_status check_flags(uint32_t flags) {
+  if (flags & ~FBG_COMPILE_WPL_MASK)
+    return fail(FBG_E_INVAL, "flags 0x%x: only FBG_COMPILE_WPL(0..5) bits are defined", flags);
+  return FBG_OK;
+}
+
+fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst, int32_t n_free, uint32_t flags,
                           fbg_program **out) {
   fbg_program *p = new (std::nothrow) fbg_program();
   if (!p) return fail(FBG_E_NOMEM, "out of host memory");
+  p->tilings = flags & FBG_COMPILE_WPL_MASK ? flags & FBG_COMPILE_WPL_MASK : FBG_COMPILE_WPL_MASK;
   std::string msg;
   int64_t off = -1;
   int st = fbg::compile_formula(src, n_vars, p->c, msg, off, subst, n_free);
@@ -417,11 +443,12 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
   size_t total = 0;
   std::string enc_err;
   for (int l = 0; l <= kMaxLog2W; l++) {
+    if (!p->has_tiling(l)) continue;  // not asked for: left empty
     p->nins[l] = fbg::encode_program(p->c, l, p->words[l], &enc_err);
     p->dev_off[l] = total;
     total += p->words[l].size();
   }
-  if (!p->general() && p->c.n >= fbg::kXcdMinVars) {
+  if (!p->general() && p->c.n >= fbg::kXcdMinVars && p->has_tiling(5)) {
     const fbg::Compiled x = fbg::exchange_variables(p->c, fbg::kXcdSwapA, fbg::kXcdSwapB, fbg::kXcdSwapLen);
     const uint32_t nx = fbg::encode_program(x, 5, p->words_xcd, &enc_err);
     if (nx != p->nins[5] && enc_err.empty()) enc_err = "internal: exchanged encoding differs in length";
@@ -463,6 +490,7 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
   } else {
     p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, p->general(), -1);
   }
+  p->auto_log2w = nearest_tiling(p->tilings, p->auto_log2w);
   *out = p;
   return FBG_OK;
 }
@@ -475,9 +503,10 @@ fbg_status fbg_compile(const char *src, int32_t n_vars, uint32_t flags, fbg_prog
   if (!out) return fail(FBG_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!src) return fail(FBG_E_INVAL, "src is NULL");
-  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
+  fbg_status st = check_flags(flags);
+  if (st) return st;
   if (n_vars < 0 || n_vars > FBG_MAX_VARS) return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_VARS);
-  return compile_common(src, n_vars, nullptr, 0, out);
+  return compile_common(src, n_vars, nullptr, 0, flags, out);
 }
 
 fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *assume, uint32_t flags,
@@ -485,7 +514,8 @@ fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *ass
   if (!out) return fail(FBG_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!src) return fail(FBG_E_INVAL, "src is NULL");
-  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
+  fbg_status st = check_flags(flags);
+  if (st) return st;
   if (n_vars < 0 || n_vars > FBG_MAX_TEXT_VARS)
     return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_TEXT_VARS);
   if (n_vars > 0 && !assume) return fail(FBG_E_INVAL, "assume is NULL");
@@ -497,7 +527,7 @@ fbg_status fbg_compile_assume(const char *src, int32_t n_vars, const int8_t *ass
     subst[(size_t)k] = assume[k] < 0 ? nfree++ : (assume[k] ? FBG_SUBST_ONE : FBG_SUBST_ZERO);
   }
   if (nfree > FBG_MAX_VARS) return fail(FBG_E_RANGE, "%d free variables (max %d)", nfree, FBG_MAX_VARS);
-  return compile_common(src, n_vars, subst.data(), nfree, out);
+  return compile_common(src, n_vars, subst.data(), nfree, flags, out);
 }
 
 fbg_status fbg_compile_subst(const char *src, int32_t n_vars, const int32_t *subst, int32_t n_free, uint32_t flags,
@@ -505,7 +535,8 @@ fbg_status fbg_compile_subst(const char *src, int32_t n_vars, const int32_t *sub
   if (!out) return fail(FBG_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!src) return fail(FBG_E_INVAL, "src is NULL");
-  if (flags != 0) return fail(FBG_E_INVAL, "flags must be 0");
+  fbg_status st = check_flags(flags);
+  if (st) return st;
   if (n_vars < 0 || n_vars > FBG_MAX_TEXT_VARS)
     return fail(FBG_E_RANGE, "n=%d out of range [0,%d]", n_vars, FBG_MAX_TEXT_VARS);
   if (n_free < 0 || n_free > FBG_MAX_VARS) return fail(FBG_E_RANGE, "n_free=%d out of range [0,%d]", n_free,
@@ -514,7 +545,7 @@ fbg_status fbg_compile_subst(const char *src, int32_t n_vars, const int32_t *sub
   for (int32_t k = 0; k < n_vars; k++)
     if (subst[k] < FBG_SUBST_ONE || subst[k] >= n_free)
       return fail(FBG_E_INVAL, "subst[%d] = %d (must be -1, -2 or in [0, %d))", k, subst[k], n_free);
-  return compile_common(src, n_vars, subst, n_free, out);
+  return compile_common(src, n_vars, subst, n_free, flags, out);
 }
 
 void fbg_program_free(fbg_program *p) {
@@ -529,9 +560,8 @@ fbg_status fbg_program_info(const fbg_program *p, struct fbg_program_info *out) 
   out->n_vars = p->c.n;
   out->const_value = p->c.const_value;
   out->l2in = p->c.l2in;
-  // clauses + instructions after them, in the plain form (one word per lane
-  // is never the jump-table form, which adds the ends of chains)
-  out->n_instr = (int32_t)(p->ncl + p->nins[0]);
+  // clauses + instructions after them, in the plain form
+  out->n_instr = (int32_t)p->c.code.size();
   out->n_regs = p->c.nregs;
   out->n_clause_instr = (int32_t)p->ncl;
   out->words_per_lane = 1 << p->auto_log2w;
@@ -551,6 +581,7 @@ fbg_status fbg_program_set_tuning(fbg_program *p, const fbg_tune *tune) {
   int l = p->auto_log2w;
   fbg_status st;
   if (tune->words_per_lane && (st = parse_wpl(tune->words_per_lane, l))) return st;
+  if ((st = check_tiling(p, l))) return st;
   int wpb;
   size_t lds;
   if ((st = block_shape((uint32_t)p->c.nregs, l, wpb, lds))) return st;
@@ -753,6 +784,10 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     uint32_t max_regs = 0;
     int var = 0;
     for (int32_t i : members) {
+      if (!ps[i]->has_tiling(l)) {
+        fbg_batch_free(b);
+        return fail(FBG_E_INVAL, "program %d was compiled without %d words per lane (FBG_COMPILE_WPL)", i, 1 << l);
+      }
       max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
       var |= ps[i]->variant(tune);
     }
@@ -784,7 +819,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       q = batch_prog(ps[i], l);
       // per tile about one step per instruction (counted in the plain form:
       // one word per lane never takes the jump-table form) and a few more
-      total_cost += (double)q.ntiles * (ps[i]->nins[0] + 4.0);
+      total_cost += (double)q.ntiles * ((double)(ps[i]->c.code.size() - ps[i]->ncl) + 4.0);
       b->plan_of[(size_t)i] = (int)b->plans.size();
     }
     // about four items per wave; never split below one tile.  A program's
@@ -796,7 +831,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     std::vector<double> cost;
     for (int32_t i : members) {
       const fbg::BatchProg &q = b->host_progs[(size_t)i];
-      const double per_tile = ps[i]->nins[0] + 4.0;
+      const double per_tile = (double)(ps[i]->c.code.size() - ps[i]->ncl) + 4.0;
       const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
       const uint64_t K = (q.ntiles + chunk - 1) / chunk;
       for (uint64_t k = 0; k < K; k++) {
@@ -1194,6 +1229,7 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   int var = sv->cofactor ? 2 : 0;
   for (int32_t i = 0; i < np; i++) {
     if ((st = check_program(ps[i]))) return st;
+    if ((st = check_tiling(ps[i], l))) return st;
     max_regs = std::max<uint32_t>(max_regs, (uint32_t)ps[i]->c.nregs);
     var |= ps[i]->variant(nullptr);
   }
@@ -1218,7 +1254,7 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   if (sl.used && (e = hipEventSynchronize(sl.done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
   fbg::BatchProg *hp = (fbg::BatchProg *)sl.h;
   fbg::BatchItem *hi = (fbg::BatchItem *)(sl.h + (size_t)sv->max_programs * sizeof(fbg::BatchProg));
-  for (int32_t i = 0; i < np; i++) hp[i] = batch_prog(ps[i], l);
+  for (int32_t i = 0; i < np; i++) hp[i] = batch_prog(ps[i], l);  // tilings checked above
   // Cut the items into pieces of at most `piece` tiles so that every resident
   // wave gets about four, within the staging capacity: the pieces number at
   // most (total tiles / piece) + nitems <= max_items.
@@ -1281,6 +1317,7 @@ fbg_status fbg_program_emulate(const fbg_program *p, int32_t words_per_lane, uin
   int l;
   fbg_status st = parse_wpl(words_per_lane, l);
   if (st) return st;
+  if ((st = check_tiling(p, l))) return st;
   const uint64_t need = dnf_words_of(p->c.n);
   if (h_dnf && out_words < need) return fail(FBG_E_INVAL, "out_words too small");
   std::vector<uint32_t> s32((size_t)std::max<uint64_t>(2, p->nslices), 0u);
@@ -1298,6 +1335,7 @@ int64_t fbg_program_disasm(const fbg_program *p, int32_t words_per_lane, char *b
   if (!p) return -1;
   int l = p->auto_log2w;
   if (words_per_lane > 0 && parse_wpl(words_per_lane, l)) return -1;
+  if (check_tiling(p, l)) return -1;
   std::string s = fbg::disasm_program(p->words[l], p->nins[l], l);
   if (buf && cap > 0) {
     size_t k = std::min<size_t>((size_t)cap - 1, s.size());

@@ -27,6 +27,19 @@ _STATUS = {0: "FBG_OK", -1: "FBG_E_INVAL", -2: "FBG_E_PARSE", -3: "FBG_E_RANGE",
 MAX_VARS = 48
 MAX_DNF_VARS = 40
 MAX_WORDS_PER_LANE = 32
+COMPILE_WPL_MASK = 0x3F
+
+
+def compile_wpl(*words_per_lane):
+    """Compile flags that encode a program only for these tilings (words
+    per lane); a call at any other tiling then fails with FBG_E_INVAL."""
+    f = 0
+    for w in words_per_lane:
+        w = int(w)
+        if w < 1 or w > MAX_WORDS_PER_LANE or w & (w - 1):
+            raise ValueError(f"words per lane {w}: not one of 1, 2, 4, 8, 16, 32")
+        f |= 1 << (w.bit_length() - 1)
+    return f
 
 
 class FbgError(RuntimeError):

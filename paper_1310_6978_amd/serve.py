@@ -49,10 +49,12 @@ class Admission:
 
 class ProgramCache:
     """Compiled programs kept resident, keyed by the hash of the text and n;
-    least recently used entries beyond `capacity` are freed."""
+    least recently used entries beyond `capacity` are freed.  `flags` are the
+    compile flags (the loop encodes only the server's tiling)."""
 
-    def __init__(self, capacity=64):
+    def __init__(self, capacity=64, flags=0):
         self.capacity = capacity
+        self.flags = int(flags)
         self.entries = collections.OrderedDict()
         self.hits = 0
         self.misses = 0
@@ -65,7 +67,7 @@ class ProgramCache:
             self.hits += 1
             return p
         self.misses += 1
-        p = fbg.Program(text, n)
+        p = fbg.Program(text, n, self.flags)
         self.entries[key] = p
         while len(self.entries) > self.capacity:
             self.entries.popitem(last=False)
@@ -111,7 +113,7 @@ class ServeLoop:
         self.copy_stream = torch.cuda.Stream()
         self.server = fbg.Server(max_programs=max_active, max_items=max_items, words_per_lane=self.W,
                                  nbuf=2 * nstreams + 2)
-        self.cache = ProgramCache(cache_capacity)
+        self.cache = ProgramCache(cache_capacity, flags=fbg.compile_wpl(self.W))
 
     def run(self, requests, realtime=True, log=None):
         torch = self.torch

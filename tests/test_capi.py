@@ -58,7 +58,8 @@ def test_null_arguments():
     assert fbg.lib.fbg_program_get_info(None, None) == fbg.FBG_E_INVAL
     out = ctypes.c_void_p()
     assert fbg.lib.fbg_compile(None, 3, 0, ctypes.byref(out)) == fbg.FBG_E_INVAL
-    assert fbg.lib.fbg_compile(b"x0", 3, 7, ctypes.byref(out)) == fbg.FBG_E_INVAL
+    assert fbg.lib.fbg_compile(b"x0", 3, 0x40, ctypes.byref(out)) == fbg.FBG_E_INVAL
+    assert "flags" in fbg.lib.fbg_last_error().decode()
     fbg.lib.fbg_program_free(None)
     fbg.lib.fbg_batch_free(None)
 
@@ -77,3 +78,35 @@ def test_program_info_through_the_c_abi():
     assert fbg.lib.fbg_program_get_info(p.handle, ctypes.byref(old)) == fbg.FBG_OK
     assert old.l_valu == info.l_valu and old.l2in == info.l2in
     assert p.info["l_valu"] == info.l_valu
+
+
+def test_compile_only_some_tilings():
+    """FBG_COMPILE_WPL: the program is encoded for the tilings asked for; the
+    results there are those of a full compile, every other tiling is refused."""
+    text, n = "a = x0 & x1\nb = a ^ x5\nb | (x2 & ~x7)\nx3 | ~x4 | x6", 8
+    full = fbg.Program(text, n)
+    part = fbg.Program(text, n, fbg.compile_wpl(4, 16))
+    assert fbg.compile_wpl(1, 2, 4, 8, 16, 32) == fbg.COMPILE_WPL_MASK
+    with pytest.raises(ValueError):
+        fbg.compile_wpl(3)
+    assert part.info["words_per_lane"] in (4, 16)
+    assert part.info["code_bytes"] <= full.info["code_bytes"]
+    assert part.info["n_instr"] == full.info["n_instr"] and part.info["l2in"] == full.info["l2in"]
+    for w in (4, 16):
+        d0, c0 = full.emulate(w)
+        d1, c1 = part.emulate(w)
+        assert c0 == c1 and (d0 == d1).all()
+        assert part.disasm(w) == full.disasm(w)
+    for w in (1, 2, 8, 32):
+        with pytest.raises(fbg.FbgError) as e:
+            part.emulate(w)
+        assert e.value.status == fbg.FBG_E_INVAL and "words per lane" in str(e.value)
+        assert fbg.lib.fbg_program_disasm(part.handle, w, None, 0) == -1
+        t = fbg.Tune(w, 0, 0, 0)
+        assert fbg.lib.fbg_program_set_tuning(part.handle, ctypes.byref(t)) == fbg.FBG_E_INVAL
+    part.set_tuning(4)
+    assert part.info["words_per_lane"] == 4
+    # the default tiling of a one-tiling program is that tiling
+    one = fbg.Program(text, n, fbg.compile_wpl(2))
+    assert one.info["words_per_lane"] == 2
+    assert one.emulate(2)[1] == full.emulate(2)[1]

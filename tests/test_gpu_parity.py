@@ -343,6 +343,39 @@ def test_server_rejects_bad_items(F):
     sv.free()
 
 
+def test_programs_compiled_for_some_tilings(F):
+    """Programs encoded only for the tilings asked for (FBG_COMPILE_WPL)
+    count as full compiles at those tilings, alone, batched and served; the
+    host refuses every other tiling before anything is launched."""
+    import torch
+    texts = [workloads.random_3cnf(16, 40, 1), workloads.random_dag(18, 300, 4), workloads.triangle_free(6)]
+    want = [oracle.count(t, n) for t, n in texts]
+    progs = [F.Program(t, n, F.compile_wpl(16)) for t, n in texts]
+    assert [gpu_count(F, p) for p in progs] == want
+    assert [gpu_count(F, p, 16) for p in progs] == want
+    assert host(F.Batch(progs, words_per_lane=16).count()).tolist() == want
+    sv = F.Server(len(progs), 8, 16, nbuf=2)
+    counts = torch.zeros(len(progs), dtype=torch.int64, device="cuda")
+    sv.launch(progs, [(i, i, 0, F.program_tiles(p, 16)) for i, p in enumerate(progs)], counts)
+    assert host(counts).tolist() == want
+    sv.free()
+    for call in (lambda: F.count(progs[0], words_per_lane=8),
+                 lambda: F.eval_dnf(progs[1], words_per_lane=32),
+                 lambda: F.Batch(progs, words_per_lane=4)):
+        with pytest.raises(F.FbgError) as ei:
+            call()
+        assert ei.value.status == F.FBG_E_INVAL
+    sv = F.Server(len(progs), 8, 8, nbuf=2)
+    with pytest.raises(F.FbgError) as ei:
+        sv.launch(progs[:1], [(0, 0, 0, F.program_tiles(progs[0], 8))], counts)
+    assert ei.value.status == F.FBG_E_INVAL
+    sv.free()
+    # clause-only programs at 32 words per lane keep the XCD-local write-out
+    t, n = workloads.random_3cnf(22, 60, 3)
+    full, part = F.Program(t, n), F.Program(t, n, F.compile_wpl(32))
+    assert np.array_equal(gpu_dnf(F, part, 32), gpu_dnf(F, full, 32))
+
+
 def test_batch_graph_replays_match_eager(F):
     import torch
     rng = random.Random(3)
