@@ -6,7 +6,7 @@
 // instructions of one program instruction; the scalar unit, which issues no
 // faster than the VALU, then bounds the loop.  Here every instruction carries
 // the byte offset of its case, and one s_setpc_b64 enters the case's code
-// directly (5 scalar instructions).  Each case fetches the next instruction
+// directly (4 scalar instructions).  Each case fetches the next instruction
 // before its VALU work, so the fetch is waited for only at the next dispatch.
 //
 // Register map (fixed; the C++ side sees acc as a pinned in/out operand and
@@ -49,13 +49,12 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 // long, so it never reads past the program.
 #define FBG_J16_NEXT_L "s_add_u32 s80, s80, 32\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
 #define FBG_J16_NEXT_S "s_add_u32 s80, s80, 8\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
-// Wait for it and jump to its case.  The offset is cut to a whole slot and
-// clamped to the slot past the last case, where the interpreter exits: no
-// instruction word can send the jump outside the table.
+// Wait for it and jump to its case.  The offset is cut to a whole slot of
+// the 256 the table holds (the slots past the last case exit the
+// interpreter): no instruction word can send the jump outside the table.
 #define FBG_J16_DISPATCH                \
   "s_waitcnt lgkmcnt(0)\n"              \
   "s_and_b32 s78, s48, 0xff00\n"        \
-  "s_min_u32 s78, s78, 0xf600\n"        \
   "s_add_u32 s78, s76, s78\n"           \
   "s_addc_u32 s79, s77, 0\n"            \
   "s_setpc_b64 s[78:79]\n"
@@ -286,7 +285,10 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASES_ORA(FBG_J16_C_ORA, 210)                                                                      \
   FBG_J16_CASES_LIA(FBG_J16_C_LIA_OR, 222)                                                                   \
   FBG_J16_CASES_LIA(FBG_J16_C_LIA_XOR, 234)                                                                  \
-  FBG_J16_CASE(246)                                                                                          \
+  FBG_J16_CASE(246) "s_branch Ld%=\n" FBG_J16_CASE(247) "s_branch Ld%=\n" FBG_J16_CASE(248) "s_branch Ld%=\n"   \
+  FBG_J16_CASE(249) "s_branch Ld%=\n" FBG_J16_CASE(250) "s_branch Ld%=\n" FBG_J16_CASE(251) "s_branch Ld%=\n"   \
+  FBG_J16_CASE(252) "s_branch Ld%=\n" FBG_J16_CASE(253) "s_branch Ld%=\n" FBG_J16_CASE(254) "s_branch Ld%=\n"   \
+  FBG_J16_CASE(255)                                                                                          \
   "Ld%=:\n"                                                                                                  \
   "s_mov_b32 m0, s83\n"
 // clang-format on
@@ -296,7 +298,7 @@ static_assert(FBG_J16_NCASES == 246 && FBG_J16_SLOT == 256 && FBG_J16_XYF_OR == 
                   FBG_J16_XYL_XOR == 138 && FBG_J16_ORS == 150 && FBG_J16_XYS_OR == 162 && FBG_J16_XYS_XOR == 174 &&
                   FBG_J16_LIS_OR == 186 && FBG_J16_LIS_XOR == 198 && FBG_J16_ORA == 210 && FBG_J16_LIA_OR == 222 &&
                   FBG_J16_LIA_XOR == 234,
-              "the case list of FBG_J16_PROGRAM and the clamp 0xf600 = 246 x 256 of FBG_J16_DISPATCH");
+              "the case list of FBG_J16_PROGRAM: 246 cases, then exits up to slot 255 (FBG_J16_DISPATCH)");
 
 // Run the general part of a program (jump-table form at `code`, its pattern
 // table at `table`) on the 16 words of this lane of tile group U0.  acc comes
