@@ -2,6 +2,7 @@
 // geometry, work plans for batches and serving, and argument checking.
 #include <hip/hip_runtime_api.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -307,6 +308,14 @@ fbg_status geometry(const fbg_program *p, const fbg_tune *tune, int mode, Geomet
   return FBG_OK;
 }
 
+// FBG_J16_TABLE=any in the environment makes the jump-table interpreter run
+// the copy of its table meant for code loaded off a 64 KiB boundary, so that
+// tests cover it (both copies compute the same).  Read at every launch.
+uint32_t j16_any() {
+  const char *v = getenv("FBG_J16_TABLE");
+  return (v && strcmp(v, "any") == 0) ? 1u : 0u;
+}
+
 fbg_status check_device(int want) {
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
@@ -330,6 +339,7 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   a.n = p->c.n;
   a.nslices = p->nslices;
   a.ntiles = tiles_of(p->nslices, log2w);
+  a.j16_any = j16_any();
   return a;
 }
 
@@ -952,6 +962,7 @@ fbg_status batch_launch(fbg_batch *b, int mode, const fbg::BatchProg *d_progs, u
     a.counts = d_counts;
     a.gscratch = pl.d_gscratch;
     a.gstride = pl.gstride;
+    a.j16_any = j16_any();
     if (mode == fbg::EVAL_DNF && pl.d_direct && b->d_tile_counts) {
       // one wave per tile over the plan's programs in order; counts from the
       // tile counts
@@ -1289,6 +1300,7 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   a.max_regs = lds_regs(max_regs, l);
   a.head = sl.d_head;
   a.counts = d_counts;
+  a.j16_any = j16_any();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((npieces + wpb - 1) / wpb, (int64_t)cus * occ));
   e = fbg::launch_batch(fbg::EVAL_COUNT, l, var, a, grid, 64 * wpb, lds, s);
   if (e == hipSuccess) e = hipEventRecord(sl.done, s);

@@ -49,18 +49,22 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 // long, so it never reads past the program.
 #define FBG_J16_NEXT_L "s_add_u32 s80, s80, 32\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
 #define FBG_J16_NEXT_S "s_add_u32 s80, s80, 8\n" "s_load_dwordx8 s[48:55], %[code], s80\n"
-// Wait for it and jump to its case.  The offset is cut to a whole slot of
-// the 256 the table holds (the slots past the last case exit the
-// interpreter): no instruction word can send the jump outside the table.
-#define FBG_J16_DISPATCH                \
-  "s_waitcnt lgkmcnt(0)\n"              \
-  "s_and_b32 s78, s48, 0xff00\n"        \
-  "s_add_u32 s78, s76, s78\n"           \
-  "s_addc_u32 s79, s77, 0\n"            \
+// Wait for it and jump to its case: an assembler macro (fbgdisp), defined
+// once per copy of the table (FBG_J16_PROGRAM).  The offset is bits 0..15 of
+// the instruction's first word, so no instruction word can send the jump
+// outside the table's 256 slots (those past the last case exit).
+#define FBG_J16_DISPATCH "fbgdisp%=\n"
+// The table on a 64 KiB boundary: s77 holds bits 16..31 of its address and
+// s79 bits 32..63, so the jump target is the offset packed under s77.
+#define FBG_J16_DISPATCH_ALIGNED "s_waitcnt lgkmcnt(0)\n" "s_pack_ll_b32_b16 s78, s48, s77\n" "s_setpc_b64 s[78:79]\n"
+// Anywhere: s[76:77] holds its address; the offset, cut to a whole slot, is
+// added to it.
+#define FBG_J16_DISPATCH_ANY                                                                           \
+  "s_waitcnt lgkmcnt(0)\n" "s_and_b32 s78, s48, 0xff00\n" "s_add_u32 s78, s76, s78\n" "s_addc_u32 s79, s77, 0\n" \
   "s_setpc_b64 s[78:79]\n"
 // Start of case k: its slot of the table (an .org that moves backwards, i.e.
 // a case longer than its slot, is an assembly error).
-#define FBG_J16_CASE(k) ".org Lc%=+(" FBG_J16_STR(k) ")*256\n"
+#define FBG_J16_CASE(k) ".org Lc%=\\s+(" FBG_J16_STR(k) ")*256\n"
 
 // per-word bodies
 #define FBG_J16_NOTCUR(i) "v_not_b32 v[16+" #i "], v[16+" #i "]\n"
@@ -116,7 +120,7 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 // then the operation
 #define FBG_J16_C_REGL(TT)                                                                \
   "s_cmp_lt_u32 s49, %[ldsb]\n"                                                          \
-  "s_cbranch_scc0 LG" #TT "%=\n"                                                          \
+  "s_cbranch_scc0 LG" #TT "%=\\s\n"                                                          \
   "v_add_u32 v15, s49, %[lb]\n"                                                           \
   "ds_read_b128 v[80:83], v15\n"                                                         \
   "ds_read_b128 v[84:87], v15 offset:16\n"                                               \
@@ -127,7 +131,7 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 // the global-memory half: the same register read from the wave's block at
 // %[gb], lane l at 64 l (%[l64]); earlier stores of this wave are waited for
 #define FBG_J16_G_REGL(TT)                                                                \
-  "LG" #TT "%=:\n"                                                                        \
+  "LG" #TT "%=\\s:\n"                                                                        \
   "s_sub_u32 s72, s49, %[ldsb]\n"                                                         \
   "v_add_u32 v15, s72, %[l64]\n"                                                          \
   "s_waitcnt vmcnt(0)\n"                                                                  \
@@ -189,14 +193,14 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   "s_set_gpr_idx_off\n" INVOUT FBG_J16_DISPATCH
 #define FBG_J16_C_ST_L(INVOUT, G)                                             \
   "s_cmp_lt_u32 s49, %[ldsb]\n"                                              \
-  "s_cbranch_scc0 LGST" #G "%=\n"                                             \
+  "s_cbranch_scc0 LGST" #G "%=\\s\n"                                             \
   "v_add_u32 v15, s49, %[lb]\n"                                               \
   "ds_write_b128 v15, v[16:19]\n"                                             \
   "ds_write_b128 v15, v[20:23] offset:16\n"                                   \
   "ds_write_b128 v15, v[24:27] offset:32\n"                                   \
   "ds_write_b128 v15, v[28:31] offset:48\n" FBG_J16_NEXT_S INVOUT FBG_J16_DISPATCH
 #define FBG_J16_G_ST_L(INVOUT, G)                                             \
-  "LGST" #G "%=:\n"                                                           \
+  "LGST" #G "%=\\s:\n"                                                           \
   "s_sub_u32 s72, s49, %[ldsb]\n"                                            \
   "v_add_u32 v15, s72, %[l64]\n"                                             \
   "global_store_dwordx4 v15, v[16:19], %[gb]\n"                              \
@@ -240,22 +244,14 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASE(BASE + 6) MAC(0x96) FBG_J16_CASE(BASE + 7) MAC(0x69)
 
 // clang-format off
-#define FBG_J16_PROGRAM                                                                                      \
-  "s_mov_b32 s83, m0\n"                                                                                      \
-  "s_getpc_b64 s[76:77]\n"                                                                                   \
-  "Lb%=:\n"                                                                                                  \
-  "s_add_u32 s76, s76, Lc%=-Lb%=\n"                                                                          \
-  "s_addc_u32 s77, s77, 0\n"                                                                                 \
-  "s_mov_b32 s80, 0\n"                                                                                       \
-  "s_load_dwordx8 s[48:55], %[code], s80\n"                                                                  \
-  FBG_J16_DISPATCH                                                                                           \
-  FBG_J16_G_REGL(0xC0) FBG_J16_G_REGL(0x30) FBG_J16_G_REGL(0xFC) FBG_J16_G_REGL(0xF3) FBG_J16_G_REGL(0x3C)   \
-  FBG_J16_G_REGL(0xC3) FBG_J16_G_REGL(0x3F) FBG_J16_G_REGL(0xCF) FBG_J16_G_REGL(0x03) FBG_J16_G_REGL(0x0C)   \
-  FBG_J16_G_REGL(0xCC) FBG_J16_G_REGL(0x33)                                                                  \
-  FBG_J16_G_ST_L("", 0) FBG_J16_G_ST_L(FBG_J16_INVOUT_AFTER_VM, 1)                                          \
-  ".p2align 8\n"                                                                                             \
-  "Lc%=:\n"                                                                                                  \
-  FBG_J16_CASE(0)  "s_branch Ld%=\n"                                                                         \
+// The table of cases, an assembler macro emitted twice: fbgtab <label
+// suffix>, <alignment as a power of two>.  Its exit returns to the address
+// in s[84:85].
+#define FBG_J16_TABLE                                                                                        \
+  ".macro fbgtab%= s, a\n"                                                                                   \
+  ".p2align \\a\n"                                                                                           \
+  "Lc%=\\s:\n"                                                                                                \
+  FBG_J16_CASE(0)  "s_branch Ld%=\\s\n"                                                                         \
   FBG_J16_CASE(1)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_NOTCUR) FBG_J16_DISPATCH                                \
   FBG_J16_CASE(2)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_ACCAND) FBG_J16_DISPATCH                                \
   FBG_J16_CASE(3)  FBG_J16_NEXT_S FBG_J16_W16(FBG_J16_ACCANDN) FBG_J16_DISPATCH                               \
@@ -285,11 +281,58 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASES_ORA(FBG_J16_C_ORA, 210)                                                                      \
   FBG_J16_CASES_LIA(FBG_J16_C_LIA_OR, 222)                                                                   \
   FBG_J16_CASES_LIA(FBG_J16_C_LIA_XOR, 234)                                                                  \
-  FBG_J16_CASE(246) "s_branch Ld%=\n" FBG_J16_CASE(247) "s_branch Ld%=\n" FBG_J16_CASE(248) "s_branch Ld%=\n"   \
-  FBG_J16_CASE(249) "s_branch Ld%=\n" FBG_J16_CASE(250) "s_branch Ld%=\n" FBG_J16_CASE(251) "s_branch Ld%=\n"   \
-  FBG_J16_CASE(252) "s_branch Ld%=\n" FBG_J16_CASE(253) "s_branch Ld%=\n" FBG_J16_CASE(254) "s_branch Ld%=\n"   \
+  FBG_J16_CASE(246) "s_branch Ld%=\\s\n" FBG_J16_CASE(247) "s_branch Ld%=\\s\n" FBG_J16_CASE(248) "s_branch Ld%=\\s\n"   \
+  FBG_J16_CASE(249) "s_branch Ld%=\\s\n" FBG_J16_CASE(250) "s_branch Ld%=\\s\n" FBG_J16_CASE(251) "s_branch Ld%=\\s\n"   \
+  FBG_J16_CASE(252) "s_branch Ld%=\\s\n" FBG_J16_CASE(253) "s_branch Ld%=\\s\n" FBG_J16_CASE(254) "s_branch Ld%=\\s\n"   \
   FBG_J16_CASE(255)                                                                                          \
-  "Ld%=:\n"                                                                                                  \
+  "Ld%=\\s:\n"                                                                                                \
+  "s_setpc_b64 s[84:85]\n"                                                                                   \
+  FBG_J16_G_REGL(0xC0) FBG_J16_G_REGL(0x30) FBG_J16_G_REGL(0xFC) FBG_J16_G_REGL(0xF3) FBG_J16_G_REGL(0x3C)   \
+  FBG_J16_G_REGL(0xC3) FBG_J16_G_REGL(0x3F) FBG_J16_G_REGL(0xCF) FBG_J16_G_REGL(0x03) FBG_J16_G_REGL(0x0C)   \
+  FBG_J16_G_REGL(0xCC) FBG_J16_G_REGL(0x33)                                                                  \
+  FBG_J16_G_ST_L("", 0) FBG_J16_G_ST_L(FBG_J16_INVOUT_AFTER_VM, 1)                                          \
+  ".endm\n"
+
+// The interpreter: return address into s[84:85]; the first instruction's
+// fetch; then into the table on its 64 KiB boundary (copy A) or, should the
+// code object not have been loaded on such a boundary or %[any] ask for it,
+// into copy B with the longer dispatch.  Both copies sit in a section of their own, so that the
+// compiler's branches around this statement do not span them.
+#define FBG_J16_PROGRAM                                                                                      \
+  "s_mov_b32 s83, m0\n"                                                                                      \
+  "s_getpc_b64 s[84:85]\n"                                                                                   \
+  "Lr%=:\n"                                                                                                  \
+  "s_add_u32 s84, s84, Lret%=-Lr%=\n"                                                                        \
+  "s_addc_u32 s85, s85, 0\n"                                                                                 \
+  "s_mov_b32 s80, 0\n"                                                                                       \
+  "s_load_dwordx8 s[48:55], %[code], s80\n"                                                                  \
+  "s_cmp_lg_u32 %[any], 0\n"                                                                                \
+  "s_cbranch_scc1 Lany%=\n"                                                                                  \
+  "s_getpc_b64 s[76:77]\n"                                                                                   \
+  "s_add_u32 s76, s76, Lc%=A@rel32@lo+4\n"                                                                   \
+  "s_addc_u32 s77, s77, Lc%=A@rel32@hi+12\n"                                                                 \
+  "s_and_b32 s72, s76, 0xffff\n"                                                                             \
+  "s_cmp_lg_u32 s72, 0\n"                                                                                    \
+  "s_cbranch_scc1 Lany%=\n"                                                                                  \
+  "s_mov_b32 s79, s77\n"                                                                                     \
+  "s_lshr_b32 s77, s76, 16\n"                                                                                \
+  FBG_J16_DISPATCH_ALIGNED                                                                                   \
+  "Lany%=:\n"                                                                                                \
+  "s_getpc_b64 s[76:77]\n"                                                                                   \
+  "s_add_u32 s76, s76, Lc%=B@rel32@lo+4\n"                                                                   \
+  "s_addc_u32 s77, s77, Lc%=B@rel32@hi+12\n"                                                                 \
+  FBG_J16_DISPATCH_ANY                                                                                       \
+  ".pushsection .text.fbg_j16, \"ax\", @progbits\n"                                                          \
+  FBG_J16_TABLE                                                                                              \
+  ".macro fbgdisp%=\n" FBG_J16_DISPATCH_ALIGNED ".endm\n"                                                    \
+  "fbgtab%= A, 16\n"                                                                                         \
+  ".purgem fbgdisp%=\n"                                                                                      \
+  ".macro fbgdisp%=\n" FBG_J16_DISPATCH_ANY ".endm\n"                                                        \
+  "fbgtab%= B, 8\n"                                                                                          \
+  ".purgem fbgdisp%=\n"                                                                                      \
+  ".purgem fbgtab%=\n"                                                                                       \
+  ".popsection\n"                                                                                            \
+  "Lret%=:\n"                                                                                                \
   "s_mov_b32 m0, s83\n"
 // clang-format on
 
@@ -306,9 +349,10 @@ static_assert(FBG_J16_NCASES == 246 && FBG_J16_SLOT == 256 && FBG_J16_XYF_OR == 
 // 3 on sit at byte offset 4096 (r - 3): below `lds_bytes` in LDS, at
 // `lds_lane` (this wave's LDS block + 64 lane); from `lds_bytes` on in global
 // memory, at `gbase` (this wave's block) + offset - lds_bytes + 64 lane.
+// `any` non-zero runs copy B of the table (both copies compute the same).
 __device__ __forceinline__ void run_general_j16(const uint32_t *code, const uint32_t *table, uint64_t U0,
                                                 uint32_t lds_lane, uint32_t lds_bytes, uint32_t *gbase,
-                                                uint32_t lane, uint32_t (&acc)[16]) {
+                                                uint32_t lane, uint32_t (&acc)[16], uint32_t any) {
   j16_u32x16 a;
 #pragma unroll
   for (int i = 0; i < 16; i++) a[i] = acc[i];
@@ -320,10 +364,10 @@ __device__ __forceinline__ void run_general_j16(const uint32_t *code, const uint
                : "+{v[96:111]}"(a), "=&{v[16:31]}"(d0), "=&{v[32:47]}"(d1), "=&{v[48:63]}"(d2),
                  "=&{v[64:79]}"(d3), "=&{v[80:95]}"(d4), "=&{v[14:15]}"(d6)
                : [code] "s"(c), [tab] "s"(t), [u0] "s"(U0), [lb] "v"(lds_lane), [ldsb] "s"(lds_bytes),
-                 [gb] "s"(g), [l64] "v"(l64)
+                 [gb] "s"(g), [l64] "v"(l64), [any] "s"(any)
                : "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58", "s59", "s60", "s61",
                  "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75",
-                 "s76", "s77", "s78", "s79", "s80", "s81", "s83", "scc", "memory");
+                 "s76", "s77", "s78", "s79", "s80", "s81", "s83", "s84", "s85", "scc", "memory");
 #pragma unroll
   for (int i = 0; i < 16; i++) acc[i] = a[i];
 }

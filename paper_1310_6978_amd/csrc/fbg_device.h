@@ -434,7 +434,8 @@ template <int LOG2W, bool GEN>
 __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g, uint32_t nins, uint64_t U0,
                                             uint32_t lane, uint32_t (&acc)[1 << LOG2W],
                                             GenState<1 << LOG2W> &st, uint32_t *__restrict__ regs,
-                                            uint32_t lds_bytes = 0, uint32_t *gregs = nullptr) {
+                                            uint32_t lds_bytes = 0, uint32_t *gregs = nullptr,
+                                            uint32_t j16_any = 0) {
   const code_ptr cb = (code_ptr)code_g;
   const code_ptr ins = cb + cb[0];
   const code_ptr table = ins + FBG_TABLE_OFFSET(nins, LOG2W);
@@ -458,7 +459,7 @@ __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g,
     const uint32_t lds_lane =
         (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint32_t *)regs) + lane * 64u;
     run_general_j16((const uint32_t *)(uintptr_t)ins, (const uint32_t *)(uintptr_t)table, U0, lds_lane, lds_bytes,
-                    gregs, lane, acc);
+                    gregs, lane, acc, j16_any);
   } else {
     run_general<LOG2W>(ins, table, nins, U0, lane, acc, st, regs);
   }
@@ -655,7 +656,8 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
       return;
     }
     if (alive) {
-      run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, st, regs, a.nregs * (W * 256u));
+      run_program<LOG2W, (VAR & 1) != 0>(a.code, a.nins, U0, lane, acc, st, regs, a.nregs * (W * 256u), nullptr,
+                                         a.j16_any);
       mask_tail<LOG2W>(acc, U0, lane, a.nslices, a.n);
     } else {
 #pragma unroll
@@ -752,7 +754,8 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_batch(BatchArgs 
       const uint64_t U0 = t << LOG2W;
       uint32_t acc[W];
       if (alive) {
-        run_program<LOG2W, (VAR & 1) != 0>(p->code, p->nins, U0, lane, acc, st, regs, a.max_regs * (W * 256u), gregs);
+        run_program<LOG2W, (VAR & 1) != 0>(p->code, p->nins, U0, lane, acc, st, regs, a.max_regs * (W * 256u), gregs,
+                                           a.j16_any);
       } else {
 #pragma unroll
         for (int i = 0; i < W; i++) acc[i] = 0u;

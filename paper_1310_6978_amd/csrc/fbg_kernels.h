@@ -32,6 +32,9 @@ struct EvalArgs {
   const uint64_t *tile_offsets;  // MODE_ENUM
   uint64_t *out_idx;      // MODE_ENUM
   uint64_t capacity;      // MODE_ENUM
+  // non-zero: the jump-table interpreter (16 words per lane) runs the copy of
+  // its table for code off a 64 KiB boundary (same results; for tests)
+  uint32_t j16_any = 0;
 };
 
 // The XCD-local layout of the batched DNF write-out (32 words per lane, a
@@ -115,6 +118,7 @@ struct BatchArgs {
   // gstride words of global scratch per wave of the grid, or none
   uint32_t *gscratch = nullptr;
   uint64_t gstride = 0;
+  uint32_t j16_any = 0;   // as in EvalArgs
 };
 
 enum { EVAL_COUNT = 0, EVAL_DNF = 1, EVAL_TILECNT = 2, EVAL_ENUM = 3 };

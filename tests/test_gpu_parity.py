@@ -522,6 +522,30 @@ def test_batch_registers_in_global_scratch(F, k):
     b.free()
 
 
+def test_jump_table_copy_for_any_load_address(F, monkeypatch):
+    """The interpreter at 16 words per lane keeps a second copy of its jump
+    table for code loaded off a 64 KiB boundary; FBG_J16_TABLE=any makes every
+    launch use it.  Its results are the oracle's: random DAGs (every case of
+    the table), registers in LDS and in global scratch, alone and batched."""
+    import torch
+    monkeypatch.setenv("FBG_J16_TABLE", "any")
+    rng = random.Random(6100)
+    texts = [workloads.random_dag(n, rng.randrange(300, 2000), 61 + n) for n in (12, 16, 19)]
+    texts += [(many_registers(rng, n, 17), n) for n in (12, 17)]
+    for text, n in texts:
+        full_check(F, text, n, wpls=[16])
+    progs = [F.Program(t, n) for t, n in texts]
+    want = [oracle.count(t, n) for t, n in texts]
+    b = F.Batch(progs, words_per_lane=16)
+    assert host(b.count()).tolist() == want
+    assert host(b.count(graph=True)).tolist() == want
+    b.free()
+    monkeypatch.delenv("FBG_J16_TABLE")
+    # and back on the aligned copy
+    assert host(F.count_batch(progs, words_per_lane=16)).tolist() == want
+    torch.cuda.synchronize()
+
+
 def test_batch_enumerate_lists_every_program(F):
     import torch
     rng = random.Random(91)
