@@ -85,16 +85,33 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 #define FBG_J16_T_XOR                          \
   "s_and_b64 s[72:73], %[u0], s[52:53]\n"      \
   "s_bcnt1_i32_b64 s72, s[72:73]\n"            \
-  "s_and_b32 s72, s72, 1\n"                    \
-  "s_sub_i32 s72, 0, s72\n"                    \
+  "s_bfe_i32 s72, s72, 0x10000\n"              \
   "s_xor_b32 s72, s72, s49\n"                  \
   "v_cndmask_b32_e64 v14, 0, -1, s[50:51]\n"   \
   "v_xor_b32 v14, s72, v14\n"
+// A set without word literals needs no VGPR for T: v14 holds its lane part
+// (all-ones or zero per lane) and s73 the rest, so that T = v14 | s73
+// (OR-sets: s73 = all-ones when a tile literal holds, else mconst) or
+// T = v14 ^ s73 (XOR-sets: s73 = mconst XOR the parity of the tile
+// literals).  The cases' tables fold that OR or XOR in, and every word still
+// takes one v_bitop3_b32 over (cur, v14, s73): one VALU instruction less per
+// set than forming T, and no scalar one more.
+#define FBG_J16_M_OR                           \
+  "s_and_b64 s[72:73], %[u0], s[52:53]\n"      \
+  "s_cmp_lg_u64 s[72:73], s[54:55]\n"          \
+  "s_cselect_b32 s73, -1, s49\n"               \
+  "v_cndmask_b32_e64 v14, 0, -1, s[50:51]\n"
+#define FBG_J16_M_XOR                          \
+  "s_and_b64 s[72:73], %[u0], s[52:53]\n"      \
+  "s_bcnt1_i32_b64 s73, s[72:73]\n"            \
+  "s_bfe_i32 s73, s73, 0x10000\n"              \
+  "s_xor_b32 s73, s73, s49\n"                  \
+  "v_cndmask_b32_e64 v14, 0, -1, s[50:51]\n"
 // Load the set's 16 pattern words (issued before T is formed).
 #define FBG_J16_PLOAD "s_lshr_b32 s81, s48, 16\n" "s_load_dwordx16 s[56:71], %[tab], s81\n"
 
 // Case bodies parameterised by a truth table TT.
-#define FBG_J16_LITNP_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v14, 0 bitop3:" TT "\n"
+#define FBG_J16_LITM_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v14, s73 bitop3:" TT "\n"
 #define FBG_J16_LITP_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v14, s[56+" #i "] bitop3:" TT "\n"
 #define FBG_J16_REGV_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v[32+" #i "], 0 bitop3:" TT "\n"
 #define FBG_J16_REGL_W(i, TT) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v[80+" #i "], 0 bitop3:" TT "\n"
@@ -102,9 +119,10 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   M(0, TT) M(1, TT) M(2, TT) M(3, TT) M(4, TT) M(5, TT) M(6, TT) M(7, TT) M(8, TT) M(9, TT) M(10, TT) \
   M(11, TT) M(12, TT) M(13, TT) M(14, TT) M(15, TT)
 
-// literal set without word literals: T, fetch, 16 x v_bitop3(cur, T, 0)
-#define FBG_J16_C_LITOR(TT) FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
-#define FBG_J16_C_LITXOR(TT) FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITNP_W, #TT) FBG_J16_DISPATCH
+// literal set without word literals: lane part, fetch, 16 x v_bitop3(cur,
+// v14, s73)
+#define FBG_J16_C_LITOR(TT) FBG_J16_M_OR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITM_W, #TT) FBG_J16_DISPATCH
+#define FBG_J16_C_LITXOR(TT) FBG_J16_M_XOR FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITM_W, #TT) FBG_J16_DISPATCH
 // with word literals: the pattern words come in with the next instruction
 #define FBG_J16_C_LITORP(TT) \
   FBG_J16_PLOAD FBG_J16_T_OR "s_waitcnt lgkmcnt(0)\n" FBG_J16_NEXT_L FBG_J16_EACH(FBG_J16_LITP_W, #TT) FBG_J16_DISPATCH
@@ -144,17 +162,19 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 // chains (fbg_isa.h): the first set sets X and Y from cur = all-ones and cur
 // = zero, each further set updates them, and the last one then applies them
 // to the words: cur = (cur & X) | (~cur & Y)
-#define FBG_J16_XYF(TT) "v_bitop3_b32 v80, -1, v14, 0 bitop3:" TT "\n" "v_bitop3_b32 v81, 0, v14, 0 bitop3:" TT "\n"
-#define FBG_J16_XYM(TT) "v_bitop3_b32 v80, v80, v14, 0 bitop3:" TT "\n" "v_bitop3_b32 v81, v81, v14, 0 bitop3:" TT "\n"
-#define FBG_J16_C_XYF_OR(TT) FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_XYF(#TT) FBG_J16_DISPATCH
-#define FBG_J16_C_XYF_XOR(TT) FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_XYF(#TT) FBG_J16_DISPATCH
-#define FBG_J16_C_XYM_OR(TT) FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_DISPATCH
-#define FBG_J16_C_XYM_XOR(TT) FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_DISPATCH
+#define FBG_J16_XYF(TT) \
+  "v_bitop3_b32 v80, -1, v14, s73 bitop3:" TT "\n" "v_bitop3_b32 v81, 0, v14, s73 bitop3:" TT "\n"
+#define FBG_J16_XYM(TT) \
+  "v_bitop3_b32 v80, v80, v14, s73 bitop3:" TT "\n" "v_bitop3_b32 v81, v81, v14, s73 bitop3:" TT "\n"
+#define FBG_J16_C_XYF_OR(TT) FBG_J16_M_OR FBG_J16_NEXT_L FBG_J16_XYF(#TT) FBG_J16_DISPATCH
+#define FBG_J16_C_XYF_XOR(TT) FBG_J16_M_XOR FBG_J16_NEXT_L FBG_J16_XYF(#TT) FBG_J16_DISPATCH
+#define FBG_J16_C_XYM_OR(TT) FBG_J16_M_OR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_DISPATCH
+#define FBG_J16_C_XYM_XOR(TT) FBG_J16_M_XOR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_DISPATCH
 #define FBG_J16_XYAPPLY(i) "v_bitop3_b32 v[16+" #i "], v[16+" #i "], v80, v81 bitop3:0xca\n"
 #define FBG_J16_C_XYL_OR(TT) \
-  FBG_J16_T_OR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_W16(FBG_J16_XYAPPLY) FBG_J16_DISPATCH
+  FBG_J16_M_OR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_W16(FBG_J16_XYAPPLY) FBG_J16_DISPATCH
 #define FBG_J16_C_XYL_XOR(TT) \
-  FBG_J16_T_XOR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_W16(FBG_J16_XYAPPLY) FBG_J16_DISPATCH
+  FBG_J16_M_XOR FBG_J16_NEXT_L FBG_J16_XYM(#TT) FBG_J16_W16(FBG_J16_XYAPPLY) FBG_J16_DISPATCH
 
 // merged stores (fbg_isa.h): ORS writes the operation's result into the
 // register it reads (index mode on the second source and the destination);
@@ -168,16 +188,16 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
 #define FBG_J16_XYS_TAIL(TT)                                                                            \
   FBG_J16_XYM(TT) "s_lshr_b32 s72, s48, 16\n" "s_set_gpr_idx_on s72, gpr_idx(DST)\n" FBG_J16_NEXT_L \
   "s_nop 1\n" FBG_J16_W16(FBG_J16_XYSTORE) "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
-#define FBG_J16_C_XYS_OR(TT) FBG_J16_T_OR FBG_J16_XYS_TAIL(#TT)
-#define FBG_J16_C_XYS_XOR(TT) FBG_J16_T_XOR FBG_J16_XYS_TAIL(#TT)
+#define FBG_J16_C_XYS_OR(TT) FBG_J16_M_OR FBG_J16_XYS_TAIL(#TT)
+#define FBG_J16_C_XYS_XOR(TT) FBG_J16_M_XOR FBG_J16_XYS_TAIL(#TT)
 // LIS: a literal set's operation, its result into R[r] (index mode on the
 // destination)
-#define FBG_J16_LIS_W(i, TT) "v_bitop3_b32 v[32+" #i "], v[16+" #i "], v14, 0 bitop3:" TT "\n"
+#define FBG_J16_LIS_W(i, TT) "v_bitop3_b32 v[32+" #i "], v[16+" #i "], v14, s73 bitop3:" TT "\n"
 #define FBG_J16_LIS_TAIL(TT)                                                                          \
   "s_lshr_b32 s72, s48, 16\n" "s_set_gpr_idx_on s72, gpr_idx(DST)\n" FBG_J16_NEXT_L "s_nop 1\n" \
   FBG_J16_EACH(FBG_J16_LIS_W, TT) "s_set_gpr_idx_off\n" FBG_J16_DISPATCH
-#define FBG_J16_C_LIS_OR(TT) FBG_J16_T_OR FBG_J16_LIS_TAIL(#TT)
-#define FBG_J16_C_LIS_XOR(TT) FBG_J16_T_XOR FBG_J16_LIS_TAIL(#TT)
+#define FBG_J16_C_LIS_OR(TT) FBG_J16_M_OR FBG_J16_LIS_TAIL(#TT)
+#define FBG_J16_C_LIS_XOR(TT) FBG_J16_M_XOR FBG_J16_LIS_TAIL(#TT)
 // merged ACC (fbg_isa.h): acc = tt(acc, cur, R[r]) with index mode on the
 // third source, or acc = tt(acc, cur, T)
 #define FBG_J16_ORA_W(i, TT) "v_bitop3_b32 v[96+" #i "], v[96+" #i "], v[16+" #i "], v[32+" #i "] bitop3:" TT "\n"
@@ -218,16 +238,46 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASE(BASE + 3) MAC(0xF3) FBG_J16_CASE(BASE + 4) MAC(0x3C) FBG_J16_CASE(BASE + 5) MAC(0xC3)        \
   FBG_J16_CASE(BASE + 6) MAC(0x3F) FBG_J16_CASE(BASE + 7) MAC(0xCF) FBG_J16_CASE(BASE + 8) MAC(0x03)        \
   FBG_J16_CASE(BASE + 9) MAC(0x0C) FBG_J16_CASE(BASE + 10) MAC(0xCC) FBG_J16_CASE(BASE + 11) MAC(0x33)
-#define FBG_J16_CASES_NP(MAC, BASE)                                                                          \
-  FBG_J16_CASE(BASE + 0) MAC(0x44) FBG_J16_CASE(BASE + 1) MAC(0x11) FBG_J16_CASE(BASE + 2) MAC(0x40)        \
-  FBG_J16_CASE(BASE + 3) MAC(0x10) FBG_J16_CASE(BASE + 4) MAC(0x15) FBG_J16_CASE(BASE + 5) MAC(0x45)        \
-  FBG_J16_CASE(BASE + 6) MAC(0x54) FBG_J16_CASE(BASE + 7) MAC(0x51) FBG_J16_CASE(BASE + 8) MAC(0x01)        \
-  FBG_J16_CASE(BASE + 9) MAC(0x04) FBG_J16_CASE(BASE + 10) MAC(0x14) FBG_J16_CASE(BASE + 11) MAC(0x41)
-#define FBG_J16_CASES_ORP(MAC, BASE)                                                                         \
-  FBG_J16_CASE(BASE + 0) MAC(0xEE) FBG_J16_CASE(BASE + 1) MAC(0x11) FBG_J16_CASE(BASE + 2) MAC(0xE0)        \
-  FBG_J16_CASE(BASE + 3) MAC(0x10) FBG_J16_CASE(BASE + 4) MAC(0x1F) FBG_J16_CASE(BASE + 5) MAC(0xEF)        \
-  FBG_J16_CASE(BASE + 6) MAC(0xFE) FBG_J16_CASE(BASE + 7) MAC(0xF1) FBG_J16_CASE(BASE + 8) MAC(0x01)        \
-  FBG_J16_CASE(BASE + 9) MAC(0x0E) FBG_J16_CASE(BASE + 10) MAC(0x1E) FBG_J16_CASE(BASE + 11) MAC(0xE1)
+// Twelve cases from a list of twelve tables (FBG_J16_APPLY splits the list
+// into arguments).
+#define FBG_J16_APPLY(M, ARGS) M ARGS
+#define FBG_J16_CASES12(MAC, B, t0, t1, t2, t3, t4, t5, t6, t7, t8, t9, t10, t11)                          \
+  FBG_J16_CASE(B + 0) MAC(t0) FBG_J16_CASE(B + 1) MAC(t1) FBG_J16_CASE(B + 2) MAC(t2)                       \
+  FBG_J16_CASE(B + 3) MAC(t3) FBG_J16_CASE(B + 4) MAC(t4) FBG_J16_CASE(B + 5) MAC(t5)                       \
+  FBG_J16_CASE(B + 6) MAC(t6) FBG_J16_CASE(B + 7) MAC(t7) FBG_J16_CASE(B + 8) MAC(t8)                       \
+  FBG_J16_CASE(B + 9) MAC(t9) FBG_J16_CASE(B + 10) MAC(t10) FBG_J16_CASE(B + 11) MAC(t11)
+// The tables of the sets without word literals (FBG_J16_NP_TABLES, over
+// cur and T) with T = v14 | s73 (ORT) or T = v14 ^ s73 (XORT) folded in, in
+// the same order; the ORT tables are also those of the OR-sets with word
+// literals (their P is OR-ed into T).  Checked below.
+#define FBG_J16_ORT_LIST 0xEE, 0x11, 0xE0, 0x10, 0x1F, 0xEF, 0xFE, 0xF1, 0x01, 0x0E, 0x1E, 0xE1
+#define FBG_J16_XORT_LIST 0x66, 0x99, 0x60, 0x90, 0x9F, 0x6F, 0xF6, 0xF9, 0x09, 0x06, 0x96, 0x69
+#define FBG_J16_CASES_ORT(MAC, BASE) FBG_J16_APPLY(FBG_J16_CASES12, (MAC, BASE, FBG_J16_ORT_LIST))
+#define FBG_J16_CASES_XORT(MAC, BASE) FBG_J16_APPLY(FBG_J16_CASES12, (MAC, BASE, FBG_J16_XORT_LIST))
+
+#define FBG_J16_LISTED(t) t,
+constexpr uint32_t kJ16NpTables[] = {FBG_J16_NP_TABLES(FBG_J16_LISTED)};
+constexpr uint32_t kJ16OrtTables[] = {FBG_J16_ORT_LIST};
+constexpr uint32_t kJ16XortTables[] = {FBG_J16_XORT_LIST};
+// tt over (a, b, c) = (0xF0, 0xCC, 0xAA) as tt0(a, b OP c, 0)
+constexpr uint32_t j16_fold(uint32_t tt0, bool is_xor) {
+  uint32_t r = 0;
+  for (uint32_t x = 0; x < 8; x++) {
+    const uint32_t a = x >> 2, b = (x >> 1) & 1u, c = x & 1u;
+    const uint32_t t = is_xor ? (b ^ c) : (b | c);
+    r |= ((tt0 >> ((a << 2) | (t << 1))) & 1u) << x;
+  }
+  return r;
+}
+constexpr bool j16_folded_tables_agree() {
+  for (int k = 0; k < 12; k++)
+    if (j16_fold(kJ16NpTables[k], false) != kJ16OrtTables[k] || j16_fold(kJ16NpTables[k], true) != kJ16XortTables[k])
+      return false;
+  return true;
+}
+static_assert(sizeof kJ16NpTables / sizeof kJ16NpTables[0] == 12 && j16_folded_tables_agree(),
+              "ORT / XORT tables are the NP tables with the lane part and s73 folded in");
+
 #define FBG_J16_CASES_ORA(MAC, BASE)                                                                         \
   FBG_J16_CASE(BASE + 0) MAC(0x80) FBG_J16_CASE(BASE + 1) MAC(0x40) FBG_J16_CASE(BASE + 2) MAC(0xE0)        \
   FBG_J16_CASE(BASE + 3) MAC(0xD0) FBG_J16_CASE(BASE + 4) MAC(0x60) FBG_J16_CASE(BASE + 5) MAC(0x90)        \
@@ -263,21 +313,21 @@ typedef uint32_t j16_u32x2 __attribute__((ext_vector_type(2)));
   FBG_J16_CASE(9)  FBG_J16_C_ST_L(FBG_J16_INVOUT_AFTER_DS, 1)                                                \
   FBG_J16_CASES_REG(FBG_J16_C_REGV, 10)                                                                      \
   FBG_J16_CASES_REG(FBG_J16_C_REGL, 22)                                                                      \
-  FBG_J16_CASES_NP(FBG_J16_C_LITOR, 34)                                                                      \
-  FBG_J16_CASES_NP(FBG_J16_C_LITXOR, 46)                                                                     \
-  FBG_J16_CASES_ORP(FBG_J16_C_LITORP, 58)                                                                    \
+  FBG_J16_CASES_ORT(FBG_J16_C_LITOR, 34)                                                                      \
+  FBG_J16_CASES_XORT(FBG_J16_C_LITXOR, 46)                                                                     \
+  FBG_J16_CASES_ORT(FBG_J16_C_LITORP, 58)                                                                    \
   FBG_J16_CASES_XORP(FBG_J16_C_LITXORP, 70)                                                                  \
-  FBG_J16_CASES_NP(FBG_J16_C_XYF_OR, 78)                                                                     \
-  FBG_J16_CASES_NP(FBG_J16_C_XYF_XOR, 90)                                                                    \
-  FBG_J16_CASES_NP(FBG_J16_C_XYM_OR, 102)                                                                    \
-  FBG_J16_CASES_NP(FBG_J16_C_XYM_XOR, 114)                                                                   \
-  FBG_J16_CASES_NP(FBG_J16_C_XYL_OR, 126)                                                                    \
-  FBG_J16_CASES_NP(FBG_J16_C_XYL_XOR, 138)                                                                   \
+  FBG_J16_CASES_ORT(FBG_J16_C_XYF_OR, 78)                                                                     \
+  FBG_J16_CASES_XORT(FBG_J16_C_XYF_XOR, 90)                                                                    \
+  FBG_J16_CASES_ORT(FBG_J16_C_XYM_OR, 102)                                                                    \
+  FBG_J16_CASES_XORT(FBG_J16_C_XYM_XOR, 114)                                                                   \
+  FBG_J16_CASES_ORT(FBG_J16_C_XYL_OR, 126)                                                                    \
+  FBG_J16_CASES_XORT(FBG_J16_C_XYL_XOR, 138)                                                                   \
   FBG_J16_CASES_REG(FBG_J16_C_ORS, 150)                                                                      \
-  FBG_J16_CASES_NP(FBG_J16_C_XYS_OR, 162)                                                                    \
-  FBG_J16_CASES_NP(FBG_J16_C_XYS_XOR, 174)                                                                   \
-  FBG_J16_CASES_NP(FBG_J16_C_LIS_OR, 186)                                                                    \
-  FBG_J16_CASES_NP(FBG_J16_C_LIS_XOR, 198)                                                                   \
+  FBG_J16_CASES_ORT(FBG_J16_C_XYS_OR, 162)                                                                    \
+  FBG_J16_CASES_XORT(FBG_J16_C_XYS_XOR, 174)                                                                   \
+  FBG_J16_CASES_ORT(FBG_J16_C_LIS_OR, 186)                                                                    \
+  FBG_J16_CASES_XORT(FBG_J16_C_LIS_XOR, 198)                                                                   \
   FBG_J16_CASES_ORA(FBG_J16_C_ORA, 210)                                                                      \
   FBG_J16_CASES_LIA(FBG_J16_C_LIA_OR, 222)                                                                   \
   FBG_J16_CASES_LIA(FBG_J16_C_LIA_XOR, 234)                                                                  \
