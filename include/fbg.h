@@ -213,10 +213,11 @@ fbg_status fbg_program_set_tuning(fbg_program *p, const fbg_tune *tune);
  *   d_out      device pointer, caller-owned, 8-byte aligned.
  *   out_words  capacity of d_out in words; must be >= max(1, 2^(n-6)).
  * n <= FBG_MAX_DNF_VARS.  A program made only of clauses with n >= 21, at 32
- * words per lane without the cofactor, is evaluated in a second encoding
- * whose tiles are pairs of 4 KiB pieces of d, each block of waves writing the
- * pieces of one residue class modulo 8 (one per XCD); the result is the same
- * vector, and it is written fastest when d_out is 32 KiB aligned.
+ * words per lane without the cofactor, into a d_out 16 bytes aligned, is
+ * evaluated in a second encoding whose tiles are pairs of 4 KiB pieces of d
+ * written as 16-byte groups, each block of waves writing the pieces of one
+ * residue class modulo 8 (one per XCD); the result is the same vector, and
+ * it is written fastest when d_out is 32 KiB aligned.
  */
 fbg_status fbg_eval_dnf(const fbg_program *p, uint64_t *d_out, uint64_t out_words, void *stream);
 

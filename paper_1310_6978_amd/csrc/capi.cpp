@@ -459,7 +459,7 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
     total += p->words[l].size();
   }
   if (!p->general() && p->c.n >= fbg::kXcdMinVars && p->has_tiling(5)) {
-    const fbg::Compiled x = fbg::exchange_variables(p->c, fbg::kXcdSwapA, fbg::kXcdSwapB, fbg::kXcdSwapLen);
+    const fbg::Compiled x = fbg::permute_variables(p->c, fbg::xcd_write_out_permutation(p->c.n));
     const uint32_t nx = fbg::encode_program(x, 5, p->words_xcd, &enc_err);
     if (nx != p->nins[5] && enc_err.empty()) enc_err = "internal: exchanged encoding differs in length";
     p->dev_off_xcd = total;
@@ -645,7 +645,8 @@ fbg_status fbg_eval_dnf_tuned(const fbg_program *p, uint64_t *d_out, uint64_t ou
   a.out32 = (uint32_t *)d_out;
   a.out_slices = 2 * need;
   // the XCD-local layout (fbg_kernels.h) on the grid of one tile per wave
-  if (g.log2w == 5 && p->has_xcd && p->variant(tune) == 0) a.xcd_code = p->d_code + p->dev_off_xcd;
+  if (g.log2w == 5 && p->has_xcd && p->variant(tune) == 0 && ((uintptr_t)d_out & 15) == 0)
+    a.xcd_code = p->d_code + p->dev_off_xcd;
   hipError_t e =
       fbg::launch_eval(fbg::EVAL_DNF, g.log2w, p->variant(tune), a, g.grid, g.block, g.lds, (hipStream_t)stream);
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of the DNF kernel");
@@ -1014,6 +1015,9 @@ fbg_status fbg_batch_set_dnf_outputs(fbg_batch *b, uint64_t *const *d_outs, cons
                   (unsigned long long)need);
     q.out32 = (uint32_t *)d_outs[i];
     q.out_slices = 2 * need;
+    // the XCD-local layout writes 16-byte groups: other outputs take the
+    // plain one
+    if ((uintptr_t)q.out32 & 15) q.xcd_code = nullptr;
     if (!b->host_dnf.empty()) {
       q.tile_counts = b->host_dnf[(size_t)i].tile_counts;
       q.chunk_counts = b->host_dnf[(size_t)i].chunk_counts;

@@ -1473,16 +1473,25 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
   return per_tile / W;
 }
 
-Compiled exchange_variables(const Compiled &c, int a, int b, int len) {
+Compiled permute_variables(const Compiled &c, const std::vector<int> &to) {
   Compiled r = c;
   for (HIns &h : r.code)
-    for (Lit &l : h.ls.lits) {
-      if (l.k >= a && l.k < a + len)
-        l.k += b - a;
-      else if (l.k >= b && l.k < b + len)
-        l.k -= b - a;
-    }
+    for (Lit &l : h.ls.lits) l.k = to[(size_t)l.k];
   return r;
+}
+
+std::vector<int> xcd_write_out_permutation(int n) {
+  // Word-index bits of the kernel's (tile t, word i, lane l), as
+  // (t << 11) | (i << 6) | l, and the bits of the DNF word they address:
+  //   l0..l5 -> 2..7    i0, i1 -> 0, 1    i2, i3 -> 8, 9    i4 -> 13
+  //   t0, t1 -> 14, 15  t2..t4 -> 10..12  t5.. -> 16..
+  // Variable 5 + b of the formula (DNF word bit b) becomes variable 5 + k
+  // of the program, k the kernel bit that lands on b.
+  static const int kernel_bit_of[16] = {6, 7, 0, 1, 2, 3, 4, 5, 8, 9, 13, 14, 15, 10, 11, 12};
+  std::vector<int> to((size_t)n);
+  for (int k = 0; k < n; k++) to[(size_t)k] = k;
+  for (int b = 0; b < 16 && 5 + b < n; b++) to[(size_t)(5 + b)] = 5 + kernel_bit_of[b];
+  return to;
 }
 
 uint32_t leading_clauses(const Compiled &c) {

@@ -465,6 +465,22 @@ __device__ __forceinline__ void run_program(const uint32_t *__restrict__ code_g,
   }
 }
 
+// Store a tile of the XCD-local layout (fbg_kernels.h): the program's
+// renamed variables put the lane's words 4g .. 4g+3 side by side, so each
+// group is one 16-byte store to 1 KiB unit g & 3 of the tile's piece g >> 2
+// (the second piece 8 pieces, 32 KiB, after the first).  dst = the first
+// piece + 4 lane words, 16-byte aligned.  (Instantiated for every W; called
+// at W = 32 only.)
+template <int W>
+__device__ __forceinline__ void store_xcd_tile(const uint32_t (&acc)[W], uint32_t *dst) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int g = 0; g < W / 4; g++) {
+    const u32x4 v = {acc[4 * g], acc[4 * g + 1], acc[4 * g + 2], acc[4 * g + 3]};
+    __builtin_nontemporal_store(v, (u32x4 *)(dst + (g >> 2) * 8192 + (g & 3) * 256));
+  }
+}
+
 // Zero the words of this lane that lie beyond the valuation space.
 template <int LOG2W>
 __device__ __forceinline__ void mask_tail(uint32_t (&acc)[1 << LOG2W], uint64_t U0, uint32_t lane,
@@ -648,11 +664,10 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
     }
     uint32_t acc[W];
     if (LOG2W == 5 && VAR == 0 && MODE == MODE_DNF && a.xcd_code) {
-      // XCD-local layout (fbg_kernels.h): full tiles only (n >= 21)
+      // XCD-local layout (fbg_kernels.h): full tiles only (n >= 21), output
+      // 16-byte aligned
       run_program<LOG2W, false>(a.xcd_code, a.nins, U0, lane, acc, st, regs);
-      uint32_t *dst = a.out32 + (((t >> 2) & 7) + 16 * (t & 3) + 64 * (t >> 5)) * 1024 + lane;
-#pragma unroll
-      for (int i = 0; i < W; i++) __builtin_nontemporal_store(acc[i], dst + (i >> 4) * 8192 + (i & 15) * 64);
+      store_xcd_tile(acc, a.out32 + (((t >> 2) & 7) + 16 * (t & 3) + 64 * (t >> 5)) * 1024 + lane * 4);
       return;
     }
     if (alive) {
@@ -842,11 +857,10 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
       // only (n >= 21)
       run_program<LOG2W, false>(p->xcd_code, p->nins, U0, lane, acc, st, nullptr);
       const uint64_t piece = ((t >> 2) & 7) + 16 * (t & 3) + 64 * (t >> 5);
-      uint32_t *dst = p->out32 + piece * 1024 + lane;
+      store_xcd_tile(acc, p->out32 + piece * 1024 + lane * 4);
       uint32_t c0 = 0, c1 = 0;
 #pragma unroll
       for (int i = 0; i < W; i++) {
-        __builtin_nontemporal_store(acc[i], dst + (i >> 4) * 8192 + (i & 15) * 64);
         if (i < 16)
           c0 += __popc(acc[i]);
         else

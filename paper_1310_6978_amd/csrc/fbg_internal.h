@@ -61,10 +61,18 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
 // Number of leading clause (CL) instructions; no CL follows them.
 uint32_t leading_clauses(const Compiled &c);
 
-// The same program with variables a .. a+len-1 and b .. b+len-1 exchanged
-// (the two ranges disjoint): evaluated at index k it gives the original's
-// value at k with those two bit fields exchanged.
-Compiled exchange_variables(const Compiled &c, int a, int b, int len);
+// The same program with its variables renamed: variable k becomes to[k]
+// (to a permutation of 0 .. n-1).  Evaluated at index j it gives the
+// original's value at the index whose bit k is bit to[k] of j.
+Compiled permute_variables(const Compiled &c, const std::vector<int> &to);
+
+// The renaming behind the XCD-local DNF write-out at 32 words per lane
+// (fbg_kernels.h), for n >= kXcdMinVars: with it, word i of lane l of tile t
+// of the renamed program is the DNF word at index
+//   piece(t, i >> 4) * 1024 + ((i >> 2) & 3) * 256 + 4 l + (i & 3),
+//   piece(t, h) = ((t >> 2) & 7) + 16 (t & 3) + 64 (t >> 5) + 8 h,
+// so that each lane writes its words 4g .. 4g+3 with one 16-byte store.
+std::vector<int> xcd_write_out_permutation(int n);
 
 // VALU instructions per 32-bit slice the evaluator issues for an encoded
 // program (a static count per tile, divided by the words per lane; the

@@ -38,20 +38,21 @@ struct EvalArgs {
 };
 
 // The XCD-local layout of the batched DNF write-out (32 words per lane, a
-// program made of clauses alone, n >= kXcdMinVars).  The write-out kernel
-// evaluates a second encoding of the program whose variables 15..17 and
-// 18..20 are exchanged, so its tile t (64 lanes x 32 words) holds the words
-// of the DNF vector whose word index has bits 10..12 equal to bits 2..4 of t
-// (bits 13..15: word bit 4 and bits 0..1 of t; 0..9: lane and word bits 0..3;
-// 16 and up: bits 5 and up of t).  Such a tile is two whole 4 KiB pieces
-// of the vector, 8 KiB apart, whose piece index is congruent to bits 2..4 of
-// t modulo 8: with one tile per wave and four waves per block, every block
-// (blocks go to the eight XCDs in turn) writes the pieces of one residue
-// class, which HBM absorbs faster than the same bytes in plain order.  The
-// model counts of a tile's two pieces go to chunk_counts[2t], [2t + 1];
-// k_sum_tile_counts adds the two pieces of each 8 KiB tile of the vector
-// into the tile counts the batched enumeration reads.
-constexpr int kXcdSwapA = 15, kXcdSwapB = 18, kXcdSwapLen = 3;
+// program made of clauses alone, n >= kXcdMinVars, an output 16 bytes
+// aligned).  The write-out kernel evaluates a second encoding of the
+// program with its variables renamed (xcd_write_out_permutation), so that
+// its tile t (64 lanes x 32 words) holds two whole 4 KiB pieces of the DNF
+// vector, pieces p and p + 8 (32 KiB apart), p = ((t >> 2) & 7) + 16 (t & 3)
+// + 64 (t >> 5), and each lane's words 4g .. 4g+3 are adjacent in memory:
+// eight 16-byte stores per lane, each a whole 1 KiB of a piece.  With one
+// tile per wave and four waves per block, every block writes 4 KiB pieces of
+// one residue class modulo 8 (blocks go to the eight XCDs in turn), so that
+// the XCDs write interleaved 4 KiB pieces of one region of the vector at a
+// time; HBM takes that faster than the same bytes in plain order or in
+// larger pieces per XCD.  The model counts of a tile's two pieces go to
+// chunk_counts[2t], [2t + 1]; k_sum_tile_counts adds the two pieces of each
+// 8 KiB tile of the vector into the tile counts the batched enumeration
+// reads.
 constexpr int kXcdMinVars = 21;
 
 struct BatchProg {

@@ -8,9 +8,9 @@
 //   "<log2w> <cof> <hex words of the emulated DNF vector>"
 // and walks the listing and the VALU count of every encoding.  For n >= 21
 // it also prints "X <hex words>": the 32-words-per-lane encoding of the
-// program with variables 15..17 and 18..20 exchanged, emulated, and each
-// emulated word put back at the index with word-index bits 10..12 and 13..15
-// exchanged (the layout of the XCD-local DNF write-out).
+// program with the variables renamed for the XCD-local DNF write-out,
+// emulated, and each emulated word (tile t, word i, lane l) put at the index
+// the write-out kernel stores it to.
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -57,15 +57,16 @@ int main() {
       }
     }
     if (c.n >= 21) {
-      const fbg::Compiled x = fbg::exchange_variables(c, 15, 18, 3);
+      const fbg::Compiled x = fbg::permute_variables(c, fbg::xcd_write_out_permutation(c.n));
       std::vector<uint32_t> words;
       std::string err;
       const uint32_t nins = fbg::encode_program(x, 5, words, &err);
       std::vector<uint32_t> em((size_t)slices, 0u), out32((size_t)slices, 0u);
       fbg::emulate_program(words, nins, x.nregs, x.n, 5, false, em.data());
       for (uint64_t s = 0; s < slices; s++) {
-        const uint64_t lo = (s >> 10) & 7, hi = (s >> 13) & 7;
-        out32[(size_t)((s & ~(uint64_t)(63u << 10)) | (lo << 13) | (hi << 10))] = em[(size_t)s];
+        const uint64_t l = s & 63, i = (s >> 6) & 31, t = s >> 11;
+        const uint64_t piece = ((t >> 2) & 7) + 16 * (t & 3) + 64 * (t >> 5) + 8 * (i >> 4);
+        out32[(size_t)(piece * 1024 + ((i >> 2) & 3) * 256 + 4 * l + (i & 3))] = em[(size_t)s];
       }
       printf("X");
       for (uint64_t w = 0; w < words64; w++)

@@ -663,32 +663,33 @@ def test_single_dnf_xcd_local_layout(F, grid):
         p.free()
 
 
-def test_batch_dnf_xcd_local_layout_unaligned_outputs(F):
-    """The XCD-local write-out into output views that start 8 bytes past a
-    32 KiB boundary (correct at any 8-byte alignment; only the speed depends
-    on it), with guard words on both sides left untouched."""
+@pytest.mark.parametrize("skip", [1, 2])
+def test_batch_dnf_xcd_local_layout_unaligned_outputs(F, skip):
+    """The write-out into output views that start 8 bytes (plain layout: the
+    XCD-local one stores 16-byte groups) or 16 bytes (XCD-local layout) past a
+    32 KiB boundary, with guard words on both sides left untouched."""
     import torch
     texts = [workloads.random_3cnf(21, 89, 11), workloads.random_3cnf(22, 94, 12), workloads.random_3cnf(13, 55, 13)]
     progs = [F.Program(t, n) for t, n in texts]
     wants = [oracle.dnf(t, n) for t, n in texts]
-    bufs = [torch.full((F.dnf_words(n) + 2,), -1, dtype=torch.int64, device="cuda") for _, n in texts]
-    views = [b[1:1 + F.dnf_words(n)] for b, (_, n) in zip(bufs, texts)]
+    bufs = [torch.full((F.dnf_words(n) + 2 * skip,), -1, dtype=torch.int64, device="cuda") for _, n in texts]
+    views = [b[skip:skip + F.dnf_words(n)] for b, (_, n) in zip(bufs, texts)]
     b = F.Batch(progs, words_per_lane=32)
     b.set_dnf_outputs(views)
     b.set_enum_outputs([None] * len(progs))
-    print("xcd layout: unaligned outputs", flush=True)
+    print("xcd layout: outputs %d words past a boundary" % skip, flush=True)
     counts = host(b.eval_dnf())
     for w, buf, c in zip(wants, bufs, counts):
         got = host(buf)
-        assert got[0] == np.uint64(2**64 - 1) and got[-1] == np.uint64(2**64 - 1)
-        assert np.array_equal(got[1:1 + len(w)], w)
+        assert (got[:skip] == np.uint64(2**64 - 1)).all() and (got[skip + len(w):] == np.uint64(2**64 - 1)).all()
+        assert np.array_equal(got[skip:skip + len(w)], w)
         assert int(c) == int(np.unpackbits(w.view(np.uint8)).sum())
     for (t, n), w in zip(texts, wants):
-        out = torch.full((F.dnf_words(n) + 2,), -1, dtype=torch.int64, device="cuda")
-        F.eval_dnf(F.Program(t, n), out=out[1:1 + F.dnf_words(n)], words_per_lane=32)
+        out = torch.full((F.dnf_words(n) + 2 * skip,), -1, dtype=torch.int64, device="cuda")
+        F.eval_dnf(F.Program(t, n), out=out[skip:skip + F.dnf_words(n)], words_per_lane=32)
         got = host(out)
-        assert got[0] == np.uint64(2**64 - 1) and got[-1] == np.uint64(2**64 - 1)
-        assert np.array_equal(got[1:1 + len(w)], w)
+        assert (got[:skip] == np.uint64(2**64 - 1)).all() and (got[skip + len(w):] == np.uint64(2**64 - 1)).all()
+        assert np.array_equal(got[skip:skip + len(w)], w)
     b.free()
 
 

@@ -75,11 +75,12 @@ def test_random_formulas_under_sanitizers(driver):
 
 
 def test_exchanged_variables_give_the_xcd_local_layout(driver):
-    """The second encoding of the batched DNF write-out: the program with
-    variables 15..17 and 18..20 exchanged, emulated at 32 words per lane, puts
-    at word index s the DNF word whose index is s with bits 10..12 and 13..15
-    exchanged.  Clause-only formulas (the write-out's programs) and general
-    ones, n = 21 and 22."""
+    """The second encoding of the batched DNF write-out: the program with its
+    variables renamed, emulated at 32 words per lane, and each word (tile t,
+    word i, lane l) put where the write-out kernel stores it (piece p(t) or
+    p(t) + 8 by i >> 4, 1 KiB unit (i >> 2) & 3, 16-byte group of lane l,
+    word i & 3) gives the DNF vector.  Clause-only formulas (the write-out's
+    programs) and general ones, n = 21 and 22."""
     rng = random.Random(2101)
     cases = [workloads.random_3cnf(21, 89, 4), workloads.random_3cnf(22, 94, 5),
              (random_cnf(rng, 22, 60), 22), (random_program(rng, 21)[1], 21)]
