@@ -15,6 +15,8 @@
 //     emitted code.
 #include <pthread.h>
 #include <string.h>
+#include <sys/mman.h>
+#include <ucontext.h>
 
 #include <algorithm>
 #include <array>
@@ -47,9 +49,15 @@ constexpr Edge kFalse = 0, kTrue = 1;
 struct Graph {
   std::vector<GNode> nodes;
   std::unordered_map<uint64_t, uint32_t> table;
-  std::unordered_map<int, uint32_t> vars;
+  std::vector<uint32_t> vars;  // node of variable k, 0 if none yet
 
   Graph() { nodes.push_back({NK_CONST, 0, 0}); }
+
+  // room for about m nodes without rehashing
+  void reserve(size_t m) {
+    nodes.reserve(m + 1);
+    table.reserve(m);
+  }
 
   uint32_t node_of(uint8_t kind, uint32_t a, uint32_t b) {
     uint64_t key = ((uint64_t)kind << 62) ^ ((uint64_t)a << 31) ^ (uint64_t)b;
@@ -68,10 +76,10 @@ struct Graph {
   }
 
   Edge var(int k) {
-    auto it = vars.find(k);
-    if (it != vars.end()) return it->second << 1;
-    uint32_t id = node_of(NK_VAR, (uint32_t)k, 0);
-    vars.emplace(k, id);
+    if ((size_t)k >= vars.size()) vars.resize((size_t)k + 1, 0u);
+    if (vars[(size_t)k]) return vars[(size_t)k] << 1;
+    const uint32_t id = node_of(NK_VAR, (uint32_t)k, 0);
+    vars[(size_t)k] = id;
     return id << 1;
   }
 
@@ -135,6 +143,7 @@ struct Parser {
   }
 
   bool lex() {
+    toks.reserve(strlen(src) / 2 + 2);
     int64_t i = 0;
     for (;;) {
       char c = src[i];
@@ -172,16 +181,17 @@ struct Parser {
           } else if (isalpha((unsigned char)c) || c == '_') {
             int64_t st = i;
             while (isalnum((unsigned char)src[i]) || src[i] == '_') i++;
-            std::string word(src + st, (size_t)(i - st));
-            bool isvar = word.size() >= 2 && word[0] == 'x';
-            for (size_t q = 1; isvar && q < word.size(); q++) isvar = isdigit((unsigned char)word[q]) != 0;
+            const int64_t len = i - st;
+            bool isvar = len >= 2 && c == 'x';
+            for (int64_t q = st + 1; isvar && q < i; q++) isvar = isdigit((unsigned char)src[q]) != 0;
             if (isvar) {
-              if (word.size() > 9) return fail(FBG_E_RANGE, st, "variable index too large");
+              if (len > 9) return fail(FBG_E_RANGE, st, "variable index too large");
               t.kind = Tok::VAR;
-              t.val = std::stoll(word.substr(1));
+              t.val = 0;
+              for (int64_t q = st + 1; q < i; q++) t.val = 10 * t.val + (src[q] - '0');
             } else {
               t.kind = Tok::NAME;
-              t.name = word;
+              t.name.assign(src + st, (size_t)len);
             }
           } else {
             return fail(FBG_E_PARSE, i, std::string("unexpected character '") + c + "'");
@@ -250,6 +260,7 @@ struct Parser {
 
   bool program(Edge &root) {
     if (!lex()) return false;
+    g.reserve(toks.size());
     root = kTrue;
     int nassert = 0;
     for (;;) {
@@ -347,7 +358,7 @@ struct Codegen {
       }
       // AND(l) = ~OR(~l); ~AND(l) = OR(~l)
       for (Lit &l : leaves) l.neg = !l.neg;
-      ls.lits = leaves;
+      ls.lits = std::move(leaves);
       ls.inv = !(e & 1u);
       return true;
     }
@@ -371,7 +382,7 @@ struct Codegen {
         }
       }
       ls.is_xor = true;
-      ls.lits = leaves;
+      ls.lits = std::move(leaves);
       ls.inv = parity;
       return true;
     }
@@ -379,6 +390,7 @@ struct Codegen {
   }
 
   void emit(const HIns &h) { code.push_back(h); }
+  void emit(HIns &&h) { code.push_back(std::move(h)); }
 
   // Invert cur: fold into the previous cur-writing instruction when possible.
   void emit_not() {
@@ -652,6 +664,7 @@ struct Codegen {
     // prefix in a loop of its own); then XOR / AND sets of literals through
     // cur; then the general conjuncts.
     n_clause = 0;
+    code.reserve(uniq.size() + 16);
     std::vector<Edge> general;
     std::vector<LitSet> other_sets;
     for (Edge e : uniq) {
@@ -660,11 +673,11 @@ struct Codegen {
         if (!ls.is_xor && !ls.inv) {
           HIns h;
           h.op = FBG_OP_CL;
-          h.ls = ls;
-          emit(h);
+          h.ls = std::move(ls);
+          emit(std::move(h));
           n_clause++;
         } else {
-          other_sets.push_back(ls);
+          other_sets.push_back(std::move(ls));
         }
       } else {
         general.push_back(e);
@@ -777,6 +790,59 @@ void *compile_thread(void *arg) {
   return nullptr;
 }
 
+// Deeply nested text recurses in the parser and the code generator, so the
+// work runs on a large stack of its own: 512 MiB of address space per
+// calling thread, reserved on its first compile (pages are committed only as
+// the recursion touches them) behind a guard page, entered with swapcontext
+// in the caller's own thread.  A thread created per compile (the first
+// design) cost about 0.1 ms and a long-lived worker thread about 0.03 ms per
+// hand-over, most of a small compile.  Under AddressSanitizer, which does not
+// follow stack switches, and if the reservation fails, a thread with such a
+// stack runs the job instead.
+constexpr size_t kCompileStack = (size_t)512 << 20;
+
+struct CompileStack {
+  void *base = nullptr;
+  bool failed = false;
+  ~CompileStack() {
+    if (base) munmap(base, kCompileStack);
+  }
+};
+thread_local CompileStack t_stack;
+thread_local CompileJob *t_job = nullptr;
+
+void compile_on_switched_stack() { compile_thread(t_job); }
+
+bool run_on_big_stack(CompileJob *job) {
+#if defined(__SANITIZE_ADDRESS__)
+  (void)job;
+  return false;
+#else
+  CompileStack &st = t_stack;
+  if (!st.base && !st.failed) {
+    void *p = mmap(nullptr, kCompileStack, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1,
+                   0);
+    if (p == MAP_FAILED || mprotect(p, 4096, PROT_NONE) != 0) {  // guard page at the low end
+      if (p != MAP_FAILED) munmap(p, kCompileStack);
+      st.failed = true;
+    } else {
+      st.base = p;
+    }
+  }
+  if (!st.base) return false;
+  ucontext_t caller, callee;
+  if (getcontext(&callee) != 0) return false;
+  callee.uc_stack.ss_sp = st.base;
+  callee.uc_stack.ss_size = kCompileStack;
+  callee.uc_link = &caller;
+  makecontext(&callee, compile_on_switched_stack, 0);
+  t_job = job;
+  const bool ok = swapcontext(&caller, &callee) == 0;
+  t_job = nullptr;
+  return ok;
+#endif
+}
+
 }  // namespace
 
 int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int64_t &offset,
@@ -787,17 +853,16 @@ int compile_formula(const char *src, int n, Compiled &out, std::string &msg, int
   job.n_free = subst ? n_free : n;
   job.out = &out;
   job.subst = subst;
-  // Deeply nested text recurses in the parser and code generator; give the
-  // work a large stack of its own.
-  pthread_attr_t attr;
-  pthread_attr_init(&attr);
-  pthread_attr_setstacksize(&attr, (size_t)512 << 20);
-  pthread_t th;
-  if (pthread_create(&th, &attr, compile_thread, &job) != 0) {
-    pthread_attr_destroy(&attr);
-    compile_thread(&job);
-  } else {
-    pthread_join(th, nullptr);
+  if (!run_on_big_stack(&job)) {
+    pthread_attr_t attr;
+    pthread_attr_init(&attr);
+    pthread_attr_setstacksize(&attr, kCompileStack);
+    pthread_t th;
+    if (pthread_create(&th, &attr, compile_thread, &job) != 0) {
+      compile_thread(&job);
+    } else {
+      pthread_join(th, nullptr);
+    }
     pthread_attr_destroy(&attr);
   }
   msg = job.msg;
@@ -814,6 +879,10 @@ struct SetWords {
   uint64_t lanemask = 0, sel = 0, neg = 0;
 };
 
+// bit i of kIndexBitMask64[j] = bit j of i
+constexpr uint64_t kIndexBitMask64[6] = {0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
+                                         0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
+
 SetWords encode_set(const LitSet &ls, int log2w) {
   SetWords s;
   const int W = 1 << log2w;
@@ -825,14 +894,13 @@ SetWords encode_set(const LitSet &ls, int log2w) {
       uint32_t m = fbg_inword_mask(l.k) ^ negmask;
       if (ls.is_xor) s.mconst ^= m; else s.mconst |= m;
     } else if (l.k < FBG_TILE_BASE_BIT) {
-      uint64_t m = 0;
-      for (int lane = 0; lane < 64; lane++)
-        if ((((unsigned)lane >> (l.k - FBG_SLICE_BITS)) & 1u) ^ (l.neg ? 1u : 0u)) m |= 1ull << lane;
+      // the lanes whose index has bit k - 5 set (clear, for a negated literal)
+      const uint64_t m = kIndexBitMask64[l.k - FBG_SLICE_BITS] ^ (l.neg ? ~0ull : 0ull);
       if (ls.is_xor) s.lanemask ^= m; else s.lanemask |= m;
     } else if (l.k < tile_bit) {
-      uint32_t m = 0;
-      for (int i = 0; i < W; i++)
-        if ((((unsigned)i >> (l.k - FBG_TILE_BASE_BIT)) & 1u) ^ (l.neg ? 1u : 0u)) m |= 1u << i;
+      // likewise the words of a lane, of W
+      const uint32_t wmask = W == 32 ? ~0u : (1u << W) - 1u;
+      const uint32_t m = ((uint32_t)kIndexBitMask64[l.k - FBG_TILE_BASE_BIT] ^ (l.neg ? ~0u : 0u)) & wmask;
       if (ls.is_xor) s.pat ^= m; else s.pat |= m;
     } else {
       uint64_t b = 1ull << (l.k - FBG_TILE_BASE_BIT);
@@ -879,9 +947,7 @@ int group_of(uint32_t pat, int log2w) {
   if (pat == 0) return 0;
   if (pat == full) return kAlwaysTrue;
   for (int j = 0; j < log2w; j++) {
-    uint32_t ones = 0;  // the words whose bit j is 1
-    for (int i = 0; i < W; i++)
-      if ((i >> j) & 1) ones |= 1u << i;
+    const uint32_t ones = (uint32_t)kIndexBitMask64[j] & full;  // the words whose bit j is 1
     if (pat == ones) return 1 + 2 * j;             // x: false where bit j = 0
     if (pat == (full & ~ones)) return 1 + 2 * j + 1;  // ~x: false where bit j = 1
   }
@@ -916,12 +982,10 @@ void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, int ki
   out.resize(base + FBG_CB_CHUNK_HDR, 0u);
   out[base + 0] = nc;
   // lane bits: clause c holds on lane l through a lane literal; padding set
-  for (int lane = 0; lane < 64; lane++) {
-    uint32_t b = nc == FBG_CB_CHUNK ? 0u : ~0u << nc;
-    for (uint32_t c = 0; c < nc; c++)
-      if ((cl[lo + c].s.lanemask >> lane) & 1u) b |= 1u << c;
-    out.push_back(b);
-  }
+  const size_t lanes = out.size();
+  out.resize(lanes + 64, nc == FBG_CB_CHUNK ? 0u : ~0u << nc);
+  for (uint32_t c = 0; c < nc; c++)
+    for (uint64_t m = cl[lo + c].s.lanemask; m; m &= m - 1) out[lanes + (size_t)__builtin_ctzll(m)] |= 1u << c;
   uint32_t tmask = 0;
   for (uint32_t c = 0; c < nc; c++) {
     const SetWords &s = cl[lo + c].s;

@@ -189,6 +189,33 @@ def test_deep_nesting_compiles():
     check(text, n, wpl=[1, 16])
 
 
+def test_deep_text_compiles_from_several_threads():
+    """The compiler recurses on a large stack of its own per calling thread:
+    deep text from several Python threads at once, each result as on the
+    main thread, and later compiles on the same threads still work."""
+    import threading
+    n = 9
+    texts = ["(" * 20000 + "x%d | ~x%d" % (k, k + 1) + ")" * 20000 for k in range(4)]
+    texts += [" ^ ".join("x%d" % ((i * 5 + k) % n) for i in range(30000)) for k in range(4)]
+    want = [fbg.Program(t, n).emulate(4)[1] for t in texts]
+    got = [None] * len(texts)
+    errors = []
+
+    def work(k):
+        try:
+            for _ in range(2):
+                got[k] = fbg.Program(texts[k], n).emulate(4)[1]
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(texts))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors and got == want
+
+
 def test_set_tuning_changes_the_default():
     p = fbg.Program(*workloads.random_3cnf(20, 85, 0))
     for w in (1, 4, 32):
