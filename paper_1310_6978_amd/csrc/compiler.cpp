@@ -22,6 +22,7 @@
 #include <array>
 #include <set>
 #include <cctype>
+#include <new>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -757,8 +758,25 @@ struct CompileJob {
   int status = FBG_OK;
 };
 
+void compile_job(CompileJob *job);
+
+// Entry of the compile on its own stack: nothing may propagate out of it
+// (an allocation failure becomes FBG_E_NOMEM).
 void *compile_thread(void *arg) {
   CompileJob *job = (CompileJob *)arg;
+  try {
+    compile_job(job);
+  } catch (const std::bad_alloc &) {
+    job->status = FBG_E_NOMEM;
+    job->msg = "out of host memory while compiling";
+  } catch (...) {
+    job->status = FBG_E_INVAL;
+    job->msg = "internal error while compiling";
+  }
+  return nullptr;
+}
+
+void compile_job(CompileJob *job) {
   Graph g;
   Parser ps(job->src, job->n, g);
   ps.subst = job->subst;
@@ -767,7 +785,7 @@ void *compile_thread(void *arg) {
     job->status = ps.status;
     job->msg = ps.msg;
     job->off = ps.off;
-    return nullptr;
+    return;
   }
   Compiled &c = *job->out;
   c = Compiled();
@@ -780,14 +798,13 @@ void *compile_thread(void *arg) {
       c.code.push_back(h);
       c.n_clause_instr = 1;
     }
-    return nullptr;
+    return;
   }
   Codegen cg(g);
   c.l2in = cg.analyse(root);
   cg.top(root, c.n_clause_instr);
   c.code.swap(cg.code);
   c.nregs = allocate_registers(c.code, cg.nvregs);
-  return nullptr;
 }
 
 // Deeply nested text recurses in the parser and the code generator, so the
