@@ -110,3 +110,29 @@ def test_compile_only_some_tilings():
     one = fbg.Program(text, n, fbg.compile_wpl(2))
     assert one.info["words_per_lane"] == 2
     assert one.emulate(2)[1] == full.emulate(2)[1]
+
+
+def test_compile_flags_for_assume_and_subst():
+    """The tiling flags act the same through fbg_compile_assume and
+    fbg_compile_subst; unknown bits are refused by all three calls."""
+    text, n = "a = x0 & x3\na | (x1 ^ x5) | ~x6\nx2 | x4 | x7", 8
+    assume = [-1, 1, -1, 0, -1, -1, -1, -1]
+    full = fbg.compile_assume(text, n, assume)
+    part = fbg.compile_assume(text, n, assume, fbg.compile_wpl(8))
+    assert part.info["words_per_lane"] == 8 and part.n == full.n == 6
+    assert part.emulate(8)[1] == full.emulate(8)[1]
+    with pytest.raises(fbg.FbgError):
+        part.emulate(4)
+    subst = [0, 1, 2, 0, -2, 3, 4, 1]  # x4 := 1; x3 = x0, x7 = x1
+    full = fbg.compile_subst(text, n, subst, 5)
+    part = fbg.compile_subst(text, n, subst, 5, fbg.compile_wpl(1, 32))
+    assert part.info["words_per_lane"] in (1, 32)
+    for w in (1, 32):
+        assert part.emulate(w)[1] == full.emulate(w)[1]
+    with pytest.raises(fbg.FbgError):
+        part.emulate(2)
+    for call in (lambda: fbg.compile_assume(text, n, assume, 0x80),
+                 lambda: fbg.compile_subst(text, n, subst, 5, 0x100)):
+        with pytest.raises(fbg.FbgError) as e:
+            call()
+        assert e.value.status == fbg.FBG_E_INVAL
