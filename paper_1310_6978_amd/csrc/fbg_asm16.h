@@ -6,12 +6,14 @@
 // instructions of one program instruction; the scalar unit, which issues no
 // faster than the VALU, then bounds the loop.  Here every instruction carries
 // the byte offset of its case, and one s_setpc_b64 enters the case's code
-// directly (4 scalar instructions).  Each case fetches the next instruction
-// before its VALU work, so the fetch is waited for only at the next dispatch.
+// directly (2 scalar instructions on the table's 64 KiB boundary, 4
+// elsewhere).  Each case fetches the next instruction before its VALU work,
+// so the fetch is waited for only at the next dispatch.
 //
 // Register map (fixed; the C++ side sees acc as a pinned in/out operand and
 // every other register below as clobbered):
-//   v14         T, the lane value of a literal set
+//   v14         T, the lane value of a literal set (of a set without word
+//               literals: its lane part, the rest in s73)
 //   v15         LDS address
 //   v[16:31]    cur, word i in v[16+i]
 //   v[32:79]    registers 0..2 in VGPRs, register r word i in v[32+16r+i]
@@ -22,9 +24,12 @@
 // leaving v[0:13] and v[112:127] to the compiler for what lives across (four
 // waves share a SIMD; two VGPR registers and five waves measured slower).
 //   s[48:55]    the current instruction, s[56:71] its pattern words,
-//   s[72:75]    scratch, s[76:77] the jump table base, s[78:79] the jump
-//               target, s80 the instruction offset, s81 the pattern offset,
-//   s83         M0 saved (index mode changes M0; restored on exit)
+//   s[72:75]    scratch (s73: the rest of a lane value, above),
+//   s[76:77]    the table's address (copy B) or bits 16..31 of it in s77
+//               (copy A), s[78:79] the jump target (s79 its bits 32..63 in
+//               copy A), s80 the instruction offset, s81 the pattern offset,
+//   s83         M0 saved (index mode changes M0; restored on exit),
+//   s[84:85]    where the interpreter returns to
 // All 64 lanes are active (the kernels call it on full waves).
 #ifndef FBG_ASM16_H
 #define FBG_ASM16_H

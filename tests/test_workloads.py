@@ -1,5 +1,7 @@
 """Input generators: determinism, sizes, and the SplitMix64 definition."""
 
+import os
+
 import workloads
 from workloads import SplitMix64
 from workloads.formulas import cnf_clause_count, random_dag_batch
@@ -65,3 +67,17 @@ def test_serving_golden_matches_the_stream():
         r = reqs[int(i)]
         assert r["n"] == g["counts"][i]["n"]
         assert oracle.count(r["text"], r["n"]) == g["counts"][i]["count"]
+
+
+def test_traffic_digest_ignores_comments_only():
+    """roofline.traffic is tied to the digest of the kernel sources' code: an
+    edit of comments keeps it, an edit of code does not."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    code = 'x = 1; // one\n/* two\n three */ asm("s_nop 0\\n");  \n'
+    assert b.code_of(code) == b.code_of('x = 1;\n asm("s_nop 0\\n"); // other words\n')
+    assert b.code_of(code) != b.code_of('x = 2; asm("s_nop 0\\n");')
+    assert len(b.kernel_sources_sha1()) == 40
