@@ -154,7 +154,7 @@ struct fbg_program {
   uint32_t tilings = FBG_COMPILE_WPL_MASK;  // bit l: encoded for 2^l words per lane
   bool has_tiling(int l) const { return (tilings >> l) & 1u; }
   // programs of clauses alone with n >= kXcdMinVars: the 32-words-per-lane
-  // encoding with variables exchanged for the XCD-local DNF write-out
+  // encoding with variables renamed for the XCD-local DNF write-out
   std::vector<uint32_t> words_xcd;
   uint64_t dev_off_xcd = 0;
   bool has_xcd = false;
@@ -461,7 +461,7 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
   if (!p->general() && p->c.n >= fbg::kXcdMinVars && p->has_tiling(5)) {
     const fbg::Compiled x = fbg::permute_variables(p->c, fbg::xcd_write_out_permutation(p->c.n));
     const uint32_t nx = fbg::encode_program(x, 5, p->words_xcd, &enc_err);
-    if (nx != p->nins[5] && enc_err.empty()) enc_err = "internal: exchanged encoding differs in length";
+    if (nx != p->nins[5] && enc_err.empty()) enc_err = "internal: renamed encoding differs in length";
     p->dev_off_xcd = total;
     total += p->words_xcd.size();
     p->has_xcd = true;

@@ -851,10 +851,10 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, 0)) void k_batch_direct(Batch
     uint32_t acc[W];
     GenState<W> st;  // unused: clause-only programs
     if (LOG2W == 5 && p->xcd_code && p->chunk_counts) {
-      // XCD-local layout (fbg_kernels.h): the exchanged program's tile t is
+      // XCD-local layout (fbg_kernels.h): the renamed program's tile t is
       // the pieces x + 8 h + 16 (t & 3) + 64 (t >> 5) of the vector, h = 0, 1
       // (words 0..15 and 16..31 of each lane), x = bits 2..4 of t; full tiles
-      // only (n >= 21)
+      // only (n >= 21), output 16-byte aligned
       run_program<LOG2W, false>(p->xcd_code, p->nins, U0, lane, acc, st, nullptr);
       const uint64_t piece = ((t >> 2) & 7) + 16 * (t & 3) + 64 * (t >> 5);
       store_xcd_tile(acc, p->out32 + piece * 1024 + lane * 4);
@@ -894,7 +894,7 @@ __global__ __launch_bounds__(256) void k_sum_tile_counts(BatchArgs a) {
   for (uint64_t t = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; t < p.ntiles; t += (uint64_t)gridDim.y * blockDim.x) {
     if (xcd) {
       // tile t of the vector is pieces 2t and 2t + 1; piece c came from
-      // tile (c & 7) << 2 | (c >> 4 & 3) | (c >> 6) << 5 of the exchanged
+      // tile (c & 7) << 2 | (c >> 4 & 3) | (c >> 6) << 5 of the renamed
       // program, its half c >> 3 & 1
       uint32_t v = 0;
       for (uint64_t c = 2 * t; c < 2 * t + 2; c++) {

@@ -66,7 +66,7 @@ struct BatchProg {
   uint64_t out_slices;  // MODE_DNF: 32-bit words of out32
   uint32_t *tile_counts;  // MODE_DNF: per-tile model counts (or null)
   // the batched DNF write-out in the XCD-local layout (or null): the program
-  // with variables exchanged, and the per-piece model counts it writes
+  // with variables renamed, and the per-piece model counts it writes
   const uint32_t *xcd_code;
   uint32_t *chunk_counts;
 };
