@@ -343,6 +343,17 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   return a;
 }
 
+// Estimated cost of one tile of a program in a batch, in steps of the
+// interpreter: one per instruction after the clause block (counted in the
+// plain form: one word per lane never takes the jump-table form) and a few
+// more per tile; a clause block adds its setup, product tree and count, and
+// one step per clause.  (On the C3 programs made of one to four clauses a tile
+// takes about 12 such steps.)
+double tile_cost(const fbg_program *p) {
+  const double general = (double)(p->c.code.size() - p->ncl);
+  return general + 4.0 + (p->ncl ? 8.0 + (double)p->ncl : 0.0);
+}
+
 fbg::BatchProg batch_prog(const fbg_program *p, int l) {
   fbg::BatchProg b;
   memset(&b, 0, sizeof b);
@@ -828,9 +839,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     for (int32_t i : members) {
       fbg::BatchProg &q = b->host_progs[(size_t)i];
       q = batch_prog(ps[i], l);
-      // per tile about one step per instruction (counted in the plain form:
-      // one word per lane never takes the jump-table form) and a few more
-      total_cost += (double)q.ntiles * ((double)(ps[i]->c.code.size() - ps[i]->ncl) + 4.0);
+      total_cost += (double)q.ntiles * tile_cost(ps[i]);
       b->plan_of[(size_t)i] = (int)b->plans.size();
     }
     // about four items per wave; never split below one tile.  A program's
@@ -842,7 +851,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     std::vector<double> cost;
     for (int32_t i : members) {
       const fbg::BatchProg &q = b->host_progs[(size_t)i];
-      const double per_tile = (double)(ps[i]->c.code.size() - ps[i]->ncl) + 4.0;
+      const double per_tile = tile_cost(ps[i]);
       const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
       const uint64_t K = (q.ntiles + chunk - 1) / chunk;
       for (uint64_t k = 0; k < K; k++) {
