@@ -369,8 +369,9 @@ fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_
  *   FBG_TUNE_COFACTOR.
  * fbg_server_launch -- upload the program table and the items (asynchronous,
  *   from pinned memory) and launch one persistent batched kernel on `stream`.
- *   Long items are cut into pieces (at most max_items pieces in all) so that
- *   a few large requests still occupy every compute unit.
+ *   Items are cut into pieces of about equal estimated cost (at most
+ *   max_items pieces in all) so that a few large requests still occupy
+ *   every compute unit.
  *   Items are validated on the host (FBG_E_INVAL on a bad index or range).
  *   A staging buffer is reused only after its previous launch has finished.
  *   Not thread-safe: one server object per host thread.

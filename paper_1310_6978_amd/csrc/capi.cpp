@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1279,22 +1280,29 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   fbg::BatchProg *hp = (fbg::BatchProg *)sl.h;
   fbg::BatchItem *hi = (fbg::BatchItem *)(sl.h + (size_t)sv->max_programs * sizeof(fbg::BatchProg));
   for (int32_t i = 0; i < np; i++) hp[i] = batch_prog(ps[i], l);  // tilings checked above
-  // Cut the items into pieces of at most `piece` tiles so that every resident
-  // wave gets about four, within the staging capacity: the pieces number at
-  // most (total tiles / piece) + nitems <= max_items.
-  uint64_t total = 0;
-  for (int32_t k = 0; k < nitems; k++) total += items[k].tile_end - items[k].tile_begin;
+  // Cut the items into pieces of about equal estimated cost (tile_cost per
+  // tile) so that every resident wave gets about four, within the staging
+  // capacity: an item of c tiles at cost w each gives ceil(c / ceil(T / w)) <=
+  // c w / T + 1 pieces for a target T, so want + nitems <= max_items in all
+  // (checked below all the same).  (Sorting the pieces by cost as the batch
+  // plans do cost more host time per slice than it saved.)
+  double total = 0;
+  for (int32_t k = 0; k < nitems; k++)
+    total += (double)(items[k].tile_end - items[k].tile_begin) * tile_cost(ps[items[k].prog]);
   const uint64_t room = (uint64_t)(sv->max_items - nitems);
   const uint64_t want = std::min<uint64_t>(room, (uint64_t)cus * occ * wpb * 4);
-  const uint64_t piece = want > 0 ? std::max<uint64_t>(1, (total + want - 1) / want) : ~0ull;
+  const double target = want > 0 ? total / (double)want * (1.0 + 1e-9) : 0.0;
   int32_t npieces = 0;
   for (int32_t k = 0; k < nitems; k++) {
-    for (uint64_t t = items[k].tile_begin; t < items[k].tile_end; t += std::min(piece, items[k].tile_end - t)) {
+    const double w = tile_cost(ps[items[k].prog]);
+    const uint64_t chunk = want > 0 ? std::max<uint64_t>(1, (uint64_t)std::ceil(target / w)) : ~0ull;
+    for (uint64_t t = items[k].tile_begin; t < items[k].tile_end; t += std::min(chunk, items[k].tile_end - t)) {
+      if (npieces >= sv->max_items) return fail(FBG_E_INVAL, "internal: more pieces than staging room");
       fbg::BatchItem &q = hi[npieces++];
       q.prog = (uint32_t)items[k].prog;
       q.slot = (uint32_t)items[k].slot;
       q.t0 = t;
-      q.t1 = t + std::min(piece, items[k].tile_end - t);
+      q.t1 = t + std::min(chunk, items[k].tile_end - t);
       q.step = 1;
     }
   }
