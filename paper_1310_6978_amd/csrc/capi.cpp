@@ -276,15 +276,16 @@ fbg_status block_shape(uint32_t nregs, int l, int &wpb, size_t &lds) {
   return FBG_OK;
 }
 
-// Launch shape of an evaluator kernel: a persistent grid of exactly the
-// blocks that can be resident at once (more would only queue behind them and
-// finish in a tail), each wave striding over the tiles.
+// FBG_E_INVAL unless the program was encoded for 2^l words per lane.
 fbg_status check_tiling(const fbg_program *p, int l) {
   if (!p->has_tiling(l))
     return fail(FBG_E_INVAL, "the program was compiled without %d words per lane (FBG_COMPILE_WPL)", 1 << l);
   return FBG_OK;
 }
 
+// Launch shape of an evaluator kernel: a persistent grid of exactly the
+// blocks that can be resident at once (more would only queue behind them and
+// finish in a tail), each wave striding over the tiles.
 fbg_status geometry(const fbg_program *p, const fbg_tune *tune, int mode, Geometry &g) {
   int l = p->auto_log2w;
   fbg_status st;
