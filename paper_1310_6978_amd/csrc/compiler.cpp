@@ -1474,7 +1474,8 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
 
 double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log2w, uint32_t nregs) {
   // The per-tile VALU instructions of the kernels, instruction by
-  // instruction of the encoding (kernels.hip, run_clauses / run_general).
+  // instruction of the encoding (run_clauses and run_general in
+  // fbg_device.h, the cases of fbg_asm16.h).
   const uint32_t W = 1u << log2w;
   if (words.empty()) return 0.0;
   const uint32_t *cb = words.data();
@@ -1512,17 +1513,19 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
       } else if (cs >= FBG_J16_ORA) {
         per_tile += W;  // one v_bitop3 per word into acc
       } else if (cs >= FBG_J16_LIS_OR) {
-        per_tile += 2 + W;  // the lane value, one v_bitop3 per word into the register
+        per_tile += 1 + W;  // the lane part, one v_bitop3 per word into the register
       } else if (cs >= FBG_J16_XYS_OR) {
-        per_tile += 4 + W;  // the lane value, X and Y, then one v_bitop3 per word
+        per_tile += 3 + W;  // the lane part, X and Y, then one v_bitop3 per word
       } else if (cs >= FBG_J16_ORS) {
         per_tile += W;  // one v_bitop3 per word into the register
       } else if (cs >= FBG_J16_XYL_OR) {
-        per_tile += 4 + W;  // the lane value, X and Y, then one v_bitop3 per word
+        per_tile += 3 + W;  // the lane part, X and Y, then one v_bitop3 per word
       } else if (cs >= FBG_J16_XYF_OR) {
-        per_tile += 4;  // the lane value, then X and Y
-      } else if (cs >= FBG_J16_LIT_OR) {
+        per_tile += 3;  // the lane part, then X and Y
+      } else if (cs >= FBG_J16_LIT_OR_P) {
         per_tile += 2 + W;  // the lane value, one v_bitop3 per word
+      } else if (cs >= FBG_J16_LIT_OR) {
+        per_tile += 1 + W;  // the lane part, one v_bitop3 per word
       } else if (cs >= FBG_J16_REG_V) {
         per_tile += W + (cs >= FBG_J16_REG_L ? 1 : 0);
       } else if (cs >= FBG_J16_ST_V) {
