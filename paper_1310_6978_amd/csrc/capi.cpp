@@ -159,6 +159,7 @@ struct fbg_program {
   std::vector<uint32_t> words_xcd;
   uint64_t dev_off_xcd = 0;
   bool has_xcd = false;
+  double j16_cost = 0;  // per tile at 16 words per lane, from the jump-table form (0: none)
   uint32_t ncl = 0;  // leading clause instructions
   int auto_log2w = 0;
   uint64_t nslices = 1;
@@ -345,14 +346,15 @@ fbg::EvalArgs base_args(const fbg_program *p, int log2w) {
   return a;
 }
 
-// Estimated cost of one tile of a program in a batch, in steps of the
-// interpreter: one per instruction after the clause block (counted in the
-// plain form: one word per lane never takes the jump-table form) and a few
-// more per tile; a clause block adds its setup, product tree and count, and
-// one step per clause.  (On the C3 programs made of one to four clauses a tile
-// takes about 12 such steps.)
-double tile_cost(const fbg_program *p) {
-  const double general = (double)(p->c.code.size() - p->ncl);
+// Estimated cost of one tile of a program in a batch or a server slice at 2^l
+// words per lane, in steps of the interpreter: at 16 words per lane the
+// general part's VALU instructions per word and half a step per dispatch of
+// its jump-table form (j16_general_cost), elsewhere one step per instruction
+// after the clause block in the plain form; a few more per tile; a clause
+// block adds its setup, product tree and count, and one step per clause.  (On
+// the C3 programs made of one to four clauses a tile takes about 12 steps.)
+double tile_cost(const fbg_program *p, int l) {
+  const double general = l == FBG_J16_LOG2W && p->j16_cost > 0 ? p->j16_cost : (double)(p->c.code.size() - p->ncl);
   return general + 4.0 + (p->ncl ? 8.0 + (double)p->ncl : 0.0);
 }
 
@@ -514,6 +516,8 @@ fbg_status compile_common(const char *src, int32_t n_vars, const int32_t *subst,
     p->auto_log2w = pick_log2w(p->nslices, (uint32_t)p->c.nregs, p->general(), -1);
   }
   p->auto_log2w = nearest_tiling(p->tilings, p->auto_log2w);
+  if (p->general() && p->has_tiling(FBG_J16_LOG2W))
+    p->j16_cost = fbg::j16_general_cost(p->words[FBG_J16_LOG2W], p->nins[FBG_J16_LOG2W]);
   *out = p;
   return FBG_OK;
 }
@@ -841,7 +845,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     for (int32_t i : members) {
       fbg::BatchProg &q = b->host_progs[(size_t)i];
       q = batch_prog(ps[i], l);
-      total_cost += (double)q.ntiles * tile_cost(ps[i]);
+      total_cost += (double)q.ntiles * tile_cost(ps[i], l);
       b->plan_of[(size_t)i] = (int)b->plans.size();
     }
     // about four items per wave; never split below one tile.  A program's
@@ -853,7 +857,7 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
     std::vector<double> cost;
     for (int32_t i : members) {
       const fbg::BatchProg &q = b->host_progs[(size_t)i];
-      const double per_tile = tile_cost(ps[i]);
+      const double per_tile = tile_cost(ps[i], l);
       const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
       const uint64_t K = (q.ntiles + chunk - 1) / chunk;
       for (uint64_t k = 0; k < K; k++) {
@@ -1289,13 +1293,13 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   // plans do cost more host time per slice than it saved.)
   double total = 0;
   for (int32_t k = 0; k < nitems; k++)
-    total += (double)(items[k].tile_end - items[k].tile_begin) * tile_cost(ps[items[k].prog]);
+    total += (double)(items[k].tile_end - items[k].tile_begin) * tile_cost(ps[items[k].prog], l);
   const uint64_t room = (uint64_t)(sv->max_items - nitems);
   const uint64_t want = std::min<uint64_t>(room, (uint64_t)cus * occ * wpb * 4);
   const double target = want > 0 ? total / (double)want * (1.0 + 1e-9) : 0.0;
   int32_t npieces = 0;
   for (int32_t k = 0; k < nitems; k++) {
-    const double w = tile_cost(ps[items[k].prog]);
+    const double w = tile_cost(ps[items[k].prog], l);
     const uint64_t chunk = want > 0 ? std::max<uint64_t>(1, (uint64_t)std::ceil(target / w)) : ~0ull;
     for (uint64_t t = items[k].tile_begin; t < items[k].tile_end; t += std::min(chunk, items[k].tile_end - t)) {
       if (npieces >= sv->max_items) return fail(FBG_E_INVAL, "internal: more pieces than staging room");

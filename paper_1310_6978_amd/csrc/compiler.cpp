@@ -1472,6 +1472,50 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
   return nins;
 }
 
+// VALU instructions per tile of the general part in the jump-table form, and
+// its instructions (dispatches), W words per lane.
+static void j16_general_work(const uint32_t *ins, uint32_t nins, uint32_t W, double &valu, uint32_t &dispatches) {
+  double per_tile = 0;
+  uint32_t n = 0;
+  const size_t end = (size_t)nins * FBG_J16_UNIT;
+  for (size_t at = 0; at < end;) {
+    const uint32_t cs = (ins[at] & 0xFFFFu) / FBG_J16_SLOT;
+    if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) break;
+    at += j16_words(cs);
+    n++;
+    if (cs >= FBG_J16_LIA_OR) {
+      per_tile += 2 + W;  // the lane value, one v_bitop3 per word into acc
+    } else if (cs >= FBG_J16_ORA) {
+      per_tile += W;  // one v_bitop3 per word into acc
+    } else if (cs >= FBG_J16_LIS_OR) {
+      per_tile += 1 + W;  // the lane part, one v_bitop3 per word into the register
+    } else if (cs >= FBG_J16_XYS_OR) {
+      per_tile += 3 + W;  // the lane part, X and Y, then one v_bitop3 per word
+    } else if (cs >= FBG_J16_ORS) {
+      per_tile += W;  // one v_bitop3 per word into the register
+    } else if (cs >= FBG_J16_XYL_OR) {
+      per_tile += 3 + W;  // the lane part, X and Y, then one v_bitop3 per word
+    } else if (cs >= FBG_J16_XYF_OR) {
+      per_tile += 3;  // the lane part, then X and Y
+    } else if (cs >= FBG_J16_LIT_OR_P) {
+      per_tile += 2 + W;  // the lane value, one v_bitop3 per word
+    } else if (cs >= FBG_J16_LIT_OR) {
+      per_tile += 1 + W;  // the lane part, one v_bitop3 per word
+    } else if (cs >= FBG_J16_REG_V) {
+      per_tile += W + (cs >= FBG_J16_REG_L ? 1 : 0);
+    } else if (cs >= FBG_J16_ST_V) {
+      const bool lds = cs >= FBG_J16_ST_L;
+      per_tile += (lds ? 1 : W) + ((cs - (lds ? FBG_J16_ST_L : FBG_J16_ST_V)) ? W : 0);
+    } else if (cs >= FBG_J16_ACC) {
+      per_tile += W + ((cs - FBG_J16_ACC) >= 2 ? W : 0);
+    } else if (cs == FBG_J16_NOT) {
+      per_tile += W;
+    }
+  }
+  valu = per_tile;
+  dispatches = n;
+}
+
 double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log2w, uint32_t nregs) {
   // The per-tile VALU instructions of the kernels, instruction by
   // instruction of the encoding (run_clauses and run_general in
@@ -1503,40 +1547,10 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
   const uint32_t *ins = cb + cb[0];
   if (log2w == FBG_J16_LOG2W) {
     // jump-table form: per instruction its case's VALU work
-    const size_t end = (size_t)nins * FBG_J16_UNIT;
-    for (size_t at = 0; at < end;) {
-      const uint32_t cs = (ins[at] & 0xFFFFu) / FBG_J16_SLOT;
-      if (cs == FBG_J16_END || cs >= FBG_J16_NCASES) break;
-      at += j16_words(cs);
-      if (cs >= FBG_J16_LIA_OR) {
-        per_tile += 2 + W;  // the lane value, one v_bitop3 per word into acc
-      } else if (cs >= FBG_J16_ORA) {
-        per_tile += W;  // one v_bitop3 per word into acc
-      } else if (cs >= FBG_J16_LIS_OR) {
-        per_tile += 1 + W;  // the lane part, one v_bitop3 per word into the register
-      } else if (cs >= FBG_J16_XYS_OR) {
-        per_tile += 3 + W;  // the lane part, X and Y, then one v_bitop3 per word
-      } else if (cs >= FBG_J16_ORS) {
-        per_tile += W;  // one v_bitop3 per word into the register
-      } else if (cs >= FBG_J16_XYL_OR) {
-        per_tile += 3 + W;  // the lane part, X and Y, then one v_bitop3 per word
-      } else if (cs >= FBG_J16_XYF_OR) {
-        per_tile += 3;  // the lane part, then X and Y
-      } else if (cs >= FBG_J16_LIT_OR_P) {
-        per_tile += 2 + W;  // the lane value, one v_bitop3 per word
-      } else if (cs >= FBG_J16_LIT_OR) {
-        per_tile += 1 + W;  // the lane part, one v_bitop3 per word
-      } else if (cs >= FBG_J16_REG_V) {
-        per_tile += W + (cs >= FBG_J16_REG_L ? 1 : 0);
-      } else if (cs >= FBG_J16_ST_V) {
-        const bool lds = cs >= FBG_J16_ST_L;
-        per_tile += (lds ? 1 : W) + ((cs - (lds ? FBG_J16_ST_L : FBG_J16_ST_V)) ? W : 0);
-      } else if (cs >= FBG_J16_ACC) {
-        per_tile += W + ((cs - FBG_J16_ACC) >= 2 ? W : 0);
-      } else if (cs == FBG_J16_NOT) {
-        per_tile += W;
-      }
-    }
+    double valu;
+    uint32_t dispatches;
+    j16_general_work(ins, nins, W, valu, dispatches);
+    per_tile += valu;
     (void)nregs;
     return per_tile / W;
   }
@@ -1555,6 +1569,14 @@ double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log
   }
   (void)nregs;
   return per_tile / W;
+}
+
+double j16_general_cost(const std::vector<uint32_t> &words, uint32_t nins) {
+  if (words.empty()) return 0.0;
+  double valu;
+  uint32_t dispatches;
+  j16_general_work(words.data() + words[0], nins, 1u << FBG_J16_LOG2W, valu, dispatches);
+  return valu / (1u << FBG_J16_LOG2W) + 0.5 * dispatches;
 }
 
 Compiled permute_variables(const Compiled &c, const std::vector<int> &to) {

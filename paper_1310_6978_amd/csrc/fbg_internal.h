@@ -78,6 +78,10 @@ std::vector<int> xcd_write_out_permutation(int n);
 // program (a static count per tile, divided by the words per lane; the
 // popcount and store epilogue excluded).
 double valu_per_slice(const std::vector<uint32_t> &words, uint32_t nins, int log2w, uint32_t nregs);
+// Estimated cost per tile of the general part of a program in the
+// jump-table form (16 words per lane), in the steps of tile_cost: its VALU
+// instructions per word, and half a step per instruction for the dispatch.
+double j16_general_cost(const std::vector<uint32_t> &words, uint32_t nins);
 
 // Listing of an encoded program.
 std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, int log2w);
