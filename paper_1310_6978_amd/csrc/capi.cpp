@@ -221,15 +221,23 @@ struct fbg_batch {
   uint64_t *graph_counts = nullptr;
 };
 
+// Bytes of queue heads at the start of a server slot: kHeadWords words,
+// rounded to whole 256-byte blocks so that the program table that follows
+// starts on its own cache lines.
+constexpr size_t kServerHeadBytes = (fbg::kHeadWords * sizeof(uint32_t) + 255) / 256 * 256;
+
 struct fbg_server {
   int device = -1;
   int log2w = 0;
   int32_t max_programs = 0, max_items = 0, nbuf = 0, next = 0;
   bool cofactor = false;
+  // A slot's staging (pinned) and device buffers hold, in this order, the
+  // kHeadWords queue heads (zero in the staging copy), the slice's program
+  // table and its pieces, so that one copy uploads the slice and clears its
+  // heads.
   struct Slot {
-    char *h = nullptr;  // pinned staging: programs then items
+    char *h = nullptr;  // pinned staging
     char *d = nullptr;  // device copy
-    uint32_t *d_head = nullptr;
     hipEvent_t done = nullptr;
     bool used = false;
   };
@@ -1233,11 +1241,12 @@ fbg_status fbg_server_create(int32_t max_programs, int32_t max_items, int32_t wo
   sv->nbuf = nbuf;
   sv->cofactor = (flags & FBG_TUNE_COFACTOR) != 0;
   sv->slots.resize((size_t)nbuf);
-  const size_t bytes = (size_t)max_programs * sizeof(fbg::BatchProg) + (size_t)max_items * sizeof(fbg::BatchItem);
+  const size_t bytes = kServerHeadBytes + (size_t)max_programs * sizeof(fbg::BatchProg) +
+                       (size_t)max_items * sizeof(fbg::BatchItem);
   for (auto &sl : sv->slots) {
     e = hipHostMalloc((void **)&sl.h, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) memset(sl.h, 0, kServerHeadBytes);
     if (e == hipSuccess) e = hipMalloc((void **)&sl.d, bytes);
-    if (e == hipSuccess) e = hipMalloc((void **)&sl.d_head, fbg::kHeadWords * sizeof(uint32_t));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     if (e != hipSuccess) {
       fbg_server_free(sv);
@@ -1284,8 +1293,9 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   sv->next = (sv->next + 1) % sv->nbuf;
   hipError_t e;
   if (sl.used && (e = hipEventSynchronize(sl.done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  fbg::BatchProg *hp = (fbg::BatchProg *)sl.h;
-  fbg::BatchItem *hi = (fbg::BatchItem *)(sl.h + (size_t)sv->max_programs * sizeof(fbg::BatchProg));
+  const size_t items_at = kServerHeadBytes + (size_t)np * sizeof(fbg::BatchProg);
+  fbg::BatchProg *hp = (fbg::BatchProg *)(sl.h + kServerHeadBytes);
+  fbg::BatchItem *hi = (fbg::BatchItem *)(sl.h + items_at);
   for (int32_t i = 0; i < np; i++) hp[i] = batch_prog(ps[i], l);  // tilings checked above
   // Cut the items into pieces of about equal estimated cost (tile_cost per
   // tile) so that every resident wave gets about four, within the staging
@@ -1314,19 +1324,14 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
     }
   }
   hipStream_t s = (hipStream_t)stream;
-  char *dp = sl.d;
-  char *di = sl.d + (size_t)sv->max_programs * sizeof(fbg::BatchProg);
-  e = hipMemcpyAsync(dp, hp, (size_t)np * sizeof(fbg::BatchProg), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && npieces > 0)
-    e = hipMemcpyAsync(di, hi, (size_t)npieces * sizeof(fbg::BatchItem), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = fbg::launch_zero(nullptr, 0, sl.d_head, fbg::kHeadWords, s);
+  e = hipMemcpyAsync(sl.d, sl.h, items_at + (size_t)npieces * sizeof(fbg::BatchItem), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "server upload");
   fbg::BatchArgs a;
-  a.progs = (const fbg::BatchProg *)dp;
-  a.items = (const fbg::BatchItem *)di;
+  a.progs = (const fbg::BatchProg *)(sl.d + kServerHeadBytes);
+  a.items = (const fbg::BatchItem *)(sl.d + items_at);
   a.nitems = (uint32_t)npieces;
   a.max_regs = lds_regs(max_regs, l);
-  a.head = sl.d_head;
+  a.head = (uint32_t *)sl.d;
   a.counts = d_counts;
   a.j16_any = j16_any();
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((npieces + wpb - 1) / wpb, (int64_t)cus * occ));
@@ -1343,7 +1348,6 @@ void fbg_server_free(fbg_server *sv) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.h) (void)hipHostFree(sl.h);
     if (sl.d) (void)hipFree(sl.d);
-    if (sl.d_head) (void)hipFree(sl.d_head);
   }
   delete sv;
 }

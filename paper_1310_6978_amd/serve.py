@@ -97,10 +97,13 @@ class _Req:
 
 class ServeLoop:
     """The serving loop.  `slice_words` bounds the clause-word work of one
-    slice (a clause applied to one 32-bit word is one unit)."""
+    slice (a clause applied to one 32-bit word is one unit).  `cofactor`
+    runs the slices with the uniform-cofactor test (a tile on which a clause
+    made only of tile literals is false is skipped); counts are the same
+    either way."""
 
     def __init__(self, words_per_lane=16, slice_words=4e10, arena_bytes=4 << 30, max_active=256,
-                 max_items=16384, nstreams=2, cache_capacity=64):
+                 max_items=16384, nstreams=2, cache_capacity=64, cofactor=True):
         import torch
         self.torch = torch
         self.W = int(words_per_lane)
@@ -112,7 +115,7 @@ class ServeLoop:
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.copy_stream = torch.cuda.Stream()
         self.server = fbg.Server(max_programs=max_active, max_items=max_items, words_per_lane=self.W,
-                                 nbuf=2 * nstreams + 2)
+                                 nbuf=2 * nstreams + 2, cofactor=cofactor)
         self.cache = ProgramCache(cache_capacity, flags=fbg.compile_wpl(self.W))
 
     def run(self, requests, realtime=True, log=None):
@@ -197,8 +200,11 @@ class ServeLoop:
             oldest = inflight[0][0] if inflight else k
             ready = [r for r in issued if max(r.deps) < oldest]
             if ready:
+                # read back only the slots from the first ready one to the last
+                lo = min(r.slot for r in ready)
+                hi = max(r.slot for r in ready) + 1
                 with torch.cuda.stream(self.copy_stream):
-                    host_counts.copy_(counts, non_blocking=True)
+                    host_counts[lo:hi].copy_(counts[lo:hi], non_blocking=True)
                 self.copy_stream.synchronize()
                 hc = host_counts.numpy().view(np.uint64)
                 tt = now()
