@@ -753,7 +753,7 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="c4: requests in the timed run")
     ap.add_argument("--sat-requests", type=int, default=1000, help="c4: requests of the saturation run")
     ap.add_argument("--loads", default="0.3,0.6,0.9", help="c4: arrival rates as fractions of saturation")
-    ap.add_argument("--slice-words", type=float, default=4e10, help="c4: clause-word work per slice")
+    ap.add_argument("--slice-words", type=float, default=2.5e11, help="c4: clause-word work per slice")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: a formula's valuation space would be cut into contiguous "

@@ -367,8 +367,9 @@ fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_
  *   items per launch, nbuf launches in flight (pinned host and device buffers
  *   allocated here, once).  words_per_lane fixes the tile size; flags takes
  *   FBG_TUNE_COFACTOR.
- * fbg_server_launch -- upload the program table and the items (asynchronous,
- *   from pinned memory) and launch one persistent batched kernel on `stream`.
+ * fbg_server_launch -- upload the cleared queue heads, the program table and
+ *   the items (one asynchronous copy from pinned memory) and launch one
+ *   persistent batched kernel on `stream`.
  *   Items are cut into pieces of about equal estimated cost (at most
  *   max_items pieces in all) so that a few large requests still occupy
  *   every compute unit.

@@ -8,6 +8,7 @@ not been built, importing this module raises: there is no fallback.
 
 import ctypes
 import os
+import threading
 import weakref
 
 import numpy as np
@@ -67,6 +68,11 @@ TUNE_COFACTOR = 1
 class Item(ctypes.Structure):
     _fields_ = [("prog", ctypes.c_int32), ("slot", ctypes.c_int32), ("tile_begin", ctypes.c_uint64),
                 ("tile_end", ctypes.c_uint64)]
+
+
+# fbg_item as a numpy record: work items marshalled in one step
+ITEM_DTYPE = np.dtype([("prog", "<i4"), ("slot", "<i4"), ("tile_begin", "<u8"), ("tile_end", "<u8")])
+assert ITEM_DTYPE.itemsize == ctypes.sizeof(Item)
 
 
 def _load():
@@ -170,18 +176,21 @@ def _stream(stream):
 # was launched is not freed directly: free() records an event on every
 # stream it was launched on and parks the handle here; it is released once
 # all those events have completed (checked whenever objects are created or
-# freed).
+# freed).  Objects may be created and freed on several threads (a serving
+# loop compiles on a thread pool): the list changes only under _grave_lock,
+# and an entry is taken off it before it is released, so it is released once.
 _graveyard = []
+_grave_lock = threading.Lock()
 
 
 def _sweep():
-    keep = []
-    for release, events, keepalive in _graveyard:
-        if all(e.query() for e in events):
-            release()
-        else:
-            keep.append((release, events, keepalive))
-    _graveyard[:] = keep
+    with _grave_lock:
+        done, keep = [], []
+        for entry in _graveyard:
+            (done if all(e.query() for e in entry[1]) else keep).append(entry)
+        _graveyard[:] = keep
+    for release, _, _ in done:
+        release()
 
 
 def _release_after(streams, release, keepalive=()):
@@ -191,7 +200,8 @@ def _release_after(streams, release, keepalive=()):
         e = torch.cuda.Event()
         e.record(s)
         events.append(e)
-    _graveyard.append((release, events, tuple(keepalive)))
+    with _grave_lock:
+        _graveyard.append((release, events, tuple(keepalive)))
     _sweep()
 
 
@@ -401,12 +411,14 @@ class Server:
         self.max_items = int(max_items)
 
     def launch(self, progs, items, counts, stream=None):
-        """progs: list of Program; items: list of (prog index, slot, tile_begin,
-        tile_end); counts: int64 device tensor of slots (added to)."""
+        """progs: list of Program; items: (prog index, slot, tile_begin,
+        tile_end) tuples, or a numpy array of ITEM_DTYPE; counts: int64 device
+        tensor of slots (added to)."""
         arr = (ctypes.c_void_p * len(progs))(*[p.handle.value for p in progs])
-        its = (Item * len(items))(*[Item(int(a), int(b), int(c), int(d)) for a, b, c, d in items])
-        _check(lib.fbg_server_launch(self._h, arr, len(progs), its, len(items), _ptr(counts), counts.numel(),
-                                     _stream(stream)))
+        its = np.ascontiguousarray(np.asarray(items, dtype=ITEM_DTYPE) if not isinstance(items, np.ndarray)
+                                   else items.astype(ITEM_DTYPE, copy=False))
+        _check(lib.fbg_server_launch(self._h, arr, len(progs), its.ctypes.data_as(ctypes.POINTER(Item)), len(its),
+                                     _ptr(counts), counts.numel(), _stream(stream)))
         _used_on(progs, stream)
 
     def free(self):

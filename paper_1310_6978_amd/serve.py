@@ -97,12 +97,14 @@ class _Req:
 
 class ServeLoop:
     """The serving loop.  `slice_words` bounds the clause-word work of one
-    slice (a clause applied to one 32-bit word is one unit).  `cofactor`
+    slice (a clause applied to one 32-bit word is one unit): a longer slice
+    spreads the host's work per launch over more requests, a shorter one lets
+    a small request that arrives behind a large one finish sooner.  `cofactor`
     runs the slices with the uniform-cofactor test (a tile on which a clause
     made only of tile literals is false is skipped); counts are the same
     either way."""
 
-    def __init__(self, words_per_lane=16, slice_words=4e10, arena_bytes=4 << 30, max_active=256,
+    def __init__(self, words_per_lane=16, slice_words=2.5e11, arena_bytes=4 << 30, max_active=256,
                  max_items=16384, nstreams=2, cache_capacity=64, cofactor=True):
         import torch
         self.torch = torch

@@ -36,6 +36,45 @@ def test_request_stream_is_seeded_and_poisson():
     assert request_stream(5, 0.0)[-1]["arrival"] == 0.0
 
 
+def test_deferred_release_runs_once_across_threads():
+    # compile threads and the loop's thread sweep the deferred-release list
+    # together; every entry must be released exactly once
+    import collections
+    import threading
+    import time
+    from paper_1310_6978_amd import fbg
+
+    class Done:
+        def query(self):
+            return True
+
+    calls = collections.Counter()
+    lock = threading.Lock()
+
+    def release(i):
+        time.sleep(0)                # let another thread run mid-release
+        with lock:
+            calls[i] += 1
+
+    with fbg._grave_lock:
+        for i in range(3000):
+            fbg._graveyard.append((lambda i=i: release(i), [Done()], ()))
+    start = threading.Barrier(8)
+
+    def work():
+        start.wait()
+        for _ in range(20):
+            fbg._sweep()
+
+    threads = [threading.Thread(target=work) for _ in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not fbg._graveyard
+    assert calls == collections.Counter(range(3000))
+
+
 @pytest.mark.gpu
 def test_mixed_requests_match_alone_and_oracle():
     import numpy as np
