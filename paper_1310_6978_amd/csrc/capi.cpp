@@ -869,7 +869,11 @@ fbg_status fbg_batch_create(const fbg_program *const *ps, int32_t np, const fbg_
       const fbg::BatchProg &q = b->host_progs[(size_t)i];
       const double per_tile = tile_cost(ps[i], l);
       const uint64_t chunk = (uint64_t)std::max(1.0, target / per_tile);
-      const uint64_t K = (q.ntiles + chunk - 1) / chunk;
+      uint64_t K = (q.ntiles + chunk - 1) / chunk;
+      // with the uniform cofactor an odd K: the tiles that survive its test
+      // often share their low index bits, and an even (above all a
+      // power-of-two) K would give them to a few items
+      if ((var & 2) && K > 1 && K < q.ntiles && !(K & 1)) K++;
       for (uint64_t k = 0; k < K; k++) {
         fbg::BatchItem it;
         it.prog = (uint32_t)i;
@@ -1300,26 +1304,47 @@ fbg_status fbg_server_launch(fbg_server *sv, const fbg_program *const *ps, int32
   // Cut the items into pieces of about equal estimated cost (tile_cost per
   // tile) so that every resident wave gets about four, within the staging
   // capacity: an item of c tiles at cost w each gives ceil(c / ceil(T / w)) <=
-  // c w / T + 1 pieces for a target T, so want + nitems <= max_items in all
-  // (checked below all the same).  (Sorting the pieces by cost as the batch
-  // plans do cost more host time per slice than it saved.)
+  // c w / T + 1 pieces for a target T (one more with the uniform cofactor,
+  // below), so want + 2 nitems <= max_items in all (checked below all the
+  // same).  (Sorting the pieces by cost as the batch plans do cost more host
+  // time per slice than it saved.)
   double total = 0;
   for (int32_t k = 0; k < nitems; k++)
     total += (double)(items[k].tile_end - items[k].tile_begin) * tile_cost(ps[items[k].prog], l);
-  const uint64_t room = (uint64_t)(sv->max_items - nitems);
+  const int64_t spare = (int64_t)sv->max_items - (sv->cofactor ? 2 : 1) * (int64_t)nitems;
+  const uint64_t room = (uint64_t)std::max<int64_t>(0, spare);
   const uint64_t want = std::min<uint64_t>(room, (uint64_t)cus * occ * wpb * 4);
   const double target = want > 0 ? total / (double)want * (1.0 + 1e-9) : 0.0;
+  // With the uniform cofactor an item's P pieces interleave (piece j takes
+  // tiles j, j + P, ... of it) with P odd: the tiles that survive the test
+  // often share index bits, and contiguous pieces, or an even stride, would
+  // give them to a few pieces.
   int32_t npieces = 0;
   for (int32_t k = 0; k < nitems; k++) {
     const double w = tile_cost(ps[items[k].prog], l);
     const uint64_t chunk = want > 0 ? std::max<uint64_t>(1, (uint64_t)std::ceil(target / w)) : ~0ull;
-    for (uint64_t t = items[k].tile_begin; t < items[k].tile_end; t += std::min(chunk, items[k].tile_end - t)) {
+    const uint64_t b = items[k].tile_begin, e = items[k].tile_end;
+    if (sv->cofactor && e - b > chunk) {
+      uint64_t P = (e - b + chunk - 1) / chunk;
+      if (!(P & 1) && P < e - b) P++;
+      for (uint64_t j = 0; j < P; j++) {
+        if (npieces >= sv->max_items) return fail(FBG_E_INVAL, "internal: more pieces than staging room");
+        fbg::BatchItem &q = hi[npieces++];
+        q.prog = (uint32_t)items[k].prog;
+        q.slot = (uint32_t)items[k].slot;
+        q.t0 = b + j;
+        q.t1 = e;
+        q.step = P;
+      }
+      continue;
+    }
+    for (uint64_t t = b; t < e; t += std::min(chunk, e - t)) {
       if (npieces >= sv->max_items) return fail(FBG_E_INVAL, "internal: more pieces than staging room");
       fbg::BatchItem &q = hi[npieces++];
       q.prog = (uint32_t)items[k].prog;
       q.slot = (uint32_t)items[k].slot;
       q.t0 = t;
-      q.t1 = t + std::min(chunk, items[k].tile_end - t);
+      q.t1 = t + std::min(chunk, e - t);
       q.step = 1;
     }
   }

@@ -992,7 +992,7 @@ int pattern_entry(std::vector<uint32_t> &pats, uint32_t pat) {
 // in-word part (multi).  kind: 0 static, 1 the first multi chunk (its keys
 // act inside the product tree), 2 a later multi chunk (after the tree).
 void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, int kind, int log2w,
-                std::vector<uint32_t> &pats, bool first, std::vector<uint32_t> &out) {
+                std::vector<uint32_t> &pats, std::vector<uint32_t> &out) {
   const uint32_t nc = (uint32_t)(hi - lo);
   const int W = 1 << log2w;
   const size_t base = out.size();
@@ -1003,14 +1003,12 @@ void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, int ki
   out.resize(lanes + 64, nc == FBG_CB_CHUNK ? 0u : ~0u << nc);
   for (uint32_t c = 0; c < nc; c++)
     for (uint64_t m = cl[lo + c].s.lanemask; m; m &= m - 1) out[lanes + (size_t)__builtin_ctzll(m)] |= 1u << c;
-  uint32_t tmask = 0;
   for (uint32_t c = 0; c < nc; c++) {
     const SetWords &s = cl[lo + c].s;
     out.push_back((uint32_t)s.sel);
     out.push_back((uint32_t)(s.sel >> 32));
     out.push_back((uint32_t)s.neg);
     out.push_back((uint32_t)(s.neg >> 32));
-    if (cl[lo + c].tile_only) tmask |= 1u << c;
   }
   // runs of equal keys; a run [a, b) has its top bit b - 1 in T and the bits
   // below it in F
@@ -1056,7 +1054,6 @@ void emit_chunk(const std::vector<BlockClause> &cl, size_t lo, size_t hi, int ki
   out.insert(out.end(), keys.begin(), keys.end());
   out[base + 2] = T;
   out[base + 3] = F;
-  if (kind == 0 && first) out[base + 4] = tmask;
   // end of each slot's keys, in bytes from the chunk start
   uint32_t end = (uint32_t)(FBG_CB_CHUNK_HDR + 64 + 4 * nc) * 4u;
   for (int sl = 0; sl < nslots; sl++) {
@@ -1399,9 +1396,22 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
   std::vector<uint32_t> block(FBG_CB_HDR, 0u);
   uint32_t nstat = 0, nmulti = 0;
   for (size_t lo = 0; lo < stat.size(); lo += FBG_CB_CHUNK, nstat++)
-    emit_chunk(stat, lo, std::min(stat.size(), lo + FBG_CB_CHUNK), 0, log2w, pats, lo == 0, block);
+    emit_chunk(stat, lo, std::min(stat.size(), lo + FBG_CB_CHUNK), 0, log2w, pats, block);
   for (size_t lo = 0; lo < multi.size(); lo += FBG_CB_CHUNK, nmulti++)
-    emit_chunk(multi, lo, std::min(multi.size(), lo + FBG_CB_CHUNK), lo == 0 ? 1 : 2, log2w, pats, false, block);
+    emit_chunk(multi, lo, std::min(multi.size(), lo + FBG_CB_CHUNK), lo == 0 ? 1 : 2, log2w, pats, block);
+  // the uniform-cofactor table: the tile selectors of every clause made only
+  // of tile literals, at the end of the block; its length in the first
+  // static chunk's h[4] (such clauses are static, so that chunk exists)
+  uint32_t ncof = 0;
+  for (const BlockClause &b : stat) {
+    if (!b.tile_only) continue;
+    block.push_back((uint32_t)b.s.sel);
+    block.push_back((uint32_t)(b.s.sel >> 32));
+    block.push_back((uint32_t)b.s.neg);
+    block.push_back((uint32_t)(b.s.neg >> 32));
+    ncof++;
+  }
+  if (nstat > 0) block[FBG_CB_HDR + 4] = ncof;
   block[0] = (uint32_t)block.size();
   block[1] = nstat;
   block[2] = nmulti;
@@ -1623,8 +1633,8 @@ std::string disasm_program(const std::vector<uint32_t> &words, uint32_t nins, in
     const int kind = k < cb[1] ? 0 : k == cb[1] ? 1 : 2;
     static const char *kinds[] = {"static", "multi-tree", "multi"};
     const uint32_t nc = ch[0];
-    snprintf(buf, sizeof buf, "chunk %u %s clauses=%u tile_only=%08x tops=%08x fill=%08x\n", k, kinds[kind], nc,
-             kind == 0 ? ch[4] : 0u, ch[2], ch[3]);
+    snprintf(buf, sizeof buf, "chunk %u %s clauses=%u cofactor=%u tops=%08x fill=%08x\n", k, kinds[kind], nc,
+             k == 0 && kind == 0 ? ch[4] : 0u, ch[2], ch[3]);
     out += buf;
     const uint32_t *td = ch + FBG_CB_CHUNK_HDR + 64;
     for (uint32_t c = 0; c < nc; c++) {
@@ -1742,6 +1752,15 @@ uint32_t clause_block_value(const uint32_t *cb, const uint32_t *table, int log2w
   uint32_t G[1 + 2 * 5];
   for (uint32_t &g : G) g = ~0u;
   const uint32_t *ch = cb + FBG_CB_HDR;
+  if (cof && cb[1] > 0) {  // the uniform-cofactor table at the end of the block
+    const uint32_t ncof = ch[4];
+    const uint32_t *td = cb + cb[0] - 4 * ncof;
+    for (uint32_t c = 0; c < ncof; c++) {
+      const uint64_t sel = (uint64_t)td[4 * c] | ((uint64_t)td[4 * c + 1] << 32);
+      const uint64_t neg = (uint64_t)td[4 * c + 2] | ((uint64_t)td[4 * c + 3] << 32);
+      if ((U0 & sel) == neg) return 0u;
+    }
+  }
   uint32_t extra = ~0u;  // the multi keys' factors of word i
   for (uint32_t k = 0; k < cb[1] + cb[2]; k++) {
     const int kind = k < cb[1] ? 0 : k == cb[1] ? 1 : 2;
@@ -1753,7 +1772,6 @@ uint32_t clause_block_value(const uint32_t *cb, const uint32_t *table, int log2w
       const uint64_t neg = (uint64_t)td[4 * c + 2] | ((uint64_t)td[4 * c + 3] << 32);
       if ((U0 & sel) != neg) S |= 1u << c;
     }
-    if (cof && k == 0 && (S & ch[4]) != ch[4]) return 0u;
     const uint32_t U = ~(ch[FBG_CB_CHUNK_HDR + lane] | S);
     // the clauses of a key are the run of bits ending at its top bit, after
     // the previous key's top bit

@@ -377,17 +377,17 @@ __device__ __forceinline__ void run_clauses(const uint32_t *__restrict__ cb_g, c
 // The uniform-cofactor test of one tile (lane-parallel: each lane may ask
 // about another tile): 0 when a clause made only of tile literals is false on
 // the whole tile, which makes the program false there (acc only loses bits
-// after the clause block), else 1.  The encoder puts those clauses first in
-// the first chunk and marks them in its h[4]; their selectors are read as
-// scalars.  Every lane runs it (no divergent branch around it), and the
-// result is a 0/1 word, not a lane-mask boolean.
+// after the clause block), else 1.  The encoder lists the tile selectors of
+// every such clause in a table at the end of the clause block, its length in
+// the first static chunk's h[4]; they are read as scalars.  Every lane runs
+// it (no divergent branch around it), and the result is a 0/1 word, not a
+// lane-mask boolean.
 template <int LOG2W>
 __device__ __forceinline__ uint32_t tile_alive(const uint32_t *__restrict__ cb_g, uint64_t t) {
   const code_ptr cb = (code_ptr)cb_g;
   if (cb[1] == 0) return 1u;
-  const code_ptr h = cb + FBG_CB_HDR;
-  const uint32_t k = __popc(h[4]);  // a prefix of the first chunk
-  const code_ptr td = h + FBG_CB_CHUNK_HDR + 64;
+  const uint32_t k = cb[FBG_CB_HDR + 4];
+  const code_ptr td = cb + cb[0] - 4 * k;
   const uint64_t U0 = t << LOG2W;
   uint32_t dead = 0u;
   for (uint32_t c = 0; c < k; ++c) {
@@ -399,28 +399,56 @@ __device__ __forceinline__ uint32_t tile_alive(const uint32_t *__restrict__ cb_g
   return dead ^ 1u;
 }
 
+// A bijection of [0, n): cycle-walking over a bijection of the bits-bit
+// integers (2^bits >= n > 2^(bits - 1), mask = 2^bits - 1), two rounds of an
+// xor-shift (invertible for a shift >= 1) and a multiplication by an odd
+// constant (invertible modulo 2^bits).  The walk from x < n ends: following
+// the permutation's cycle through x returns to x.
+__device__ __forceinline__ uint64_t tile_hash(uint64_t x, uint64_t n, uint32_t bits, uint64_t mask) {
+  const uint32_t h = bits > 1 ? bits >> 1 : 1u;
+  do {
+    x = ((x ^ (x >> h)) * 0x9E3779B97F4A7C15ull) & mask;
+    x = ((x ^ (x >> h)) * 0xD6E8FEB86659FD93ull) & mask;
+    x ^= x >> h;
+  } while (x >= n);
+  return x;
+}
+
 // Visit the tiles first, first + stride, ... below end.  body(t, alive):
 // alive = false means the tile is known to be all zeros (uniform cofactor)
 // and need not be evaluated.  With COF the wave tests the next 64 tiles at
 // once, one per lane, and visits only the live ones, or (ALL) every tile,
 // the dead ones with alive = false.  Lanes past the end test some tile
-// beyond it; the valid mask removes them.
-template <int LOG2W, bool COF, bool ALL, typename Body>
+// beyond it; the valid mask removes them.  With HASH (COF only: a launch in
+// which wave w of nw visits w, w + nw, ... of the tiles [0, end)) the k-th
+// tile a wave visits is tile_hash of that index instead: the tiles that
+// survive the test often share their low index bits, and a power-of-two
+// stride would give them all to a few waves.
+template <int LOG2W, bool COF, bool ALL, bool HASH = false, typename Body>
 __device__ __forceinline__ void for_tiles(const uint32_t *__restrict__ code, uint64_t first, uint64_t stride,
                                           uint64_t end, uint32_t lane, Body &&body) {
   if (!COF) {
     for (uint64_t t = first; t < end; t += stride) body(t, true);
     return;
   }
+  uint32_t bits = 0;
+  if (HASH)
+    while ((1ull << bits) < end) bits++;
+  const uint64_t mask = bits >= 64 ? ~0ull : (1ull << bits) - 1;
   for (uint64_t q0 = 0; first + q0 * stride < end; q0 += 64) {
-    const uint64_t tl = first + (q0 + lane) * stride;
-    const uint64_t valid = __ballot(tl < end);
+    const uint64_t il = first + (q0 + lane) * stride;
+    const uint64_t valid = __ballot(il < end);
+    const uint64_t tl = HASH && il < end ? tile_hash(il, end, bits, mask) : il;
     const uint64_t alive = __ballot(tile_alive<LOG2W>(code, tl) != 0u) & valid;
     uint64_t todo = ALL ? valid : alive;
     while (todo) {
       const uint32_t l = (uint32_t)__builtin_ctzll(todo);
       todo &= todo - 1;
-      body(first + (q0 + l) * stride, ((alive >> l) & 1ull) != 0);
+      // lane l's tile, read as a scalar (l is wave-uniform)
+      const uint64_t t = HASH ? (uint64_t)__builtin_amdgcn_readlane((uint32_t)tl, l) |
+                                    (uint64_t)__builtin_amdgcn_readlane((uint32_t)(tl >> 32), l) << 32
+                              : first + (q0 + l) * stride;
+      body(t, ((alive >> l) & 1ull) != 0);
     }
   }
 }
@@ -657,7 +685,7 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
   // dead tiles (uniform cofactor) still write their zeros in DNF and
   // tile-count modes; counting and compaction skip them
   constexpr bool ALL = MODE == MODE_DNF || MODE == MODE_TILECNT;
-  for_tiles<LOG2W, (VAR & 2) != 0, ALL>(a.code, wave, nwaves, a.ntiles, lane, [&](uint64_t t, bool alive) {
+  for_tiles<LOG2W, (VAR & 2) != 0, ALL, true>(a.code, wave, nwaves, a.ntiles, lane, [&](uint64_t t, bool alive) {
     const uint64_t U0 = t << LOG2W;
     if (MODE == MODE_ENUM) {
       if (a.tile_counts[t] == 0u) return;  // no model in this tile

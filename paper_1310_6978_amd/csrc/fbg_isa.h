@@ -70,8 +70,8 @@
  *   then the chunks (static ones first), each:
  *     h[0] clauses nc (1 .. FBG_CB_CHUNK)   h[1] chunk size in words
  *     h[2] T   h[3] F
- *     h[4] first static chunk only: the clauses made of tile literals alone
- *          (the encoder puts them first)
+ *     h[4] first static chunk only: the length of the uniform-cofactor
+ *          table
  *     h[5 ..] end of each slot's keys, in bytes from the chunk start; slots
  *          are the groups 0 .. 2 log2 W (static), the (level j, half v)
  *          pairs 2 (j - 1) + v (first multi chunk), or one (later ones)
@@ -80,6 +80,10 @@
  *     pattern of the first multi chunk's keys over the 2^j nodes of their
  *     half
  *     zero padding to a multiple of 4 words
+ *   then the uniform-cofactor table, the last 4 h[4] words of the block:
+ *   (sel lo, sel hi, neg lo, neg hi) of every clause made only of tile
+ *   literals (such a clause is constant on a tile; where it is false the
+ *   whole tile is)
  *
  * Instruction: 8 x uint32.
  *   w0 bits 0..3   opcode

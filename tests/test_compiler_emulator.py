@@ -239,10 +239,11 @@ def test_autotune_cache_keys(tmp_path):
     assert autotune.Tuner(path=str(tmp_path / "t.json")).table[k]["words_per_lane"] == 8
 
 
-def test_tile_only_clauses_lead_the_block():
-    """At every tiling the clauses made only of tile variables come first in
-    the first chunk, and its header marks exactly them (the uniform-cofactor
-    kernels then drop a dead tile before any other work)."""
+def test_tile_only_clauses_fill_the_cofactor_table():
+    """At every tiling the uniform-cofactor table at the end of the clause
+    block lists every clause made only of tile variables, once (the
+    uniform-cofactor kernels drop a tile on which one of them is false before
+    any other work), and the emulated cofactor reading equals the oracle."""
     text, n = workloads.random_3cnf(32, 136, 4)
     clauses = set()
     for part in text.splitlines():
@@ -253,10 +254,27 @@ def test_tile_only_clauses_lead_the_block():
         tile_bit = 11 + w.bit_length() - 1
         want = sum(all(int(l.lstrip("~")[1:]) >= tile_bit for l in c) for c in clauses)
         first = [l for l in p.disasm(w).splitlines() if l.startswith("chunk 0 ")][0]
-        mask = int(first.split("tile_only=")[1].split()[0], 16)
-        k = bin(mask).count("1")
-        assert mask == (1 << k) - 1 and k == min(want, 32), (w, want, mask)
+        k = int(first.split("cofactor=")[1].split()[0])
+        assert k == want > 32 if w == 1 else k == want, (w, want, k)
     check("(x0|x1) & (x22|~x23) & (x2|x12) & ~x21 & (x18|x20)", 24, wpl=[1, 32])
+    # more tile-only clauses than one chunk holds (40 on variables 11..19),
+    # read by the emulated uniform-cofactor kernels
+    rng = random.Random(5)
+    parts = set()
+    while len(parts) < 40:
+        vs = sorted(rng.sample(range(11, 20), 2))
+        parts.add(" | ".join(("~x%d" if rng.random() < 0.5 else "x%d") % v for v in vs))
+    parts = sorted(parts) + ["x0 | ~x12 | x3", "~x5 | x15", "x9 | x10"]
+    text = " & ".join("(%s)" % c for c in parts)
+    p = fbg.Program(text, 20)
+    assert int([l for l in p.disasm(1).splitlines() if l.startswith("chunk 0 ")][0]
+               .split("cofactor=")[1].split()[0]) == 40
+    want = oracle.count(text, 20)
+    for w in (1, 2, 8):
+        p.set_tuning(w, cofactor=True)
+        dnf, cnt = p.emulate(w)
+        assert cnt == want, (w, cnt, want)
+        assert np.array_equal(dnf, oracle.dnf(text, 20)), w
 
 
 def test_clause_groups_by_word_literals():
