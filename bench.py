@@ -74,7 +74,7 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # (their code, comments left out) the counters were taken on.  The bench line
 # reports the bytes only while the sources still have that digest, and null
 # otherwise.
-C1_TRAFFIC = {"bytes": 8606027510, "kernel_sources_sha1": "6d4b5d859e555a8de89b4b6e2bf5d56f26faa5b2"}
+C1_TRAFFIC = {"bytes": 8605967872, "kernel_sources_sha1": "487380b2af7312c95c80b2432adee6cd03d3edfa"}
 KERNEL_SOURCES = ("fbg_device.h", "fbg_asm16.h", "fbg_isa.h", "fbg_kernels.h", "batch.hip")
 
 
@@ -430,8 +430,9 @@ def bench_c4(args, torch, fbg):
     """Serving: Poisson arrivals of model-counting requests (90% random 3-CNF
     with n uniform in [12,36] and ratio 4.25, 10% the theories of the k=9
     equivalence, 5x5 permutation and k=8 triangle-free workloads), continuous
-    batching.  First the saturation rate is measured with every request
-    arriving at once; then one timed run per load level, arrivals at that
+    batching.  First a burst (every request arriving at once), then the
+    saturation rate: the rate served while real-time arrivals come at 1.25 x
+    the burst rate; then one timed run per load level, arrivals at that
     fraction of the saturation rate.  Results are checked against the
     theories' closed forms and against the stored oracle counts of the
     stream's 3-CNF requests with n <= 20 (tests/golden/c4_requests.json)."""
@@ -444,8 +445,16 @@ def bench_c4(args, torch, fbg):
     loop = ServeLoop(words_per_lane=16, slice_words=args.slice_words, max_active=256)
     warm = request_stream(50, 0.0, seed=99)
     loop.run(warm, realtime=False, log=log)
-    log("c4: saturation run, %d requests at once" % args.sat_requests)
-    sat = loop.run(request_stream(args.sat_requests, 0.0, seed=1), realtime=False, log=log)
+    log("c4: burst run, %d requests at once" % args.sat_requests)
+    burst = loop.run(request_stream(args.sat_requests, 0.0, seed=1), realtime=False, log=log)
+    # Requests that are all there at once batch better than arrivals spread
+    # in time, so the burst rate overstates what the loop sustains: the
+    # saturation rate is the rate served while real-time arrivals come faster
+    # than that (1.25 x the burst rate), and the load levels are fractions of it.
+    over = 1.25 * burst["requests_per_s"]
+    log("c4: burst %.1f req/s; overload run, %d requests at %.1f req/s" % (burst["requests_per_s"],
+                                                                          args.sat_requests * 4, over))
+    sat = loop.run(request_stream(args.sat_requests * 4, over, seed=2), realtime=True, log=log)
     rate = sat["requests_per_s"]
     closed = {"equivalence_k9": 21147, "permutations_k5": 120, "triangle_free_k8": 4682270}
     with open(os.path.join(ROOT, "tests", "golden", "c4_requests.json")) as f:
@@ -484,6 +493,8 @@ def bench_c4(args, torch, fbg):
                                "permutations, triangle-free k=8)" % (args.requests, args.loads),
                    "requests": args.requests, "loads": args.loads},
         "serving": {"saturation_requests_per_s": rate, "saturation_valuations_per_s": sat["valuations_per_s"],
+                    "saturation_offered_requests_per_s": over,
+                    "burst_requests_per_s": burst["requests_per_s"], "burst_valuations_per_s": burst["valuations_per_s"],
                     "runs": runs},
         "bit_exact_vs_oracle": ok, "requests_checked": checked,
     }
@@ -751,7 +762,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="c1: leave out the 4096-formula batch block")
     ap.add_argument("--requests", type=int, default=20000, help="c4: requests in the timed run")
-    ap.add_argument("--sat-requests", type=int, default=1000, help="c4: requests of the saturation run")
+    ap.add_argument("--sat-requests", type=int, default=1000, help="c4: requests of the burst run (the overload run takes 4 x as many)")
     ap.add_argument("--loads", default="0.3,0.6,0.9", help="c4: arrival rates as fractions of saturation")
     ap.add_argument("--slice-words", type=float, default=2.5e11, help="c4: clause-word work per slice")
     args = ap.parse_args()
