@@ -580,19 +580,31 @@ def bench_theories(args, torch, fbg):
         best_total += best
         # every model listed (two passes: tile counts and scan, then the
         # compaction of the tiles that hold models), at the library's tiling
+        # (then again with the uniform cofactor at the same tiling: the same
+        # list, element by element)
         cap = want
-        idx, tot = fbg.enumerate_models(p, cap, stream=stream)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(args.steps):
-            fbg.enumerate_models(p, cap, out=idx, total=tot, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ok = ok and int(tot.cpu().numpy().view("uint64")[0]) == want
-        enum_rows.append({"theory": name, "models": want, "ms": a.elapsed_time(b) / args.steps,
-                          "list_bytes": 8 * want})
+        first = None
+        for cof in (False, True):
+            if cof:
+                p.set_tuning(p.info["words_per_lane"], cofactor=True)
+            idx, tot = fbg.enumerate_models(p, cap, stream=stream)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                fbg.enumerate_models(p, cap, out=idx, total=tot, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ok = ok and int(tot.cpu().numpy().view("uint64")[0]) == want
+            got = idx[:want].cpu()
+            if first is None:
+                first = got
+            else:
+                ok = ok and bool(torch.equal(got, first))
+            enum_rows.append({"theory": name, "models": want, "cofactor": cof,
+                              "words_per_lane": p.info["words_per_lane"], "ms": a.elapsed_time(b) / args.steps,
+                              "list_bytes": 8 * want})
     return {"metric": "valuations/s of one full-evaluation count per theory (best tiling)",
             "value": vals / (best_total / 1e3), "unit": "valuations/s", "ms_per_step": best_total, "dtype": "u32",
             "config": {"workload": "propositional theories: equivalence k=9 and k=6, triangle-free k=8, "
