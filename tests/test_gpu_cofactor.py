@@ -118,3 +118,84 @@ def test_batch_and_server(F):
     sv.launch(progs, items, counts)
     assert host(counts).tolist() == want
     sv.free()
+
+
+def many_tile_clauses(n, lo, count, seed):
+    """count distinct 3-clauses over the tile variables lo .. n-1, each true
+    under one planted assignment (so some tiles live), then clauses that
+    reach the in-word, lane and word variables."""
+    rng = random.Random(seed)
+    plant = {v: rng.random() < 0.5 for v in range(lo, n)}
+    parts = set()
+    while len(parts) < count:
+        vs = sorted(rng.sample(range(lo, n), 3))
+        keep = rng.choice(vs)                   # this literal holds under the plant
+        lits = []
+        for v in vs:
+            neg = (not plant[v]) if v == keep else rng.random() < 0.5
+            lits.append(("~x%d" if neg else "x%d") % v)
+        parts.add(" | ".join(lits))
+    parts = sorted(parts) + ["x0 | ~x%d | x3" % (lo + 1), "~x5 | x%d" % (n - 1), "x9 | x12 | ~x14"]
+    return " & ".join("(%s)" % c for c in parts)
+
+
+def test_more_tile_clauses_than_a_chunk(F):
+    # 48 tile-only clauses at 32 words per lane (tile variables 16 .. 24),
+    # more at smaller tilings: the test reads all of them from the block's
+    # table; tiles visited in hashed order (single-program launches) and
+    # interleaved pieces (batch, server) must still cover every tile once
+    import torch
+    n = 25
+    text = many_tile_clauses(n, 16, 48, 9)
+    p, total = cof_check(F, text, n)
+    assert 0 < total < (1 << n) // 20           # most valuations are not models
+    want, _ = oracle.models(text, n)
+    for w in (1, 16, 32):
+        p.set_tuning(w, cofactor=True)
+        idx, tot = F.enumerate_models(p, total + 5)
+        assert int(host(tot)[0]) == total
+        assert np.array_equal(host(idx)[:total], want), w
+    other = F.Program(workloads.random_3cnf(20, 85, 3)[0], 20)
+    progs = [p, other, p]
+    cnts = [total, oracle.count(*workloads.random_3cnf(20, 85, 3)), total]
+    for wpl in (1, 8, 32):
+        b = F.Batch(progs, words_per_lane=wpl, cofactor=True)
+        assert host(b.count()).tolist() == cnts, wpl
+    for wpl in (1, 16):
+        sv = F.Server(len(progs), 256, wpl, nbuf=2, cofactor=True)
+        counts = torch.zeros(len(progs), dtype=torch.int64, device="cuda")
+        nt = F.program_tiles(p, wpl)
+        # one request split over two launches, the second from an odd tile
+        items = [(0, 0, 0, nt // 3), (1, 1, 0, F.program_tiles(other, wpl)), (2, 2, 0, nt)]
+        sv.launch(progs, items, counts)
+        sv.launch(progs[:1], [(0, 0, nt // 3, nt)], counts)
+        assert host(counts).tolist() == cnts, wpl
+        sv.free()
+
+
+def test_c2a_equivalence_k9_with_cofactor(F):
+    # 90 tile-only clauses at 32 words per lane, 105 at 16; most tiles dead
+    path = os.path.join(GOLDEN, "c2_theories.json")
+    with open(path) as f:
+        g = json.load(f)["equivalence_k9"]
+    text, n = workloads.equivalence_relations(9)
+    p = F.Program(text, n)
+    for w in (8, 16, 32):
+        assert int(host(F.count(p, words_per_lane=w, cofactor=True))[0]) == 21147 == g["count"], w
+    for w in (16, 32):
+        p.set_tuning(w, cofactor=True)
+        idx, tot = F.enumerate_models(p, 30000)
+        assert int(host(tot)[0]) == 21147
+        assert host(idx)[:21147].tolist() == g["models"], w
+
+
+def test_c2c_triangle_free_with_cofactor(F):
+    import hashlib
+    with open(os.path.join(GOLDEN, "c2_theories.json")) as f:
+        g = json.load(f)["triangle_free_k8"]
+    text, n = workloads.triangle_free(8)
+    p = F.Program(text, n)
+    p.set_tuning(16, cofactor=True)
+    idx, tot = F.enumerate_models(p, g["count"])
+    assert int(host(tot)[0]) == g["count"]
+    assert hashlib.sha256(host(idx)[:g["count"]].astype("<u8").tobytes()).hexdigest() == g["models_sha256"]
