@@ -3,12 +3,17 @@
 The evaluator's cost per clause per tile is a fixed scalar part (instruction
 fetch, the lane and tile parts of the literal set) plus one VALU operation
 per word, so more words per lane amortise the fixed part, while fewer words
-per lane give small valuation spaces more tiles (and so more waves).  The
-tuner times fbg_count on the candidate tilings with HIP events, keeps the
-fastest, and caches the choice per (device architecture, n, program-size
-bucket, clause-only or not) in a JSON file (FBG_TUNE_CACHE, default
+per lane give small valuation spaces more tiles (and so more waves).  For a
+program with clauses the uniform-cofactor test is a second dimension: it
+skips every tile on which a clause made only of tile variables is false,
+which pays where such clauses kill most tiles (the theories) and costs a
+little where they do not.  The tuner times fbg_count on the candidate
+tilings, with and without the test, with HIP events, keeps the fastest, and
+caches the choice per (device architecture, n, program-size bucket,
+clause-only or not) in a JSON file (FBG_TUNE_CACHE, default
 ~/.cache/fbg/tune.json).  It then makes the choice the program's default
-through fbg_program_set_tuning.
+through fbg_program_set_tuning (counts, DNF vectors and enumerations then use
+it; results are the same either way).
 """
 
 import hashlib
@@ -55,38 +60,44 @@ class Tuner:
                 self.table = {}
 
     def measure(self, prog):
-        """{words_per_lane: ms} for one count of `prog` at each candidate."""
+        """{(words_per_lane, cofactor): ms} for one count of `prog` at each
+        candidate (the cofactor only for programs with clauses)."""
         import torch
         out = torch.empty(1, dtype=torch.int64, device="cuda")
         res = {}
+        cofs = (False, True) if int(prog.info["n_clause_instr"]) > 0 else (False,)
         for w in self.candidates:
-            try:
-                fbg.count(prog, out=out, words_per_lane=w)  # warm-up
-            except fbg.FbgError:
-                continue  # registers do not fit at this tiling
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(self.reps):
-                fbg.count(prog, out=out, words_per_lane=w)
-            b.record()
-            torch.cuda.synchronize()
-            res[w] = a.elapsed_time(b) / self.reps
+            for cof in cofs:
+                try:
+                    fbg.count(prog, out=out, words_per_lane=w, cofactor=cof)  # warm-up
+                except fbg.FbgError:
+                    break  # registers do not fit at this tiling
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(self.reps):
+                    fbg.count(prog, out=out, words_per_lane=w, cofactor=cof)
+                b.record()
+                torch.cuda.synchronize()
+                res[(w, cof)] = a.elapsed_time(b) / self.reps
         return res
 
     def apply(self, prog, save=True):
-        """Set the program's default tiling from the cache, measuring on a miss.
-        Returns the chosen words per lane."""
+        """Set the program's default tiling and cofactor choice from the cache,
+        measuring on a miss.  Returns the chosen words per lane."""
         k = key_of(prog)
-        w = self.table.get(k, {}).get("words_per_lane")
+        entry = self.table.get(k, {})
+        w = entry.get("words_per_lane")
+        cof = bool(entry.get("cofactor", False))
         if w is None:
             times = self.measure(prog)
-            w = min(times, key=times.get)
-            self.table[k] = {"words_per_lane": w, "ms": times}
+            w, cof = min(times, key=times.get)
+            self.table[k] = {"words_per_lane": w, "cofactor": cof,
+                             "ms": {"%d%s" % (x, "c" if c else ""): t for (x, c), t in times.items()}}
             if save:
                 self.save()
-        prog.set_tuning(w)
+        prog.set_tuning(w, cofactor=cof)
         return w
 
     def tune_batch(self, progs, candidates=(0, 4, 8, 16, 32), save=True):

@@ -405,7 +405,17 @@ def test_autotuner_choice_is_exact(F, tmp_path):
     w = t.apply(p)
     assert w in autotune.CANDIDATES and p.info["words_per_lane"] == w
     assert gpu_count(F, p) == oracle.count(text, n)
-    assert t.table[autotune.key_of(p)]["ms"]
+    entry = t.table[autotune.key_of(p)]
+    assert len(entry["ms"]) == 2 * len(autotune.CANDIDATES)      # with and without the cofactor test
+    m, tot = gpu_models(F, p, 1 << 16)                           # the enumeration takes the choice too
+    want, total = oracle.models(text, n)
+    assert tot == total and np.array_equal(m[:total], want)
+    # the theory whose tile-only clauses kill most tiles: the cofactor wins
+    eq, ne = workloads.equivalence_relations(9)
+    q = F.Program(eq, ne)
+    t.apply(q)
+    assert t.table[autotune.key_of(q)]["cofactor"] is True
+    assert gpu_count(F, q) == 21147                              # Bell number B_9
 
 
 def test_batch_eval_dnf_writes_every_vector(F):
