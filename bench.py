@@ -74,7 +74,7 @@ PAPER_CONTEXT = {"valuations_per_s": 2.0 ** 30, "node_bit_ops_per_s": 2.0 ** 47,
 # (their code, comments left out) the counters were taken on.  The bench line
 # reports the bytes only while the sources still have that digest, and null
 # otherwise.
-C1_TRAFFIC = {"bytes": 8605967872, "kernel_sources_sha1": "487380b2af7312c95c80b2432adee6cd03d3edfa"}
+C1_TRAFFIC = {"bytes": 8606066816, "kernel_sources_sha1": "f9c1039855fcdb7cf1166deeffbccc7ce8e7d404"}
 KERNEL_SOURCES = ("fbg_device.h", "fbg_asm16.h", "fbg_isa.h", "fbg_kernels.h", "batch.hip")
 
 

@@ -390,10 +390,13 @@ size_t enum_temp_bytes(uint64_t nt, size_t *bytes_cnt, size_t *bytes_off) {
 
 // Two-pass enumeration given the pass launcher and the temporaries `tmp`
 // (enum_temp_bytes(a.ntiles) bytes of device memory): counts -> scan ->
-// compaction.  Every temporary word is written before it is read.
+// compaction.  Every temporary word is written before it is read.  With
+// zero_counts (the uniform-cofactor passes, which write the counts of live
+// tiles only) a fill kernel clears the tile counts first, in one coalesced
+// sweep instead of a scattered write per dead tile.
 template <typename Pass>
 hipError_t enumerate_passes(fbg::EvalArgs a, char *tmp, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total,
-                            hipStream_t s, Pass pass) {
+                            hipStream_t s, bool zero_counts, Pass pass) {
   const uint64_t nt = a.ntiles;
   size_t bytes_cnt, bytes_off;
   enum_temp_bytes(nt, &bytes_cnt, &bytes_off);
@@ -401,7 +404,8 @@ hipError_t enumerate_passes(fbg::EvalArgs a, char *tmp, uint64_t *d_idx, uint64_
   uint64_t *off = (uint64_t *)(tmp + bytes_cnt);
   uint64_t *blk = (uint64_t *)(tmp + bytes_cnt + bytes_off);
   a.tile_counts = cnt;
-  hipError_t e = pass(fbg::EVAL_TILECNT, a);
+  hipError_t e = zero_counts ? fbg::launch_zero((uint64_t *)cnt, bytes_cnt / 8, nullptr, 0, s) : hipSuccess;
+  if (e == hipSuccess) e = pass(fbg::EVAL_TILECNT, a);
   if (e == hipSuccess) e = fbg::launch_scan(cnt, nt, off, blk, d_total, s);
   if (e == hipSuccess && capacity > 0) {
     a.tile_offsets = off;
@@ -415,13 +419,13 @@ hipError_t enumerate_passes(fbg::EvalArgs a, char *tmp, uint64_t *d_idx, uint64_
 // The same with the temporaries allocated on the stream and freed after.
 template <typename Pass>
 fbg_status enumerate_with(fbg::EvalArgs a, uint64_t *d_idx, uint64_t capacity, uint64_t *d_total, hipStream_t s,
-                          Pass pass) {
+                          bool zero_counts, Pass pass) {
   size_t bytes_cnt, bytes_off;
   const size_t bytes = enum_temp_bytes(a.ntiles, &bytes_cnt, &bytes_off);
   char *tmp = nullptr;
   hipError_t e = hipMallocAsync((void **)&tmp, bytes, s);
   if (e != hipSuccess) return fail(FBG_E_NOMEM, "hipMallocAsync of %zu bytes: %s", bytes, hipGetErrorString(e));
-  e = enumerate_passes(a, tmp, d_idx, capacity, d_total, s, pass);
+  e = enumerate_passes(a, tmp, d_idx, capacity, d_total, s, zero_counts, pass);
   hipError_t e2 = hipFreeAsync(tmp, s);
   if (e != hipSuccess) return hip_fail(e, "launch of an enumeration kernel");
   if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
@@ -692,7 +696,7 @@ fbg_status fbg_enumerate(const fbg_program *p, uint64_t *d_idx, uint64_t capacit
   if ((st = geometry(p, nullptr, fbg::EVAL_TILECNT, g))) return st;
   hipStream_t s = (hipStream_t)stream;
   const int var = p->variant(nullptr);
-  return enumerate_with(base_args(p, g.log2w), d_idx, capacity, d_total, s,
+  return enumerate_with(base_args(p, g.log2w), d_idx, capacity, d_total, s, (var & 2) != 0,
                         [&](int mode, const fbg::EvalArgs &a) {
                           return fbg::launch_eval(mode, g.log2w, var, a, g.grid, g.block, g.lds, s);
                         });
@@ -721,7 +725,8 @@ fbg_status fbg_enumerate_noalloc(const fbg_program *p, uint64_t *d_idx, uint64_t
   if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
   hipStream_t s = (hipStream_t)stream;
   const int var = p->variant(nullptr);
-  e = enumerate_passes(a, (char *)scratch, d_idx, capacity, d_total, s, [&](int mode, const fbg::EvalArgs &aa) {
+  e = enumerate_passes(a, (char *)scratch, d_idx, capacity, d_total, s, (var & 2) != 0,
+                       [&](int mode, const fbg::EvalArgs &aa) {
     return fbg::launch_eval(mode, g.log2w, var, aa, g.grid, g.block, g.lds, s);
   });
   return e == hipSuccess ? FBG_OK : hip_fail(e, "launch of an enumeration kernel");
@@ -745,7 +750,7 @@ fbg_status fbg_enumerate_dnf(const uint64_t *d_dnf, int32_t n_vars, uint64_t *d_
   const uint64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)cu_count(dev) * 8));
   hipStream_t s = (hipStream_t)stream;
-  return enumerate_with(a, d_idx, capacity, d_total, s, [&](int mode, const fbg::EvalArgs &aa) {
+  return enumerate_with(a, d_idx, capacity, d_total, s, false, [&](int mode, const fbg::EvalArgs &aa) {
     return fbg::launch_dnf_scan(mode, aa, grid, 64 * kWavesPerBlock, s);
   });
 }

@@ -682,9 +682,10 @@ __global__ __launch_bounds__(256, min_waves(LOG2W, VAR)) void k_eval(EvalArgs a)
   uint64_t total = 0;
   GenState<W> st;
   if (VAR & 1) st.clear();
-  // dead tiles (uniform cofactor) still write their zeros in DNF and
-  // tile-count modes; counting and compaction skip them
-  constexpr bool ALL = MODE == MODE_DNF || MODE == MODE_TILECNT;
+  // dead tiles (uniform cofactor) still write their zeros in DNF mode;
+  // counting and compaction skip them, and so does the tile-count pass,
+  // whose counts the host clears beforehand
+  constexpr bool ALL = MODE == MODE_DNF;
   for_tiles<LOG2W, (VAR & 2) != 0, ALL, true>(a.code, wave, nwaves, a.ntiles, lane, [&](uint64_t t, bool alive) {
     const uint64_t U0 = t << LOG2W;
     if (MODE == MODE_ENUM) {
