@@ -1377,9 +1377,9 @@ uint32_t encode_program(const Compiled &c, int log2w, std::vector<uint32_t> &wor
     }
     (b.group == kMulti ? multi : stat).push_back(b);
   }
-  // clauses made only of tile literals first (the uniform-cofactor kernel
-  // drops a tile as soon as one of them is false on it), then by group and
-  // in-word part so that equal keys share a chunk
+  // clauses made only of tile literals first (their keys stay apart from the
+  // others'; the uniform-cofactor table at the end of the block lists them
+  // again), then by group and in-word part so that equal keys share a chunk
   std::stable_sort(stat.begin(), stat.end(), [](const BlockClause &a, const BlockClause &b) {
     if (a.tile_only != b.tile_only) return a.tile_only;
     if (a.group != b.group) return a.group < b.group;
